@@ -1,0 +1,176 @@
+"""Neural Transformation Cache oracle, float64 numpy (test infrastructure only).
+
+Follows Sec. 4.1 and Eq. 5: (dmu, dq) = MLP(h(mu)), where h(x) is the
+multi-resolution hash encoding h(x) = [h(x;0), ..., h(x;L-1)] and h(x;l) is
+the trilinear interpolation of the d-dimensional feature vectors stored at
+the eight corners of the level-l voxel around x.  The MLP has two hidden
+ReLU layers of 64 units and a linear 7-output layer (3 translation + 4
+quaternion, Sec. 4.1 and Suppl. Sec. A).
+
+Readings where the paper is silent (listed with the rest of the design
+readings): the input is normalised by the scene AABB, x_n = (mu - aabb_min) *
+inv_extent, and points with any x_n outside [0, 1] are discarded (identity
+transform dmu = 0, dq = (1, 0, 0, 0), no gradient; Suppl. Sec. A);
+level l has an integer resolution N_l (grid of (N_l + 1)^3 vertices); a
+level is stored densely when (N_l + 1)^3 <= T (index x + (N+1)(y + (N+1)z))
+and otherwise through the spatial hash (x * 1) ^ (y * 2654435761) ^
+(z * 805459861) mod T of the instant-NGP encoding the paper follows; the
+cell index is floor(x_n N_l) clamped to N_l - 1; the MLP has no biases.
+
+The cell index is an integer decision, so it is taken in single precision
+exactly as the GPU takes it (x_n and x_n * N_l rounded to float32); the
+trilinear weights and everything after are float64.
+
+Mixed-precision emulation (`precision` = "f16" / "bf16"): table entries,
+weights and forward activations (encoding, h1, h2) are rounded to the
+storage type; backward activation gradients are rounded to the storage
+type's significand width (11 or 8 bits) with an unbounded exponent, which is
+what a power-of-two-scaled half-precision operand holds.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+try:  # bfloat16 rounding uses plain PyTorch CPU ops
+    import torch
+except Exception:  # pragma: no cover
+    torch = None
+
+PRIME_Y = np.uint64(2654435761)
+PRIME_Z = np.uint64(805459861)
+
+
+class NTCSpec:
+    """Shape of an NTC: levels, features, table size, resolutions, AABB."""
+
+    def __init__(self, cfg):
+        self.L = cfg.levels
+        self.F = cfg.feats
+        self.T = 1 << cfg.log2_T
+        self.res = list(cfg.resolutions())
+        self.hidden = cfg.hidden
+        self.out_dim = cfg.out_dim
+        self.sizes = [min((r + 1) ** 3, self.T) for r in self.res]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        self.aabb_min = np.asarray(cfg.aabb_min, np.float32)
+        self.inv_ext = cfg.inv_extent()
+        self.n_table = int(self.offsets[-1]) * self.F
+        self.in_dim = self.L * self.F
+
+    def split(self, params: np.ndarray):
+        """Flat [table | W1 | W2 | W3] -> (table (entries, F), W1, W2, W3)."""
+        p = np.asarray(params, np.float64)
+        h, i, o = self.hidden, self.in_dim, self.out_dim
+        k = self.n_table
+        table = p[:k].reshape(-1, self.F)
+        W1 = p[k:k + h * i].reshape(h, i)
+        k += h * i
+        W2 = p[k:k + h * h].reshape(h, h)
+        k += h * h
+        W3 = p[k:k + o * h].reshape(o, h)
+        return table, W1, W2, W3
+
+
+def round_storage(x, precision: str):
+    if precision == "f32":
+        return np.asarray(x, np.float64)
+    if precision == "f16":
+        return np.asarray(x, np.float64).astype(np.float16).astype(np.float64)
+    if precision == "bf16":
+        t = torch.from_numpy(np.asarray(x, np.float64).astype(np.float32))
+        return t.to(torch.bfloat16).to(torch.float64).numpy()
+    raise ValueError(precision)
+
+
+def round_significand(x, precision: str):
+    bits = {"f32": None, "f16": 11, "bf16": 8}[precision]
+    x = np.asarray(x, np.float64)
+    if bits is None:
+        return x
+    m, e = np.frexp(x)          # x = m 2^e, 0.5 <= |m| < 1
+    return np.ldexp(np.round(m * 2.0 ** bits) / 2.0 ** bits, e)
+
+
+def corners(spec: NTCSpec, means: np.ndarray):
+    """Per level: corner table rows (n, 8) and trilinear weights (n, 8)."""
+    means = np.asarray(means, np.float32)
+    xn32 = (means - spec.aabb_min) * spec.inv_ext                      # float32, as the GPU
+    inside = np.all((xn32 >= 0) & (xn32 <= 1), axis=1)
+    xn64 = (means.astype(np.float64) - spec.aabb_min.astype(np.float64)) * spec.inv_ext.astype(np.float64)
+    rows, wts = [], []
+    for l, N in enumerate(spec.res):
+        p32 = xn32 * np.float32(N)
+        i0 = np.minimum(np.floor(p32).astype(np.int64), N - 1)
+        i0 = np.maximum(i0, 0)
+        w = xn64 * N - i0                                               # float64 fractions
+        dense = (N + 1) ** 3 <= spec.T
+        r = np.zeros((means.shape[0], 8), np.int64)
+        wt = np.ones((means.shape[0], 8))
+        for c in range(8):
+            b = [(c >> k) & 1 for k in range(3)]
+            v = i0 + np.asarray(b)[None, :]
+            if dense:
+                idx = v[:, 0] + (N + 1) * (v[:, 1] + (N + 1) * v[:, 2])
+            else:
+                vu = v.astype(np.uint64)
+                h = (vu[:, 0] * np.uint64(1)) ^ (vu[:, 1] * PRIME_Y) ^ (vu[:, 2] * PRIME_Z)
+                idx = (h & np.uint64(0xFFFFFFFF)).astype(np.int64) % spec.T
+            r[:, c] = spec.offsets[l] + idx
+            for k in range(3):
+                wt[:, c] *= w[:, k] if b[k] else (1.0 - w[:, k])
+        rows.append(r)
+        wts.append(wt)
+    return inside, rows, wts
+
+
+def encode(spec: NTCSpec, table: np.ndarray, means: np.ndarray, precision: str = "f32"):
+    inside, rows, wts = corners(spec, means)
+    tab = round_storage(table, precision)
+    n = means.shape[0]
+    enc = np.zeros((n, spec.in_dim))
+    for l in range(spec.L):
+        for c in range(8):
+            enc[:, spec.F * l:spec.F * (l + 1)] += wts[l][:, c:c + 1] * tab[rows[l][:, c]]
+    return enc, inside, rows, wts
+
+
+def forward(spec: NTCSpec, params: np.ndarray, means: np.ndarray, precision: str = "f32"):
+    """Returns dmu (n, 3), dq (n, 4) and a cache for backward()."""
+    table, W1, W2, W3 = spec.split(params)
+    rs = lambda a: round_storage(a, precision)
+    enc, inside, rows, wts = encode(spec, table, means, precision)
+    enc_s = rs(enc)
+    W1s, W2s, W3s = rs(W1), rs(W2), rs(W3)
+    h1 = rs(np.maximum(enc_s @ W1s.T, 0.0))
+    h2 = rs(np.maximum(h1 @ W2s.T, 0.0))
+    out = h2 @ W3s.T
+    dmu = out[:, 0:3].copy()
+    dq = out[:, 3:7].copy()
+    dmu[~inside] = 0.0
+    dq[~inside] = np.array([1.0, 0.0, 0.0, 0.0])
+    cache = dict(enc=enc_s, h1=h1, h2=h2, W=(W1s, W2s, W3s), inside=inside, rows=rows, wts=wts)
+    return dmu, dq, cache
+
+
+def backward(spec: NTCSpec, params: np.ndarray, cache: dict, d_dmu: np.ndarray, d_dq: np.ndarray,
+             precision: str = "f32") -> np.ndarray:
+    """Gradient of <d_dmu, dmu> + <d_dq, dq> w.r.t. the flat parameter vector."""
+    rg = lambda a: round_significand(a, precision)
+    W1s, W2s, W3s = cache["W"]
+    inside = cache["inside"]
+    dout = np.concatenate([np.asarray(d_dmu, np.float64), np.asarray(d_dq, np.float64)], axis=1)
+    dout[~inside] = 0.0
+    dout = rg(dout)
+    h1, h2, enc = cache["h1"], cache["h2"], cache["enc"]
+    dW3 = dout.T @ h2
+    dh2 = rg((dout @ W3s) * (h2 > 0))
+    dW2 = dh2.T @ h1
+    dh1 = rg((dh2 @ W2s) * (h1 > 0))
+    dW1 = dh1.T @ enc
+    denc = dh1 @ W1s
+    dtable = np.zeros((int(spec.offsets[-1]), spec.F))
+    for l in range(spec.L):
+        g = denc[:, spec.F * l:spec.F * (l + 1)]
+        for c in range(8):
+            np.add.at(dtable, cache["rows"][l][:, c], cache["wts"][l][:, c:c + 1] * g)
+    return np.concatenate([dtable.reshape(-1), dW1.reshape(-1), dW2.reshape(-1), dW3.reshape(-1)])

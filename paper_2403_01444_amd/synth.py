@@ -1,0 +1,277 @@
+"""Seeded synthetic inputs shaped like the paper's multi-view captures.
+
+This module only draws inputs: Gaussians, pinhole cameras, a motion field
+that moves the Gaussians to make the next frame's scene, NTC initial
+parameters and the integer table of hash-grid resolutions.  It holds none of
+the method's arithmetic (no projection, compositing, encoding or MLP), so
+both the HIP path and the CPU oracle take their inputs from here.
+
+Scene recipe (stands in for the N3DV / Meet Room captures of Sec. 5.1, which
+are not available): means U[-1,1]^3, log-scales N(-3, 0.3) per axis, unit
+quaternions normalize(N(0, I4)) stored (w, x, y, z), opacity logits N(0, 1),
+SH degree-0 term chosen so the DC colour is U[0,1]^3, higher bands
+N(0, 0.05^2).  Cameras: pinhole, square pixels, principal point at the image
+centre ((W-1)/2, (H-1)/2), looking at the origin from distance 3.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Value of the degree-0 real spherical harmonic, used only to make the drawn
+# DC colour uniform on [0, 1] (colour = sh0 * Y00 + 0.5).
+_Y00 = 1.0 / (2.0 * math.sqrt(math.pi))
+
+
+@dataclass
+class Gaussians:
+    means: np.ndarray           # (n, 3) float32
+    quats: np.ndarray           # (n, 4) float32, (w, x, y, z)
+    log_scales: np.ndarray      # (n, 3) float32
+    opacity_logits: np.ndarray  # (n,)   float32
+    sh: np.ndarray              # (n, (deg+1)^2, 3) float32
+    sh_degree: int
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    def subset(self, idx) -> "Gaussians":
+        return Gaussians(self.means[idx].copy(), self.quats[idx].copy(),
+                         self.log_scales[idx].copy(),
+                         self.opacity_logits[idx].copy(), self.sh[idx].copy(),
+                         self.sh_degree)
+
+
+@dataclass
+class Camera:
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    near: float
+    world_to_cam: np.ndarray    # (3, 4) float32, rows = camera x (right), y (down), z (forward)
+    cam_pos: np.ndarray         # (3,) float32
+    bg: np.ndarray = field(default_factory=lambda: np.zeros(3, np.float32))
+
+
+def make_gaussians(n: int, sh_degree: int, seed: int) -> Gaussians:
+    rng = np.random.default_rng(seed)
+    means = rng.uniform(-1.0, 1.0, size=(n, 3))
+    log_scales = rng.normal(-3.0, 0.3, size=(n, 3))
+    q = rng.normal(0.0, 1.0, size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    logits = rng.normal(0.0, 1.0, size=(n,))
+    k = (sh_degree + 1) ** 2
+    sh = np.zeros((n, k, 3))
+    sh[:, 0, :] = (rng.uniform(0.0, 1.0, size=(n, 3)) - 0.5) / _Y00
+    if k > 1:
+        sh[:, 1:, :] = rng.normal(0.0, 0.05, size=(n, k - 1, 3))
+    f = np.float32
+    return Gaussians(means.astype(f), q.astype(f), log_scales.astype(f),
+                     logits.astype(f), sh.astype(f), sh_degree)
+
+
+def look_at_camera(width: int, height: int, fov_x_deg: float = 60.0,
+                   azimuth_deg: float = 0.0, elevation_deg: float = 0.0,
+                   distance: float = 3.0, near: float = 0.2,
+                   bg=(0.0, 0.0, 0.0)) -> Camera:
+    """Pinhole camera at `distance` from the origin looking at it.
+
+    Azimuth turns about the world +y axis; azimuth 0 sits on the -z axis.
+    fx = fy = (W/2) / tan(fov_x/2); principal point ((W-1)/2, (H-1)/2).
+    """
+    th = math.radians(azimuth_deg)
+    ph = math.radians(elevation_deg)
+    eye = distance * np.array([math.sin(th) * math.cos(ph), math.sin(ph),
+                               -math.cos(th) * math.cos(ph)])
+    zc = -eye / np.linalg.norm(eye)
+    up = np.array([0.0, 1.0, 0.0])
+    xc = np.cross(zc, up)
+    xc /= np.linalg.norm(xc)
+    yc = np.cross(zc, xc)
+    rot = np.stack([xc, yc, zc])
+    t = -rot @ eye
+    w2c = np.concatenate([rot, t[:, None]], axis=1)
+    fx = (width / 2.0) / math.tan(math.radians(fov_x_deg) / 2.0)
+    return Camera(width, height, float(np.float32(fx)), float(np.float32(fx)),
+                  (width - 1) / 2.0, (height - 1) / 2.0, near,
+                  w2c.astype(np.float32), eye.astype(np.float32),
+                  np.asarray(bg, np.float32))
+
+
+def ring_cameras(count: int, width: int, height: int, **kw) -> list[Camera]:
+    """`count` cameras on a horizontal ring (azimuth 0, 360/count, ...)."""
+    return [look_at_camera(width, height, azimuth_deg=360.0 * i / count, **kw)
+            for i in range(count)]
+
+
+def arc_cameras(count: int, width: int, height: int, half_angle: float = 30.0,
+                **kw) -> list[Camera]:
+    """`count` forward-facing cameras, azimuth evenly spaced in [-a, +a]."""
+    if count == 1:
+        return [look_at_camera(width, height, **kw)]
+    return [look_at_camera(width, height,
+                           azimuth_deg=-half_angle + 2 * half_angle * i / (count - 1),
+                           **kw) for i in range(count)]
+
+
+# --- motion fields: draw the next frame's scene -----------------------------
+
+def _hamilton(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    aw, ax, ay, az = a[..., 0], a[..., 1], a[..., 2], a[..., 3]
+    bw, bx, by, bz = b[..., 0], b[..., 1], b[..., 2], b[..., 3]
+    return np.stack([aw * bw - ax * bx - ay * by - az * bz,
+                     aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx,
+                     aw * bz + ax * by - ay * bx + az * bw], axis=-1)
+
+
+def smooth_displacement(g: Gaussians, seed: int, max_disp: float = 0.05) -> Gaussians:
+    """Means shifted by a seeded smooth field with |d| <= max_disp."""
+    rng = np.random.default_rng(seed)
+    x = g.means.astype(np.float64)
+    d = np.zeros_like(x)
+    amp = max_disp / math.sqrt(3.0)
+    for c in range(3):
+        k = rng.normal(size=3)
+        k /= np.linalg.norm(k)
+        phase = rng.uniform(0, 2 * math.pi)
+        d[:, c] = amp * np.sin(math.pi * (x @ k) + phase)
+    out = g.subset(slice(None))
+    out.means = (x + d).astype(np.float32)
+    return out
+
+
+def rigid_sinusoid_motion(g: Gaussians, seed: int, angle_deg: float = 1.0,
+                          translation: float = 0.01, wave: float = 0.01) -> Gaussians:
+    """Rigid rotation about a random axis + translation + sinusoid.
+
+    The rotation also turns every Gaussian: q_next = q_rot (x) q.
+    """
+    rng = np.random.default_rng(seed)
+    axis = rng.normal(size=3)
+    axis /= np.linalg.norm(axis)
+    half = math.radians(angle_deg) / 2.0
+    q_rot = np.concatenate([[math.cos(half)], math.sin(half) * axis])
+    w, (ax, ay, az) = q_rot[0], q_rot[1:]
+    rot = np.array([[1 - 2 * (ay * ay + az * az), 2 * (ax * ay - w * az), 2 * (ax * az + w * ay)],
+                    [2 * (ax * ay + w * az), 1 - 2 * (ax * ax + az * az), 2 * (ay * az - w * ax)],
+                    [2 * (ax * az - w * ay), 2 * (ay * az + w * ax), 1 - 2 * (ax * ax + ay * ay)]])
+    tdir = rng.normal(size=3)
+    tdir /= np.linalg.norm(tdir)
+    k = rng.normal(size=3)
+    k /= np.linalg.norm(k)
+    phase = rng.uniform(0, 2 * math.pi, size=3)
+    x = g.means.astype(np.float64)
+    s = np.sin(2 * math.pi * (x @ k)[:, None] + phase[None, :]) * (wave / math.sqrt(3.0))
+    moved = x @ rot.T + translation * tdir + s
+    out = g.subset(slice(None))
+    out.means = moved.astype(np.float32)
+    qn = _hamilton(np.broadcast_to(q_rot, g.quats.shape), g.quats.astype(np.float64))
+    out.quats = qn.astype(np.float32)
+    return out
+
+
+# --- NTC configuration and initial parameters --------------------------------
+
+@dataclass
+class NTCConfig:
+    levels: int = 16
+    feats: int = 2
+    log2_T: int = 15
+    base_res: int = 16
+    max_res: int = 1024
+    hidden: int = 64
+    out_dim: int = 7
+    aabb_min: tuple = (-1.2, -1.2, -1.2)
+    aabb_max: tuple = (1.2, 1.2, 1.2)
+
+    def resolutions(self) -> list[int]:
+        """Integer grid resolution per level: floor(base * b^l), b^(L-1) = max/base.
+
+        Evaluated in float64 with a 1e-9 guard so that exact powers (64, 256,
+        1024 for base 16 and max 1024) do not round down.
+        """
+        if self.levels == 1:
+            return [self.base_res]
+        b = math.exp(math.log(self.max_res / self.base_res) / (self.levels - 1))
+        return [int(math.floor(self.base_res * b ** l + 1e-9)) for l in range(self.levels)]
+
+    def level_sizes(self) -> list[int]:
+        T = 1 << self.log2_T
+        return [min((r + 1) ** 3, T) for r in self.resolutions()]
+
+    def num_table_params(self) -> int:
+        return sum(self.level_sizes()) * self.feats
+
+    def num_mlp_params(self) -> int:
+        h, i = self.hidden, self.levels * self.feats
+        return h * i + h * h + self.out_dim * h
+
+    def num_params(self) -> int:
+        return self.num_table_params() + self.num_mlp_params()
+
+    def inv_extent(self) -> np.ndarray:
+        ext = np.asarray(self.aabb_max, np.float64) - np.asarray(self.aabb_min, np.float64)
+        return (1.0 / ext).astype(np.float32)
+
+
+def ntc_init_params(cfg: NTCConfig, seed: int) -> np.ndarray:
+    """Flat float32 vector [table | W1 | W2 | W3].
+
+    Table U(-1e-4, 1e-4); each weight matrix (row-major [out][in])
+    Kaiming-uniform U(-sqrt(6/fan_in), +sqrt(6/fan_in)).
+    """
+    rng = np.random.default_rng(seed)
+    table = rng.uniform(-1e-4, 1e-4, size=cfg.num_table_params())
+    h, i, o = cfg.hidden, cfg.levels * cfg.feats, cfg.out_dim
+    ws = []
+    for (fo, fi) in ((h, i), (h, h), (o, h)):
+        bound = math.sqrt(6.0 / fi)
+        ws.append(rng.uniform(-bound, bound, size=fo * fi))
+    return np.concatenate([table] + ws).astype(np.float32)
+
+
+def warmup_points(means: np.ndarray, cfg: NTCConfig, seed: int, rel_sigma: float = 0.01) -> np.ndarray:
+    """Noise-augmented means for the NTC warm-up: mu + N(0, (rel_sigma * extent)^2)."""
+    rng = np.random.default_rng(seed)
+    ext = np.asarray(cfg.aabb_max) - np.asarray(cfg.aabb_min)
+    return (means + rng.normal(size=means.shape) * (rel_sigma * ext)).astype(np.float32)
+
+
+# --- the benchmark workloads --------------------------------------------------
+
+def workload(name: str, seed: int = 0):
+    """Scene, cameras and motion for one named workload.
+
+    small-2k-64px   : 2,000 Gaussians, SH0, one 64x64 camera.
+    ring-50k-256px  : 50K Gaussians, SH1, four 256x256 cameras on a ring.
+    arc-300k-1352px : 300K Gaussians, SH3, 20 training cameras at 1352x1014 on a
+                      forward arc (azimuth in [-30, 30] deg) + one held-out
+                      camera at azimuth 1.5 deg.
+    grad-200-32px   : 200 Gaussians, SH3, one 32x32 camera.
+    """
+    if name == "small-2k-64px":
+        g = make_gaussians(2000, 0, seed)
+        cams = [look_at_camera(64, 64)]
+        nxt = smooth_displacement(g, seed + 1000)
+        return g, cams, [], nxt
+    if name == "ring-50k-256px":
+        g = make_gaussians(50_000, 1, seed)
+        cams = ring_cameras(4, 256, 256)
+        nxt = rigid_sinusoid_motion(g, seed + 1000)
+        return g, cams, [look_at_camera(256, 256, azimuth_deg=45.0)], nxt
+    if name == "arc-300k-1352px":
+        g = make_gaussians(300_000, 3, seed)
+        cams = arc_cameras(20, 1352, 1014)
+        nxt = rigid_sinusoid_motion(g, seed + 1000)
+        return g, cams, [look_at_camera(1352, 1014, azimuth_deg=1.5)], nxt
+    if name == "grad-200-32px":
+        g = make_gaussians(200, 3, seed)
+        return g, [look_at_camera(32, 32)], [], smooth_displacement(g, seed + 1000)
+    raise KeyError(name)
