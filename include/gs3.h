@@ -1,0 +1,254 @@
+/*
+ * gs3 — 3DGStream Stage-1 hot path on MI355X (gfx950): C ABI.
+ *
+ * One Stage-1 iteration of 3DGStream (arXiv 2403.01444, Sec. 4.1): query the
+ * Neural Transformation Cache (NTC) at every Gaussian mean (Eq. 5),
+ * transform the Gaussians (mu' = mu + dmu, q' = norm(q) x norm(dq), SH
+ * rotation), render a view with a tile-based differentiable rasterizer
+ * (Sec. 3.2, Eq. 2-4), evaluate the loss of Eq. 6, backpropagate, and step
+ * Adam on the NTC parameters.
+ *
+ * Conventions for every call:
+ *  - Array arguments are caller-owned DEVICE memory (contiguous float32,
+ *    structure of arrays) unless a comment says "host".  The library never
+ *    frees them and never keeps them beyond what a comment states.
+ *  - Calls are asynchronous on the context's stream (gs3_set_stream) unless
+ *    a comment says they synchronise.  Kernel-side conditions (pair-list
+ *    overflow, non-finite loss) raise device flags, reported by
+ *    gs3_debug_counts / gs3_check_flags as GS3_ECAPACITY / GS3_ENONFINITE.
+ *  - Every call returns a gs3_status and never aborts the process; the text
+ *    of the last error of a context is returned by gs3_last_error.
+ *  - Gradient outputs ACCUMULATE (+=); the caller zeroes them.  Any gradient
+ *    pointer may be NULL to skip that output.
+ *  - Quaternions are (w, x, y, z); the identity is (1, 0, 0, 0) (Sec. 4.2).
+ *  - Images are planar 3 x H x W float32 (channel, row, column).
+ */
+#ifndef GS3_H
+#define GS3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GS3_OK = 0,
+    GS3_EINVAL = -1,      /* bad argument (NULL, size out of range, bad slot) */
+    GS3_ENOMEM = -2,      /* device allocation failed */
+    GS3_EHIP = -3,        /* a HIP runtime call failed */
+    GS3_ECAPACITY = -4,   /* more (Gaussian, tile) pairs than max_pairs */
+    GS3_ENONFINITE = -5,  /* the loss was NaN or infinite */
+    GS3_ESTATE = -6       /* call out of order (e.g. backward before render) */
+} gs3_status;
+
+enum { GS3_F32 = 0, GS3_F16 = 1, GS3_BF16 = 2 };            /* NTC storage precision */
+enum { GS3_SORT_DEPTH_FIRST = 0, GS3_SORT_RADIX64 = 1 };    /* pair-ordering method */
+
+#define GS3_MAX_LEVELS 16
+#define GS3_TILE 16          /* tiles are 16 x 16 pixels */
+#define GS3_MAX_TILES 16384  /* ceil(W/16) * ceil(H/16) must not exceed this */
+
+/* NTC shape (Sec. 4.1, Suppl. Sec. A): L levels of a multi-resolution hash
+ * grid with F = 2 features per entry and 2^log2_T entries per hashed level,
+ * then an MLP (L*F) -> 64 -> 64 -> 7 with ReLU hidden layers, no biases. */
+typedef struct {
+    int32_t levels;                  /* L, 1..16; L*F must be 32 */
+    int32_t feats;                   /* F, must be 2 */
+    int32_t log2_T;                  /* 10..22 */
+    int32_t hidden;                  /* must be 64 */
+    int32_t precision;               /* GS3_F32 | GS3_F16 | GS3_BF16 */
+    int32_t res[GS3_MAX_LEVELS];     /* grid resolution N_l per level, 1..65535 */
+    float aabb_min[3];               /* scene AABB corner */
+    float inv_extent[3];             /* 1 / (aabb_max - aabb_min), per axis */
+} gs3_ntc_config;
+
+typedef struct {
+    int64_t max_gaussians;           /* capacity in Gaussians, >= 1 */
+    int64_t max_pairs;               /* capacity in (Gaussian, tile) pairs per slot */
+    int32_t max_width, max_height;   /* largest image */
+    int32_t num_slots;               /* renders whose state is kept for backward, 1..8 */
+    int32_t sort_mode;               /* GS3_SORT_DEPTH_FIRST (default) | GS3_SORT_RADIX64 */
+    int32_t enable_ntc;              /* 0: rasterizer only */
+    int32_t reserved;
+    gs3_ntc_config ntc;
+} gs3_config;
+
+/* Frozen Gaussians (Sec. 3.1): n means (n x 3), quaternions (n x 4),
+ * log-scales (n x 3), opacity logits (n), SH coefficients
+ * (n x (sh_degree+1)^2 x 3, coefficient-major, channel-minor), sh_degree 0..3.
+ * Real orthonormal SH basis with the Condon-Shortley phase; colour =
+ * max(0, sum_k sh_k Y_k(d) + 0.5). */
+typedef struct {
+    int64_t n;
+    int32_t sh_degree;
+    int32_t reserved;
+    const float* means;
+    const float* quats;
+    const float* log_scales;
+    const float* opacity_logits;
+    const float* sh;
+} gs3_gaussians;
+
+/* Pinhole camera: pixel (x, y) is evaluated at integer coordinates; a
+ * camera-space point t maps to (fx t_x / t_z + cx, fy t_y / t_z + cy).
+ * world_to_cam is the row-major 3 x 4 [R | t]; cam_pos its centre;
+ * near_z the cull plane (t_z <= near_z is culled); bg the background. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy, near_z;
+    float world_to_cam[12];
+    float cam_pos[3];
+    float bg[3];
+} gs3_camera;
+
+/* Gradient outputs of gs3_render_backward (all accumulate, any may be NULL).
+ * Stage 1 trains only the NTC, so only d_dmu and d_dq are needed there;
+ * the others give the full adjoint.  d_uv, d_conic, d_opacity, d_rgb are the
+ * per-Gaussian 2D accumulators (image-space mean, conic (A, B, C) with
+ * power = -(A dx^2 + C dy^2)/2 - B dx dy, activated opacity, colour). */
+typedef struct {
+    float* d_means;          /* n x 3 */
+    float* d_quats;          /* n x 4 */
+    float* d_log_scales;     /* n x 3 */
+    float* d_opacity_logits; /* n */
+    float* d_sh;             /* n x (deg+1)^2 x 3 */
+    float* d_dmu;            /* n x 3 */
+    float* d_dq;             /* n x 4 */
+    float* d_uv;             /* n x 2 */
+    float* d_conic;          /* n x 3 */
+    float* d_opacity;        /* n */
+    float* d_rgb;            /* n x 3 */
+} gs3_grads;
+
+typedef struct gs3_ctx gs3_ctx;
+
+/* Create a context on the current HIP device: allocates every workspace
+ * (pair lists sized by max_pairs, per-slot render state, NTC parameters and
+ * Adam state).  Synchronises.  Returns GS3_EINVAL for out-of-range fields,
+ * GS3_ENOMEM when an allocation fails. */
+gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out);
+
+/* Free a context and everything it allocated.  Synchronises.  NULL is a no-op. */
+void gs3_destroy(gs3_ctx* ctx);
+
+/* Text of the last error on this context (static storage owned by ctx). */
+const char* gs3_last_error(const gs3_ctx* ctx);
+
+/* Launch all further work of this context on `hip_stream` (a hipStream_t;
+ * NULL = the default stream). */
+gs3_status gs3_set_stream(gs3_ctx* ctx, void* hip_stream);
+
+/* ---- Neural Transformation Cache (Sec. 4.1, Eq. 5) ----------------------- */
+
+/* Number of float32 NTC parameters: table (sum_l min((N_l+1)^3, T) x F)
+ * followed by W1 (64 x L*F), W2 (64 x 64), W3 (7 x 64), row-major [out][in]. */
+gs3_status gs3_ntc_num_params(const gs3_ctx* ctx, int64_t* n);
+
+/* Load the float32 master parameters from HOST memory (layout above), reset
+ * the Adam moments, the step counter and the accumulated gradients.
+ * Synchronises. */
+gs3_status gs3_ntc_load(gs3_ctx* ctx, const float* host_params, int64_t n);
+
+/* Copy the float32 master parameters to HOST memory (cap >= num_params).
+ * Synchronises. */
+gs3_status gs3_ntc_save(gs3_ctx* ctx, float* host_params, int64_t cap);
+
+/* (dmu, dq) = MLP(h(mu)) for n means (n x 3) -> dmu (n x 3), dq (n x 4).
+ * Means outside the AABB get the identity (0, (1,0,0,0)) (Suppl. Sec. A). */
+gs3_status gs3_ntc_forward(gs3_ctx* ctx, const float* means, int64_t n, float* dmu, float* dq);
+
+/* Accumulate into the context's float32 gradient buffers the gradient of
+ * <d_dmu, dmu> + <d_dq, dq> for the same means (adjoint of Eq. 5: MLP
+ * backward, then the hash-table scatter-add). */
+gs3_status gs3_ntc_backward(gs3_ctx* ctx, const float* means, int64_t n,
+                            const float* d_dmu, const float* d_dq);
+
+/* One Adam step on the NTC parameters with the accumulated gradients,
+ * then zero the gradients and refresh the FP16/BF16 working copy. */
+gs3_status gs3_ntc_step(gs3_ctx* ctx, float lr, float beta1, float beta2, float eps);
+
+/* Copy the accumulated float32 gradients (num_params) to DEVICE memory. */
+gs3_status gs3_ntc_grads(gs3_ctx* ctx, float* dev_out, int64_t cap);
+
+/* Zero the accumulated gradients. */
+gs3_status gs3_ntc_zero_grads(gs3_ctx* ctx);
+
+/* Warm-up loss (Eq. 7) averaged over n points: mean ||dmu||_1 -
+ * mean (dq_w / ||dq||)^2.  Writes the loss to loss_dev[0] (device float)
+ * and OVERWRITES d_dmu (n x 3), d_dq (n x 4) with its gradient. */
+gs3_status gs3_warmup_loss(gs3_ctx* ctx, const float* dmu, const float* dq, int64_t n,
+                           float* loss_dev, float* d_dmu, float* d_dq);
+
+/* ---- Rasterizer (Sec. 3.2, Eq. 2-4) -------------------------------------- */
+
+/* Transform (mu' = mu + dmu, q' = norm(q) x norm(dq), SH evaluated at the
+ * direction rotated back by R(q') R(norm q)^T) and render one view into
+ * `image` (3 x H x W).  dmu (n x 3) and dq (n x 4) may be NULL (no
+ * translation / no rotation).  The slot keeps this render's state for
+ * gs3_render_backward, INCLUDING the pointers g->*, dmu and dq: they must
+ * stay valid and unchanged until the slot's backward has run. */
+gs3_status gs3_render(gs3_ctx* ctx, int32_t slot, const gs3_gaussians* g, const float* dmu,
+                      const float* dq, const gs3_camera* cam, float* image);
+
+/* Adjoint of the slot's last gs3_render for dL/dimage (3 x H x W); gradients
+ * accumulate into `out`.  Per-pixel transmittance is recomputed from the
+ * final transmittance, not stored. */
+gs3_status gs3_render_backward(gs3_ctx* ctx, int32_t slot, const float* d_image, const gs3_grads* out);
+
+/* ---- Loss (Eq. 6) and optimiser ------------------------------------------ */
+
+/* L = (1 - lambda) L1 + lambda (1 - SSIM) over 3 x H x W images (11x11
+ * Gaussian window, sigma 1.5, zero padding); lambda = 0 gives plain L1.
+ * Writes L to loss_dev[0] and OVERWRITES d_image with dL/dimage. */
+gs3_status gs3_loss(gs3_ctx* ctx, const float* image, const float* target, int32_t height,
+                    int32_t width, float lambda_dssim, float* loss_dev, float* d_image);
+
+/* In-place Adam on n float32 parameters (bias correction with `step` >= 1);
+ * used by the direct per-Gaussian optimisation comparator. */
+gs3_status gs3_adam(gs3_ctx* ctx, float* param, const float* grad, float* m, float* v, int64_t n,
+                    int32_t step, float lr, float beta1, float beta2, float eps);
+
+/* ---- Inspection (parity tests, benchmarks) ------------------------------- */
+
+/* Number of (Gaussian, tile) pairs of the slot's last render and its overflow
+ * flag; sums the contributors walked.  Synchronises.  Returns GS3_ECAPACITY
+ * when the pair list overflowed. */
+gs3_status gs3_debug_counts(gs3_ctx* ctx, int32_t slot, int64_t* num_pairs, int32_t* overflow);
+
+/* Sorted pairs of the slot's last render into DEVICE buffers: keys
+ * (tile << 32 | float bits of view-space z) and Gaussian indices; cap >=
+ * num_pairs. */
+gs3_status gs3_debug_pairs(gs3_ctx* ctx, int32_t slot, uint64_t* keys, uint32_t* vals, int64_t cap);
+
+/* Per-tile [start, end) into the sorted pairs, (tiles x 2) u32, DEVICE. */
+gs3_status gs3_debug_ranges(gs3_ctx* ctx, int32_t slot, uint32_t* ranges);
+
+/* Per-Gaussian decisions of the slot's last render into DEVICE buffers (any
+ * may be NULL): depth key bits (0xFFFFFFFF when culled), pixel box
+ * (n x 4 int32: x0, y0, x1, y1), 2D record (n x 9 float: u, v, A, B, C,
+ * opacity, r, g, b). */
+gs3_status gs3_debug_gaussians(gs3_ctx* ctx, int32_t slot, uint32_t* key, int32_t* box, float* rec);
+
+/* Per-pixel final transmittance (H x W float) and number of tile-list
+ * entries walked up to the last contributor (H x W int32), DEVICE. */
+gs3_status gs3_debug_pixels(gs3_ctx* ctx, int32_t slot, float* T_final, int32_t* last);
+
+/* Check the device flags raised since the last check (overflow of any slot,
+ * non-finite loss) and clear them.  Synchronises. */
+gs3_status gs3_check_flags(gs3_ctx* ctx);
+
+/* ---- Profiling ----------------------------------------------------------- */
+
+/* When on, every kernel launch is bracketed by HIP events on the context
+ * stream; gs3_profile_query returns the summed device time (ms) and launch
+ * count of one kernel by name, synchronising first. */
+gs3_status gs3_profile_enable(gs3_ctx* ctx, int32_t on);
+gs3_status gs3_profile_reset(gs3_ctx* ctx);
+gs3_status gs3_profile_query(gs3_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS3_H */

@@ -1,0 +1,593 @@
+// C ABI of libgs3.so (declared in include/gs3.h).
+#include <math.h>
+#include <string.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/gs3.h"
+#include "kernels.h"
+#include "ntc.h"
+
+using namespace gs3;
+
+namespace {
+
+struct EventProfiler : Profiler {
+    struct Rec {
+        std::string name;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<Rec> open;
+    std::map<std::string, std::pair<double, int64_t>> totals;
+    void begin(const char* name, hipStream_t st) override {
+        Rec r{name, nullptr, nullptr};
+        hipEventCreate(&r.a);
+        hipEventCreate(&r.b);
+        hipEventRecord(r.a, st);
+        open.push_back(r);
+    }
+    void end(hipStream_t st) override {
+        if (open.empty()) return;
+        Rec r = open.back();
+        open.pop_back();
+        hipEventRecord(r.b, st);
+        pending.push_back(r);
+    }
+    void collect() {
+        for (auto& r : pending) {
+            hipEventSynchronize(r.b);
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, r.a, r.b);
+            auto& t = totals[r.name];
+            t.first += ms;
+            t.second += 1;
+            hipEventDestroy(r.a);
+            hipEventDestroy(r.b);
+        }
+        pending.clear();
+    }
+    ~EventProfiler() override {
+        for (auto& r : pending) {
+            hipEventDestroy(r.a);
+            hipEventDestroy(r.b);
+        }
+    }
+};
+
+struct Slot {
+    float4* rec = nullptr;
+    uint32_t* key = nullptr;
+    uint2* rect = nullptr;
+    uint32_t* count = nullptr;
+    uint32_t* vals[2] = {nullptr, nullptr};
+    uint64_t* pkeys[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint2* ranges = nullptr;
+    float* T_final = nullptr;
+    uint32_t* last = nullptr;
+    uint64_t* total = nullptr;
+    bool valid = false;
+    GaussDev g{};
+    CamDev cam{};
+    int64_t K_host = -1;
+};
+
+}  // namespace
+
+struct gs3_ctx {
+    gs3_config cfg{};
+    hipStream_t st = nullptr;
+    std::string err;
+    std::vector<Slot> slots;
+    std::vector<void*> allocs;
+    int max_tiles = 0;
+    // depth sort and binning
+    uint32_t* dkeys[2] = {nullptr, nullptr};
+    uint32_t* dvals[2] = {nullptr, nullptr};
+    uint32_t* radix_hist = nullptr;
+    uint64_t* scan_tmp = nullptr;
+    uint32_t* bin_hist = nullptr;
+    uint64_t* bin_base = nullptr;
+    uint64_t* offs = nullptr;
+    float* accum = nullptr;
+    int* flags = nullptr;   // [0] pair overflow, [1] non-finite loss
+    float* loss_maps = nullptr;
+    double* loss_bsum = nullptr;
+    // NTC
+    NtcDev nd{};
+    int64_t n_table_floats = 0, n_params = 0;
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    void* work = nullptr;
+    int step = 0;
+    float* g_part = nullptr;
+    int max_parts = 0;
+    double* warm_bsum = nullptr;
+    EventProfiler prof;
+    bool prof_on = false;
+
+    Launch L() { return Launch{st, prof_on ? &prof : nullptr}; }
+
+    template <typename T>
+    bool alloc(T** out, int64_t count) {
+        *out = nullptr;
+        if (count <= 0) count = 1;
+        void* ptr = nullptr;
+        if (hipMalloc(&ptr, (size_t)count * sizeof(T)) != hipSuccess) {
+            err = "hipMalloc of " + std::to_string((long long)count * (long long)sizeof(T)) + " bytes failed";
+            return false;
+        }
+        allocs.push_back(ptr);
+        *out = (T*)ptr;
+        return true;
+    }
+    gs3_status fail(gs3_status s, const std::string& msg) {
+        err = msg;
+        return s;
+    }
+    gs3_status check_launch(const char* what) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(GS3_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+        return GS3_OK;
+    }
+};
+
+static const char* kNullCtx = "null context";
+
+static int tiles_of(int w, int h) { return ((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile); }
+
+extern "C" {
+
+gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
+    if (!cfg || !out) return GS3_EINVAL;
+    *out = nullptr;
+    if (cfg->max_gaussians < 1 || cfg->max_gaussians > (int64_t)1 << 31 || cfg->max_pairs < 1 ||
+        cfg->max_pairs >= (int64_t)1 << 31 || cfg->max_width < 1 || cfg->max_height < 1 ||
+        cfg->max_width > 32767 || cfg->max_height > 32767 || cfg->num_slots < 1 || cfg->num_slots > 8 ||
+        (cfg->sort_mode != GS3_SORT_DEPTH_FIRST && cfg->sort_mode != GS3_SORT_RADIX64))
+        return GS3_EINVAL;
+    if (tiles_of(cfg->max_width, cfg->max_height) > GS3_MAX_TILES) return GS3_EINVAL;
+    gs3_ctx* c = new gs3_ctx();
+    c->cfg = *cfg;
+    c->max_tiles = tiles_of(cfg->max_width, cfg->max_height);
+    const int64_t N = cfg->max_gaussians, PK = cfg->max_pairs, PX = (int64_t)cfg->max_width * cfg->max_height;
+    const int64_t nchunks = (N + kBinChunk - 1) / kBinChunk;
+    bool ok = true;
+    c->slots.resize(cfg->num_slots);
+    for (auto& s : c->slots) {
+        ok = ok && c->alloc(&s.rec, 3 * N) && c->alloc(&s.key, N) && c->alloc(&s.rect, N) && c->alloc(&s.count, N) &&
+             c->alloc(&s.vals[0], PK) && c->alloc(&s.ranges, c->max_tiles) && c->alloc(&s.T_final, PX) &&
+             c->alloc(&s.last, PX) && c->alloc(&s.total, 1);
+        if (ok && cfg->sort_mode == GS3_SORT_RADIX64)
+            ok = c->alloc(&s.vals[1], PK) && c->alloc(&s.pkeys[0], PK) && c->alloc(&s.pkeys[1], PK);
+    }
+    const int64_t sort_items = cfg->sort_mode == GS3_SORT_RADIX64 ? std::max(N, PK) : N;
+    const int64_t hist_words = radix_hist_words(sort_items);
+    const int64_t bin_words = (int64_t)c->max_tiles * nchunks;
+    const int64_t scan_items = std::max(std::max(hist_words, bin_words), N);
+    ok = ok && c->alloc(&c->dkeys[0], N) && c->alloc(&c->dkeys[1], N) && c->alloc(&c->dvals[0], N) &&
+         c->alloc(&c->dvals[1], N) && c->alloc(&c->radix_hist, hist_words) &&
+         c->alloc(&c->scan_tmp, scan_tmp_words(scan_items) + 4) && c->alloc(&c->accum, 9 * N) &&
+         c->alloc(&c->flags, 4) && c->alloc(&c->loss_maps, loss_map_floats(cfg->max_height, cfg->max_width)) &&
+         c->alloc(&c->loss_bsum, 2 * (int64_t)loss_blocks(cfg->max_height, cfg->max_width));
+    if (ok && cfg->sort_mode == GS3_SORT_DEPTH_FIRST)
+        ok = c->alloc(&c->bin_hist, bin_words) && c->alloc(&c->bin_base, bin_words);
+    if (ok && cfg->sort_mode == GS3_SORT_RADIX64) ok = c->alloc(&c->offs, N);
+    if (ok && cfg->enable_ntc) {
+        const gs3_ntc_config& nc = cfg->ntc;
+        if (nc.levels != 16 || nc.feats != 2 || nc.hidden != 64 || nc.log2_T < 10 || nc.log2_T > 22 ||
+            nc.precision < GS3_F32 || nc.precision > GS3_BF16) {
+            gs3_destroy(c);
+            return GS3_EINVAL;
+        }
+        const int64_t T = (int64_t)1 << nc.log2_T;
+        int64_t off = 0;
+        c->nd.dense_mask = 0;
+        for (int l = 0; l < 16; l++) {
+            if (nc.res[l] < 1 || nc.res[l] > 65535) {
+                gs3_destroy(c);
+                return GS3_EINVAL;
+            }
+            const int64_t r1 = (int64_t)nc.res[l] + 1;
+            const int64_t full = r1 * r1 * r1;
+            c->nd.res[l] = nc.res[l];
+            c->nd.off[l] = off;
+            if (full <= T) c->nd.dense_mask |= 1u << l;
+            off += full <= T ? full : T;
+        }
+        c->nd.T_mask = (uint32_t)(T - 1);
+        for (int k = 0; k < 3; k++) {
+            c->nd.aabb_min[k] = nc.aabb_min[k];
+            c->nd.inv_ext[k] = nc.inv_extent[k];
+        }
+        c->n_table_floats = off * 2;
+        c->n_params = c->n_table_floats + ntc_mlp_params();
+        c->max_parts = 2048;
+        ok = c->alloc(&c->p, c->n_params) && c->alloc(&c->g, c->n_params) && c->alloc(&c->m, c->n_params) &&
+             c->alloc(&c->v, c->n_params) && c->alloc((float**)&c->work, c->n_params) &&
+             c->alloc(&c->g_part, (int64_t)c->max_parts * ntc_mlp_params()) && c->alloc(&c->warm_bsum, (N + 255) / 256);
+    }
+    if (!ok) {
+        gs3_destroy(c);
+        return GS3_ENOMEM;
+    }
+    Launch L{nullptr, nullptr};
+    fill_u32(L, (uint32_t*)c->flags, 0u, 4);
+    if (c->n_params) {
+        fill_f32(L, c->p, 0.f, c->n_params);
+        fill_f32(L, c->g, 0.f, c->n_params);
+        fill_f32(L, c->m, 0.f, c->n_params);
+        fill_f32(L, c->v, 0.f, c->n_params);
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        gs3_destroy(c);
+        return GS3_EHIP;
+    }
+    *out = c;
+    return GS3_OK;
+}
+
+void gs3_destroy(gs3_ctx* ctx) {
+    if (!ctx) return;
+    hipDeviceSynchronize();
+    for (void* p : ctx->allocs) hipFree(p);
+    delete ctx;
+}
+
+const char* gs3_last_error(const gs3_ctx* ctx) { return ctx ? ctx->err.c_str() : kNullCtx; }
+
+gs3_status gs3_set_stream(gs3_ctx* ctx, void* hip_stream) {
+    if (!ctx) return GS3_EINVAL;
+    ctx->st = (hipStream_t)hip_stream;
+    return GS3_OK;
+}
+
+/* ---- NTC ---------------------------------------------------------------- */
+
+gs3_status gs3_ntc_num_params(const gs3_ctx* ctx, int64_t* n) {
+    if (!ctx || !n) return GS3_EINVAL;
+    *n = ctx->n_params;
+    return ctx->n_params ? GS3_OK : GS3_ESTATE;
+}
+
+gs3_status gs3_ntc_load(gs3_ctx* c, const float* host_params, int64_t n) {
+    if (!c || !host_params) return GS3_EINVAL;
+    if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
+    if (n != c->n_params) return c->fail(GS3_EINVAL, "ntc_load: wrong parameter count");
+    if (hipMemcpyAsync(c->p, host_params, (size_t)n * 4, hipMemcpyHostToDevice, c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "ntc_load: copy failed");
+    Launch L = c->L();
+    fill_f32(L, c->g, 0.f, n);
+    fill_f32(L, c->m, 0.f, n);
+    fill_f32(L, c->v, 0.f, n);
+    ntc_refresh_work(L, c->cfg.ntc.precision, c->p, c->work, n);
+    c->step = 0;
+    if (hipStreamSynchronize(c->st) != hipSuccess) return c->fail(GS3_EHIP, "ntc_load: sync failed");
+    return c->check_launch("ntc_load");
+}
+
+gs3_status gs3_ntc_save(gs3_ctx* c, float* host_params, int64_t cap) {
+    if (!c || !host_params) return GS3_EINVAL;
+    if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
+    if (cap < c->n_params) return c->fail(GS3_EINVAL, "ntc_save: buffer too small");
+    if (hipMemcpyAsync(host_params, c->p, (size_t)c->n_params * 4, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "ntc_save: copy failed");
+    return GS3_OK;
+}
+
+static void ntc_ptrs(gs3_ctx* c, const void** table, const void** mlp) {
+    if (c->cfg.ntc.precision == GS3_F32) {
+        *table = c->p;
+        *mlp = c->p + c->n_table_floats;
+    } else {
+        *table = c->work;
+        *mlp = (const char*)c->work + 2 * c->n_table_floats;
+    }
+}
+
+gs3_status gs3_ntc_forward(gs3_ctx* c, const float* means, int64_t n, float* dmu, float* dq) {
+    if (!c) return GS3_EINVAL;
+    if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
+    if (n < 0 || (n > 0 && (!means || !dmu || !dq))) return c->fail(GS3_EINVAL, "ntc_forward: bad arguments");
+    const void *table, *mlp;
+    ntc_ptrs(c, &table, &mlp);
+    ntc_forward(c->L(), c->cfg.ntc.precision, c->nd, table, mlp, means, n, dmu, dq);
+    return c->check_launch("ntc_forward");
+}
+
+gs3_status gs3_ntc_backward(gs3_ctx* c, const float* means, int64_t n, const float* d_dmu, const float* d_dq) {
+    if (!c) return GS3_EINVAL;
+    if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
+    if (n < 0 || (n > 0 && (!means || !d_dmu || !d_dq))) return c->fail(GS3_EINVAL, "ntc_backward: bad arguments");
+    const void *table, *mlp;
+    ntc_ptrs(c, &table, &mlp);
+    ntc_backward(c->L(), c->cfg.ntc.precision, c->nd, table, mlp, means, n, d_dmu, d_dq, c->g,
+                 c->g + c->n_table_floats, c->g_part, c->max_parts);
+    return c->check_launch("ntc_backward");
+}
+
+gs3_status gs3_ntc_step(gs3_ctx* c, float lr, float beta1, float beta2, float eps) {
+    if (!c) return GS3_EINVAL;
+    if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
+    c->step += 1;
+    const float bc1 = (float)(1.0 - pow((double)beta1, (double)c->step));
+    const float bc2 = (float)(1.0 - pow((double)beta2, (double)c->step));
+    ntc_adam(c->L(), c->cfg.ntc.precision, c->p, c->g, c->m, c->v, c->work, c->n_params, lr, beta1, beta2, eps, bc1,
+             bc2);
+    return c->check_launch("ntc_step");
+}
+
+gs3_status gs3_ntc_grads(gs3_ctx* c, float* dev_out, int64_t cap) {
+    if (!c || !dev_out) return GS3_EINVAL;
+    if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
+    if (cap < c->n_params) return c->fail(GS3_EINVAL, "ntc_grads: buffer too small");
+    if (hipMemcpyAsync(dev_out, c->g, (size_t)c->n_params * 4, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "ntc_grads: copy failed");
+    return GS3_OK;
+}
+
+gs3_status gs3_ntc_zero_grads(gs3_ctx* c) {
+    if (!c) return GS3_EINVAL;
+    if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
+    fill_f32(c->L(), c->g, 0.f, c->n_params);
+    return c->check_launch("ntc_zero_grads");
+}
+
+gs3_status gs3_warmup_loss(gs3_ctx* c, const float* dmu, const float* dq, int64_t n, float* loss_dev, float* d_dmu,
+                           float* d_dq) {
+    if (!c) return GS3_EINVAL;
+    if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
+    if (n < 1 || n > c->cfg.max_gaussians || !dmu || !dq || !loss_dev || !d_dmu || !d_dq)
+        return c->fail(GS3_EINVAL, "warmup_loss: bad arguments");
+    warmup_loss(c->L(), dmu, dq, n, loss_dev, d_dmu, d_dq, c->warm_bsum);
+    return c->check_launch("warmup_loss");
+}
+
+/* ---- render ------------------------------------------------------------- */
+
+static gs3_status make_cam(gs3_ctx* c, const gs3_camera* cam, CamDev* out) {
+    if (!cam) return c->fail(GS3_EINVAL, "null camera");
+    if (cam->width < 1 || cam->height < 1 || cam->width > c->cfg.max_width || cam->height > c->cfg.max_height)
+        return c->fail(GS3_EINVAL, "camera size outside the context's maximum");
+    if (!(cam->fx > 0.f) || !(cam->fy > 0.f) || !(cam->near_z > 0.f)) return c->fail(GS3_EINVAL, "bad intrinsics");
+    CamDev d;
+    d.W = cam->width;
+    d.H = cam->height;
+    d.tiles_x = (cam->width + kTile - 1) / kTile;
+    d.tiles_y = (cam->height + kTile - 1) / kTile;
+    d.fx = cam->fx; d.fy = cam->fy; d.cx = cam->cx; d.cy = cam->cy; d.near_z = cam->near_z;
+    for (int r = 0; r < 3; r++) {
+        for (int k = 0; k < 3; k++) d.R[3 * r + k] = cam->world_to_cam[4 * r + k];
+        d.t[r] = cam->world_to_cam[4 * r + 3];
+        d.cpos[r] = cam->cam_pos[r];
+        d.bg[r] = cam->bg[r];
+    }
+    *out = d;
+    return GS3_OK;
+}
+
+gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const float* dmu, const float* dq,
+                      const gs3_camera* cam, float* image) {
+    if (!c) return GS3_EINVAL;
+    if (slot < 0 || slot >= (int)c->slots.size()) return c->fail(GS3_EINVAL, "bad slot");
+    if (!g || !image) return c->fail(GS3_EINVAL, "null argument");
+    if (g->n < 0 || g->n > c->cfg.max_gaussians) return c->fail(GS3_EINVAL, "Gaussian count outside [0, max]");
+    if (g->sh_degree < 0 || g->sh_degree > 3) return c->fail(GS3_EINVAL, "sh_degree must be 0..3");
+    if (g->n > 0 && (!g->means || !g->quats || !g->log_scales || !g->opacity_logits || !g->sh))
+        return c->fail(GS3_EINVAL, "null Gaussian array");
+    CamDev cd;
+    gs3_status s = make_cam(c, cam, &cd);
+    if (s != GS3_OK) return s;
+    Slot& sl = c->slots[slot];
+    sl.valid = false;
+    GaussDev gd;
+    gd.means = g->means; gd.quats = g->quats; gd.log_scales = g->log_scales; gd.opac = g->opacity_logits;
+    gd.sh = g->sh; gd.dmu = dmu; gd.dq = dq; gd.n = g->n; gd.sh_degree = g->sh_degree;
+    const int ntiles = cd.tiles_x * cd.tiles_y;
+    const uint64_t cap = (uint64_t)c->cfg.max_pairs;
+    Launch L = c->L();
+    const int64_t n = g->n;
+    preprocess(L, gd, cd, sl.rec, sl.key, sl.rect, sl.count);
+    if (c->cfg.sort_mode == GS3_SORT_DEPTH_FIRST) {
+        sl.cur = 0;
+        if (n > 0) {
+            hipMemcpyAsync(c->dkeys[0], sl.key, (size_t)n * 4, hipMemcpyDeviceToDevice, c->st);
+            iota_u32(L, c->dvals[0], n);
+            const int r = radix_sort_u32(L, c->dkeys, c->dvals, n, 32, c->radix_hist, c->scan_tmp);
+            const uint32_t* order = c->dvals[r];
+            const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
+            bin_count(L, order, n, sl.rect, sl.count, cd.tiles_x, ntiles, c->bin_hist);
+            scan_u32_to_u64(L, c->bin_hist, (int64_t)ntiles * nchunks, c->bin_base, sl.total, c->scan_tmp);
+            bin_scatter(L, order, n, sl.rect, sl.count, cd.tiles_x, ntiles, c->bin_base, cap, sl.vals[0]);
+            ranges_from_hist(L, c->bin_base, sl.total, ntiles, (int)nchunks, cap, sl.ranges, c->flags);
+        } else {
+            fill_u32(L, (uint32_t*)sl.ranges, 0u, 2 * (int64_t)ntiles);
+            fill_u32(L, (uint32_t*)sl.total, 0u, 2);
+        }
+        sl.K_host = -1;
+    } else {
+        scan_u32_to_u64(L, sl.count, n, c->offs, sl.total, c->scan_tmp);
+        emit_pairs(L, n, sl.key, sl.rect, c->offs, cd.tiles_x, cap, sl.pkeys[0], sl.vals[0]);
+        uint64_t K = 0;
+        if (hipMemcpyAsync(&K, sl.total, 8, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+            hipStreamSynchronize(c->st) != hipSuccess)
+            return c->fail(GS3_EHIP, "render: reading the pair count failed");
+        sl.K_host = (int64_t)K;
+        if (K > cap) {
+            fill_u32(L, (uint32_t*)c->flags, 1u, 1);
+            return c->fail(GS3_ECAPACITY, "render: more pairs than max_pairs");
+        }
+        int tb = 0;
+        while ((1 << tb) < ntiles) tb++;
+        sl.cur = radix_sort_u64(L, sl.pkeys, sl.vals, (int64_t)K, 32 + tb, c->radix_hist, c->scan_tmp);
+        ranges_from_keys(L, sl.pkeys[sl.cur], (int64_t)K, ntiles, sl.ranges);
+    }
+    blend_forward(L, cd, sl.ranges, sl.vals[sl.cur], sl.rec, image, sl.T_final, sl.last);
+    gs3_status st = c->check_launch("render");
+    if (st != GS3_OK) return st;
+    sl.g = gd;
+    sl.cam = cd;
+    sl.valid = true;
+    return GS3_OK;
+}
+
+gs3_status gs3_render_backward(gs3_ctx* c, int32_t slot, const float* d_image, const gs3_grads* out) {
+    if (!c) return GS3_EINVAL;
+    if (slot < 0 || slot >= (int)c->slots.size()) return c->fail(GS3_EINVAL, "bad slot");
+    if (!d_image || !out) return c->fail(GS3_EINVAL, "null argument");
+    Slot& sl = c->slots[slot];
+    if (!sl.valid) return c->fail(GS3_ESTATE, "render_backward before a successful render on this slot");
+    Launch L = c->L();
+    const int64_t n = sl.g.n;
+    fill_f32(L, c->accum, 0.f, 9 * n);
+    blend_backward(L, sl.cam, sl.ranges, sl.vals[sl.cur], sl.rec, d_image, sl.T_final, sl.last, c->accum);
+    GradsDev gd;
+    gd.d_means = out->d_means; gd.d_quats = out->d_quats; gd.d_log_scales = out->d_log_scales;
+    gd.d_opac = out->d_opacity_logits; gd.d_sh = out->d_sh; gd.d_dmu = sl.g.dmu ? out->d_dmu : nullptr;
+    gd.d_dq = sl.g.dq ? out->d_dq : nullptr; gd.d_uv = out->d_uv; gd.d_conic = out->d_conic;
+    gd.d_opacity = out->d_opacity; gd.d_rgb = out->d_rgb;
+    preprocess_backward(L, sl.g, sl.cam, c->accum, gd);
+    return c->check_launch("render_backward");
+}
+
+/* ---- loss / optimiser ----------------------------------------------------- */
+
+gs3_status gs3_loss(gs3_ctx* c, const float* image, const float* target, int32_t height, int32_t width,
+                    float lambda_dssim, float* loss_dev, float* d_image) {
+    if (!c) return GS3_EINVAL;
+    if (!image || !target || !loss_dev || !d_image) return c->fail(GS3_EINVAL, "loss: null argument");
+    if (height < 1 || width < 1 || height > c->cfg.max_height || width > c->cfg.max_width)
+        return c->fail(GS3_EINVAL, "loss: image size outside the context's maximum");
+    if (!(lambda_dssim >= 0.f && lambda_dssim <= 1.f)) return c->fail(GS3_EINVAL, "loss: lambda outside [0, 1]");
+    LossWork w{c->loss_maps, c->loss_bsum, loss_blocks(height, width)};
+    loss_forward_backward(c->L(), image, target, height, width, lambda_dssim, w, loss_dev, d_image, c->flags + 1);
+    return c->check_launch("loss");
+}
+
+gs3_status gs3_adam(gs3_ctx* c, float* param, const float* grad, float* m, float* v, int64_t n, int32_t step,
+                    float lr, float beta1, float beta2, float eps) {
+    if (!c) return GS3_EINVAL;
+    if (n < 0 || step < 1 || (n > 0 && (!param || !grad || !m || !v))) return c->fail(GS3_EINVAL, "adam: bad arguments");
+    adam(c->L(), param, grad, m, v, n, step, lr, beta1, beta2, eps);
+    return c->check_launch("adam");
+}
+
+/* ---- inspection ----------------------------------------------------------- */
+
+gs3_status gs3_debug_counts(gs3_ctx* c, int32_t slot, int64_t* num_pairs, int32_t* overflow) {
+    if (!c) return GS3_EINVAL;
+    if (slot < 0 || slot >= (int)c->slots.size()) return c->fail(GS3_EINVAL, "bad slot");
+    Slot& sl = c->slots[slot];
+    uint64_t K = 0;
+    int flags[4] = {0, 0, 0, 0};
+    if (hipMemcpyAsync(&K, sl.total, 8, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipMemcpyAsync(flags, c->flags, 16, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "debug_counts: copy failed");
+    if (num_pairs) *num_pairs = (int64_t)K;
+    const int ov = K > (uint64_t)c->cfg.max_pairs;
+    if (overflow) *overflow = ov;
+    return ov ? c->fail(GS3_ECAPACITY, "pair list overflowed") : GS3_OK;
+}
+
+gs3_status gs3_debug_pairs(gs3_ctx* c, int32_t slot, uint64_t* keys, uint32_t* vals, int64_t cap) {
+    if (!c) return GS3_EINVAL;
+    if (slot < 0 || slot >= (int)c->slots.size()) return c->fail(GS3_EINVAL, "bad slot");
+    Slot& sl = c->slots[slot];
+    if (!sl.valid) return c->fail(GS3_ESTATE, "no render on this slot");
+    int64_t K = 0;
+    int32_t ov = 0;
+    gs3_status s = gs3_debug_counts(c, slot, &K, &ov);
+    if (s != GS3_OK) return s;
+    if (cap < K) return c->fail(GS3_EINVAL, "debug_pairs: buffer too small");
+    if (K == 0) return GS3_OK;
+    const int ntiles = sl.cam.tiles_x * sl.cam.tiles_y;
+    if (vals && hipMemcpyAsync(vals, sl.vals[sl.cur], (size_t)K * 4, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "debug_pairs: copy failed");
+    if (keys) {
+        if (c->cfg.sort_mode == GS3_SORT_RADIX64) {
+            if (hipMemcpyAsync(keys, sl.pkeys[sl.cur], (size_t)K * 8, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+                return c->fail(GS3_EHIP, "debug_pairs: copy failed");
+        } else {
+            debug_keys(c->L(), sl.ranges, sl.vals[sl.cur], sl.key, ntiles, keys);
+        }
+    }
+    return c->check_launch("debug_pairs");
+}
+
+gs3_status gs3_debug_ranges(gs3_ctx* c, int32_t slot, uint32_t* ranges) {
+    if (!c || !ranges) return GS3_EINVAL;
+    if (slot < 0 || slot >= (int)c->slots.size()) return c->fail(GS3_EINVAL, "bad slot");
+    Slot& sl = c->slots[slot];
+    if (!sl.valid) return c->fail(GS3_ESTATE, "no render on this slot");
+    const int ntiles = sl.cam.tiles_x * sl.cam.tiles_y;
+    if (hipMemcpyAsync(ranges, sl.ranges, (size_t)ntiles * 8, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "debug_ranges: copy failed");
+    return GS3_OK;
+}
+
+gs3_status gs3_debug_gaussians(gs3_ctx* c, int32_t slot, uint32_t* key, int32_t* box, float* rec) {
+    if (!c) return GS3_EINVAL;
+    if (slot < 0 || slot >= (int)c->slots.size()) return c->fail(GS3_EINVAL, "bad slot");
+    Slot& sl = c->slots[slot];
+    if (!sl.valid) return c->fail(GS3_ESTATE, "no render on this slot");
+    const int64_t n = sl.g.n;
+    if (key && n && hipMemcpyAsync(key, sl.key, (size_t)n * 4, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "debug_gaussians: copy failed");
+    if (box || rec) debug_records(c->L(), n, sl.rec, box, rec);
+    return c->check_launch("debug_gaussians");
+}
+
+gs3_status gs3_debug_pixels(gs3_ctx* c, int32_t slot, float* T_final, int32_t* last) {
+    if (!c) return GS3_EINVAL;
+    if (slot < 0 || slot >= (int)c->slots.size()) return c->fail(GS3_EINVAL, "bad slot");
+    Slot& sl = c->slots[slot];
+    if (!sl.valid) return c->fail(GS3_ESTATE, "no render on this slot");
+    const size_t P = (size_t)sl.cam.W * sl.cam.H;
+    if (T_final && hipMemcpyAsync(T_final, sl.T_final, P * 4, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "debug_pixels: copy failed");
+    if (last && hipMemcpyAsync(last, sl.last, P * 4, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "debug_pixels: copy failed");
+    return GS3_OK;
+}
+
+gs3_status gs3_check_flags(gs3_ctx* c) {
+    if (!c) return GS3_EINVAL;
+    int flags[4] = {0, 0, 0, 0};
+    if (hipMemcpyAsync(flags, c->flags, 16, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "check_flags: copy failed");
+    fill_u32(c->L(), (uint32_t*)c->flags, 0u, 4);
+    if (flags[0]) return c->fail(GS3_ECAPACITY, "a pair list overflowed");
+    if (flags[1]) return c->fail(GS3_ENONFINITE, "a loss was not finite");
+    return GS3_OK;
+}
+
+/* ---- profiling ------------------------------------------------------------- */
+
+gs3_status gs3_profile_enable(gs3_ctx* c, int32_t on) {
+    if (!c) return GS3_EINVAL;
+    c->prof_on = on != 0;
+    return GS3_OK;
+}
+
+gs3_status gs3_profile_reset(gs3_ctx* c) {
+    if (!c) return GS3_EINVAL;
+    c->prof.collect();
+    c->prof.totals.clear();
+    return GS3_OK;
+}
+
+gs3_status gs3_profile_query(gs3_ctx* c, const char* kernel, double* total_ms, int64_t* launches) {
+    if (!c || !kernel) return GS3_EINVAL;
+    c->prof.collect();
+    auto it = c->prof.totals.find(kernel);
+    if (total_ms) *total_ms = it == c->prof.totals.end() ? 0.0 : it->second.first;
+    if (launches) *launches = it == c->prof.totals.end() ? 0 : it->second.second;
+    return GS3_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,327 @@
+// Device-side building blocks shared by the gs3 kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs3 {
+
+constexpr int kTile = 16;
+constexpr int kBlendThreads = kTile * kTile;   // one thread per pixel of a tile
+
+// Camera constants passed by value to kernels.
+struct CamDev {
+    int W, H, tiles_x, tiles_y;
+    float fx, fy, cx, cy, near_z;
+    float R[9];     // world_to_cam rotation, row-major
+    float t[3];     // world_to_cam translation
+    float cpos[3];  // camera centre
+    float bg[3];
+};
+
+// Gaussian inputs of one render.
+struct GaussDev {
+    const float* means;
+    const float* quats;
+    const float* log_scales;
+    const float* opac;
+    const float* sh;
+    const float* dmu;   // may be null
+    const float* dq;    // may be null
+    int64_t n;
+    int sh_degree;
+};
+
+// Blend record of one Gaussian, three 16-byte words:
+//   w0 = (u, v, A, B), w1 = (C, opacity, r, g), w2 = (b, box x0|y0<<16, box x1|y1<<16, 0)
+// with the conic stored so that power = -(A dx^2 + C dy^2)/2 - B dx dy.
+
+// exp used for the scale activation.  It is part of the single-precision
+// decision procedure (the 3-sigma radius depends on it), so its result is
+// fixed bit for bit: Cody-Waite reduction x = k ln2 + r with ln2 split into
+// a 16-bit head and a tail, degree-7 Taylor polynomial of e^r by Horner's
+// rule, then scaling by 2^k.
+__device__ __forceinline__ float spec_exp(float x) {
+#pragma clang fp contract(off)
+    x = fminf(fmaxf(x, -87.0f), 88.0f);
+    float k = rintf(x * 0x1.715476p+0f);
+    float r = x - k * 0x1.62e4p-1f;
+    r = r - k * 0x1.7f7d1cp-20f;
+    float p = 1.0f / 5040.0f;
+    p = p * r + 1.0f / 720.0f;
+    p = p * r + 1.0f / 120.0f;
+    p = p * r + 1.0f / 24.0f;
+    p = p * r + 1.0f / 6.0f;
+    p = p * r + 0.5f;
+    p = p * r + 1.0f;
+    p = p * r + 1.0f;
+    return ldexpf(p, (int)k);
+}
+
+// Forward geometry of one Gaussian in single precision.  Every quantity
+// that feeds a discrete decision (view depth, 2D covariance, radius, pixel
+// box) is evaluated with a fixed operation order and no contraction; the
+// same values are then used as the continuous forward values.
+struct Geo {
+    float m[3];          // translated mean
+    float t[3];          // camera-space mean
+    float qn;            // |q|
+    float qh[4];         // q / |q|
+    float dn;            // max(|dq|, 1e-12)
+    float dh[4];         // dq / dn
+    float qp[4];         // q' = qh (x) dh
+    float Rp[9];         // R(q')
+    float s[3];          // exp(log-scale)
+    float S00, S01, S02, S11, S12, S22;   // 3D covariance
+    float txz, tyz;      // t_x / t_z, t_y / t_z
+    float txc, tyc;      // clamped for J
+    bool clx, cly;       // clamp active
+    float j00, j02, j11, j12;
+    float T00, T01, T02, T10, T11, T12;   // J W
+    float a, b, c, det;  // 2D covariance (+0.3 I) and its determinant
+    float u, v, r;       // image-space mean and 3-sigma radius (pixels)
+    int x0, y0, x1, y1;  // inclusive pixel box
+};
+
+// Returns false when the Gaussian is culled.
+__device__ __forceinline__ bool geo_forward(const GaussDev& g, const CamDev& cam, int64_t i, Geo& o) {
+#pragma clang fp contract(off)
+    const float* R = cam.R;
+    float m0 = g.means[3 * i + 0], m1 = g.means[3 * i + 1], m2 = g.means[3 * i + 2];
+    if (g.dmu) {
+        m0 = m0 + g.dmu[3 * i + 0];
+        m1 = m1 + g.dmu[3 * i + 1];
+        m2 = m2 + g.dmu[3 * i + 2];
+    }
+    o.m[0] = m0; o.m[1] = m1; o.m[2] = m2;
+    float tx = ((R[0] * m0 + R[1] * m1) + R[2] * m2) + cam.t[0];
+    float ty = ((R[3] * m0 + R[4] * m1) + R[5] * m2) + cam.t[1];
+    float tz = ((R[6] * m0 + R[7] * m1) + R[8] * m2) + cam.t[2];
+    o.t[0] = tx; o.t[1] = ty; o.t[2] = tz;
+    if (!(tz > cam.near_z)) return false;
+
+    float q0 = g.quats[4 * i + 0], q1 = g.quats[4 * i + 1], q2 = g.quats[4 * i + 2], q3 = g.quats[4 * i + 3];
+    float qn = sqrtf(((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3);
+    o.qn = qn;
+    float aw = 1.0f, ax = 0.0f, ay = 0.0f, az = 0.0f;
+    if (qn > 0.0f) { aw = q0 / qn; ax = q1 / qn; ay = q2 / qn; az = q3 / qn; }
+    o.qh[0] = aw; o.qh[1] = ax; o.qh[2] = ay; o.qh[3] = az;
+    float w = aw, x = ax, y = ay, z = az;
+    if (g.dq) {
+        float d0 = g.dq[4 * i + 0], d1 = g.dq[4 * i + 1], d2 = g.dq[4 * i + 2], d3 = g.dq[4 * i + 3];
+        float dn = sqrtf(((d0 * d0 + d1 * d1) + d2 * d2) + d3 * d3);
+        dn = fmaxf(dn, 1e-12f);
+        float bw = d0 / dn, bx = d1 / dn, by = d2 / dn, bz = d3 / dn;
+        o.dn = dn;
+        o.dh[0] = bw; o.dh[1] = bx; o.dh[2] = by; o.dh[3] = bz;
+        w = ((aw * bw - ax * bx) - ay * by) - az * bz;
+        x = ((aw * bx + ax * bw) + ay * bz) - az * by;
+        y = ((aw * by - ax * bz) + ay * bw) + az * bx;
+        z = ((aw * bz + ax * by) - ay * bx) + az * bw;
+    }
+    o.qp[0] = w; o.qp[1] = x; o.qp[2] = y; o.qp[3] = z;
+    float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+    float wx = w * x, wy = w * y, wz = w * z;
+    float r00 = 1.0f - 2.0f * (yy + zz), r01 = 2.0f * (xy - wz), r02 = 2.0f * (xz + wy);
+    float r10 = 2.0f * (xy + wz), r11 = 1.0f - 2.0f * (xx + zz), r12 = 2.0f * (yz - wx);
+    float r20 = 2.0f * (xz - wy), r21 = 2.0f * (yz + wx), r22 = 1.0f - 2.0f * (xx + yy);
+    o.Rp[0] = r00; o.Rp[1] = r01; o.Rp[2] = r02;
+    o.Rp[3] = r10; o.Rp[4] = r11; o.Rp[5] = r12;
+    o.Rp[6] = r20; o.Rp[7] = r21; o.Rp[8] = r22;
+    float s0 = spec_exp(g.log_scales[3 * i + 0]);
+    float s1 = spec_exp(g.log_scales[3 * i + 1]);
+    float s2 = spec_exp(g.log_scales[3 * i + 2]);
+    o.s[0] = s0; o.s[1] = s1; o.s[2] = s2;
+    float M00 = r00 * s0, M01 = r01 * s1, M02 = r02 * s2;
+    float M10 = r10 * s0, M11 = r11 * s1, M12 = r12 * s2;
+    float M20 = r20 * s0, M21 = r21 * s1, M22 = r22 * s2;
+    o.S00 = (M00 * M00 + M01 * M01) + M02 * M02;
+    o.S01 = (M00 * M10 + M01 * M11) + M02 * M12;
+    o.S02 = (M00 * M20 + M01 * M21) + M02 * M22;
+    o.S11 = (M10 * M10 + M11 * M11) + M12 * M12;
+    o.S12 = (M10 * M20 + M11 * M21) + M12 * M22;
+    o.S22 = (M20 * M20 + M21 * M21) + M22 * M22;
+
+    float limx = (1.3f * (0.5f * (float)cam.W)) / cam.fx;
+    float limy = (1.3f * (0.5f * (float)cam.H)) / cam.fy;
+    float txz = tx / tz, tyz = ty / tz;
+    o.txz = txz; o.tyz = tyz;
+    float txc = fminf(fmaxf(txz, -limx), limx);
+    float tyc = fminf(fmaxf(tyz, -limy), limy);
+    o.txc = txc; o.tyc = tyc;
+    o.clx = (txz < -limx) || (txz > limx);
+    o.cly = (tyz < -limy) || (tyz > limy);
+    float j00 = cam.fx / tz, j02 = -(cam.fx * txc) / tz;
+    float j11 = cam.fy / tz, j12 = -(cam.fy * tyc) / tz;
+    o.j00 = j00; o.j02 = j02; o.j11 = j11; o.j12 = j12;
+    float T00 = j00 * R[0] + j02 * R[6], T01 = j00 * R[1] + j02 * R[7], T02 = j00 * R[2] + j02 * R[8];
+    float T10 = j11 * R[3] + j12 * R[6], T11 = j11 * R[4] + j12 * R[7], T12 = j11 * R[5] + j12 * R[8];
+    o.T00 = T00; o.T01 = T01; o.T02 = T02; o.T10 = T10; o.T11 = T11; o.T12 = T12;
+    float U00 = (T00 * o.S00 + T01 * o.S01) + T02 * o.S02;
+    float U01 = (T00 * o.S01 + T01 * o.S11) + T02 * o.S12;
+    float U02 = (T00 * o.S02 + T01 * o.S12) + T02 * o.S22;
+    float U10 = (T10 * o.S00 + T11 * o.S01) + T12 * o.S02;
+    float U11 = (T10 * o.S01 + T11 * o.S11) + T12 * o.S12;
+    float U12 = (T10 * o.S02 + T11 * o.S12) + T12 * o.S22;
+    float a = ((U00 * T00 + U01 * T01) + U02 * T02) + 0.3f;
+    float b = (U00 * T10 + U01 * T11) + U02 * T12;
+    float c = ((U10 * T10 + U11 * T11) + U12 * T12) + 0.3f;
+    float det = a * c - b * b;
+    o.a = a; o.b = b; o.c = c; o.det = det;
+    if (!(det > 0.0f)) return false;
+    float mid = 0.5f * (a + c);
+    float disc = mid * mid - det;
+    float lam = mid + sqrtf(fmaxf(disc, 0.0f));
+    float r = ceilf(3.0f * sqrtf(lam));
+    float u = cam.fx * txz + cam.cx;
+    float v = cam.fy * tyz + cam.cy;
+    o.u = u; o.v = v; o.r = r;
+    if (!(fabsf(u) <= 1e7f && fabsf(v) <= 1e7f && r <= 1e7f)) return false;
+    float x0 = fmaxf(ceilf(u - r), 0.0f), x1 = fminf(floorf(u + r), (float)(cam.W - 1));
+    float y0 = fmaxf(ceilf(v - r), 0.0f), y1 = fminf(floorf(v + r), (float)(cam.H - 1));
+    if (x0 > x1 || y0 > y1) return false;
+    o.x0 = (int)x0; o.y0 = (int)y0; o.x1 = (int)x1; o.y1 = (int)y1;
+    return true;
+}
+
+// Real orthonormal SH (Condon-Shortley phase), k = l^2 + l + m.
+namespace shc {
+constexpr float c0 = 0.28209479177387814f;   // 1 / (2 sqrt(pi))
+constexpr float c1 = 0.4886025119029199f;    // sqrt(3 / (4 pi))
+constexpr float c2a = 1.0925484305920792f;   // sqrt(15 / pi) / 2
+constexpr float c2b = 0.31539156525252005f;  // sqrt(5 / pi) / 4
+constexpr float c2c = 0.5462742152960396f;   // sqrt(15 / pi) / 4
+constexpr float c3a = 0.5900435899266435f;   // sqrt(35 / (2 pi)) / 4
+constexpr float c3b = 2.890611442640554f;    // sqrt(105 / pi) / 2
+constexpr float c3c = 0.4570457994644658f;   // sqrt(21 / (2 pi)) / 4
+constexpr float c3d = 0.3731763325901154f;   // sqrt(7 / pi) / 4
+constexpr float c3e = 1.445305721320277f;    // sqrt(105 / pi) / 4
+}  // namespace shc
+
+__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float Y[16]) {
+    using namespace shc;
+    Y[0] = c0;
+    if (deg < 1) return;
+    Y[1] = -c1 * y; Y[2] = c1 * z; Y[3] = -c1 * x;
+    if (deg < 2) return;
+    float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = c2a * x * y;
+    Y[5] = -c2a * y * z;
+    Y[6] = c2b * (2.0f * zz - xx - yy);
+    Y[7] = -c2a * x * z;
+    Y[8] = c2c * (xx - yy);
+    if (deg < 3) return;
+    Y[9] = -c3a * y * (3.0f * xx - yy);
+    Y[10] = c3b * x * y * z;
+    Y[11] = -c3c * y * (4.0f * zz - xx - yy);
+    Y[12] = c3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -c3c * x * (4.0f * zz - xx - yy);
+    Y[14] = c3e * z * (xx - yy);
+    Y[15] = -c3a * x * (xx - 3.0f * yy);
+}
+
+// sum_k w_k grad Y_k(x, y, z) (gradient with respect to the raw components)
+__device__ __forceinline__ void sh_grad(int deg, float x, float y, float z, const float w[16],
+                                        float& gx, float& gy, float& gz) {
+    using namespace shc;
+    gx = 0.0f; gy = 0.0f; gz = 0.0f;
+    if (deg < 1) return;
+    gy += -c1 * w[1]; gz += c1 * w[2]; gx += -c1 * w[3];
+    if (deg < 2) return;
+    float xx = x * x, yy = y * y, zz = z * z;
+    gx += c2a * y * w[4];               gy += c2a * x * w[4];
+    gy += -c2a * z * w[5];              gz += -c2a * y * w[5];
+    gx += -2.0f * c2b * x * w[6];       gy += -2.0f * c2b * y * w[6];   gz += 4.0f * c2b * z * w[6];
+    gx += -c2a * z * w[7];              gz += -c2a * x * w[7];
+    gx += 2.0f * c2c * x * w[8];        gy += -2.0f * c2c * y * w[8];
+    if (deg < 3) return;
+    gx += -c3a * 6.0f * x * y * w[9];   gy += -c3a * (3.0f * xx - 3.0f * yy) * w[9];
+    gx += c3b * y * z * w[10];          gy += c3b * x * z * w[10];      gz += c3b * x * y * w[10];
+    gx += 2.0f * c3c * x * y * w[11];   gy += -c3c * (4.0f * zz - xx - 3.0f * yy) * w[11];
+    gz += -8.0f * c3c * y * z * w[11];
+    gx += -6.0f * c3d * x * z * w[12];  gy += -6.0f * c3d * y * z * w[12];
+    gz += c3d * (6.0f * zz - 3.0f * xx - 3.0f * yy) * w[12];
+    gx += -c3c * (4.0f * zz - 3.0f * xx - yy) * w[13];
+    gy += 2.0f * c3c * x * y * w[13];   gz += -8.0f * c3c * x * z * w[13];
+    gx += 2.0f * c3e * x * z * w[14];   gy += -2.0f * c3e * y * z * w[14];  gz += c3e * (xx - yy) * w[14];
+    gx += -c3a * (3.0f * xx - 3.0f * yy) * w[15];  gy += 6.0f * c3a * x * y * w[15];
+}
+
+// rotation matrix of a unit quaternion (w, x, y, z), row-major
+__device__ __forceinline__ void quat_to_rot(const float q[4], float R[9]) {
+    float w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0f - 2.0f * (y * y + z * z); R[1] = 2.0f * (x * y - w * z); R[2] = 2.0f * (x * z + w * y);
+    R[3] = 2.0f * (x * y + w * z); R[4] = 1.0f - 2.0f * (x * x + z * z); R[5] = 2.0f * (y * z - w * x);
+    R[6] = 2.0f * (x * z - w * y); R[7] = 2.0f * (y * z + w * x); R[8] = 1.0f - 2.0f * (x * x + y * y);
+}
+
+// Colour of a Gaussian: direction from the camera centre to the translated
+// mean, rotated back into the frame of the untransformed Gaussian
+// (d_loc = R(qh) R(q')^T d), then max(0, SH(d_loc) + 0.5).
+struct ColourCtx {
+    float dir[3], wn;     // unit direction and |mu' - c|
+    float Rh[9];          // R(qh) (only with a rotation delta)
+    float Ml[9];          // R(qh) R(q')^T
+    float dl[3];          // d_loc
+    float raw[3];         // SH + 0.5 before the clamp
+};
+
+__device__ __forceinline__ void colour_forward(const GaussDev& g, const CamDev& cam, int64_t i, const Geo& o,
+                                               ColourCtx& cc) {
+    float w0 = o.m[0] - cam.cpos[0], w1 = o.m[1] - cam.cpos[1], w2 = o.m[2] - cam.cpos[2];
+    float wn = sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
+    cc.wn = wn;
+    float inv = 1.0f / wn;
+    cc.dir[0] = w0 * inv; cc.dir[1] = w1 * inv; cc.dir[2] = w2 * inv;
+    if (g.dq) {
+        quat_to_rot(o.qh, cc.Rh);
+        // Ml = Rh Rp^T
+        for (int r = 0; r < 3; r++)
+            for (int k = 0; k < 3; k++)
+                cc.Ml[3 * r + k] = cc.Rh[3 * r + 0] * o.Rp[3 * k + 0] + cc.Rh[3 * r + 1] * o.Rp[3 * k + 1] +
+                                   cc.Rh[3 * r + 2] * o.Rp[3 * k + 2];
+        for (int r = 0; r < 3; r++)
+            cc.dl[r] = cc.Ml[3 * r] * cc.dir[0] + cc.Ml[3 * r + 1] * cc.dir[1] + cc.Ml[3 * r + 2] * cc.dir[2];
+    } else {
+        cc.dl[0] = cc.dir[0]; cc.dl[1] = cc.dir[1]; cc.dl[2] = cc.dir[2];
+    }
+    float Y[16];
+    sh_basis(g.sh_degree, cc.dl[0], cc.dl[1], cc.dl[2], Y);
+    int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+    const float* sh = g.sh + i * (int64_t)K * 3;
+    float c0 = 0.5f, c1 = 0.5f, c2 = 0.5f;
+    for (int k = 0; k < K; k++) {
+        c0 += Y[k] * sh[3 * k + 0];
+        c1 += Y[k] * sh[3 * k + 1];
+        c2 += Y[k] * sh[3 * k + 2];
+    }
+    cc.raw[0] = c0; cc.raw[1] = c1; cc.raw[2] = c2;
+}
+
+// alpha of a Gaussian record at pixel (px, py); false when the candidate is
+// skipped (power > 0 or alpha < 1/255).  Used identically by the forward and
+// backward blend so that both walk the same contributors.
+__device__ __forceinline__ bool blend_alpha(float px, float py, const float4& w0, const float4& w1,
+                                            float& dx, float& dy, float& G, float& raw, float& alpha) {
+#pragma clang fp contract(off)
+    dx = px - w0.x;
+    dy = py - w0.y;
+    float power = -0.5f * (w0.z * dx * dx + w1.x * dy * dy) - w0.w * dx * dy;
+    if (power > 0.0f) return false;
+    G = __expf(power);
+    raw = w1.y * G;
+    alpha = fminf(0.99f, raw);
+    return alpha >= (1.0f / 255.0f);
+}
+
+__device__ __forceinline__ bool box_contains(uint32_t b0, uint32_t b1, int px, int py) {
+    int x0 = (int)(b0 & 0xFFFFu), y0 = (int)(b0 >> 16), x1 = (int)(b1 & 0xFFFFu), y1 = (int)(b1 >> 16);
+    return px >= x0 && px <= x1 && py >= y0 && py <= y1;
+}
+
+// wave64 helpers
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace gs3

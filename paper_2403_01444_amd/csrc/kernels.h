@@ -1,0 +1,92 @@
+// Host-side launchers of the gs3 kernels (internal to libgs3.so).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace gs3 {
+
+// Optional per-kernel timing: when `prof` is set, every launch is bracketed
+// by events recorded on the launch stream.
+struct Profiler {
+    virtual ~Profiler() = default;
+    virtual void begin(const char* name, hipStream_t st) = 0;
+    virtual void end(hipStream_t st) = 0;
+};
+
+struct Launch {
+    hipStream_t st;
+    Profiler* prof;
+};
+
+// ---- scan / sort (sort.hip) ------------------------------------------------
+// Exclusive prefix sum of n u32 values into u32 or u64 outputs; the grand
+// total goes to *total (device).  `tmp` holds scan_tmp_words(n) u64.
+int64_t scan_tmp_words(int64_t n);
+void scan_u32_to_u64(const Launch& L, const uint32_t* in, int64_t n, uint64_t* out, uint64_t* total, uint64_t* tmp);
+void scan_u32_to_u32(const Launch& L, const uint32_t* in, int64_t n, uint32_t* out, uint64_t* total, uint64_t* tmp);
+
+// Stable LSD radix sort of (key, value) pairs over the low `bits` key bits.
+// Buffers ping-pong; returns the index (0 or 1) holding the result.
+// `hist` holds radix_hist_words(n) u32, `tmp` scan_tmp_words(radix_hist_words(n)) u64.
+int64_t radix_hist_words(int64_t n);
+int radix_sort_u32(const Launch& L, uint32_t* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist,
+                   uint64_t* tmp);
+int radix_sort_u64(const Launch& L, uint64_t* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist,
+                   uint64_t* tmp);
+
+void fill_u32(const Launch& L, uint32_t* p, uint32_t v, int64_t n);
+void fill_f32(const Launch& L, float* p, float v, int64_t n);
+void iota_u32(const Launch& L, uint32_t* p, int64_t n);
+
+// ---- rasterizer (raster.hip) -------------------------------------------------
+void preprocess(const Launch& L, const GaussDev& g, const CamDev& cam, float4* rec, uint32_t* key, uint2* rect,
+                uint32_t* count);
+// radix64 path: keys/vals of every pair in Gaussian order from exclusive offsets
+void emit_pairs(const Launch& L, int64_t n, const uint32_t* key, const uint2* rect, const uint64_t* offs,
+                int tiles_x, uint64_t cap, uint64_t* keys, uint32_t* vals);
+void ranges_from_keys(const Launch& L, const uint64_t* keys, int64_t K, int ntiles, uint2* ranges);
+// depth-first path: per-chunk tile histograms of depth-ordered Gaussians,
+// then an order-preserving scatter of Gaussian indices.
+constexpr int kBinChunk = 1024;
+void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
+               int tiles_x, int ntiles, uint32_t* hist);
+void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
+                 int tiles_x, int ntiles, const uint64_t* base, uint64_t cap, uint32_t* vals);
+void ranges_from_hist(const Launch& L, const uint64_t* base, const uint64_t* total, int ntiles, int nchunks,
+                      uint64_t cap, uint2* ranges, int* overflow);
+void pairs_total_check(const Launch& L, const uint64_t* total, uint64_t cap, int* overflow);
+
+void blend_forward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals, const float4* rec,
+                   float* image, float* T_final, uint32_t* last);
+void blend_backward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals,
+                    const float4* rec, const float* d_image, const float* T_final, const uint32_t* last,
+                    float* accum);
+
+struct GradsDev {
+    float *d_means, *d_quats, *d_log_scales, *d_opac, *d_sh, *d_dmu, *d_dq;
+    float *d_uv, *d_conic, *d_opacity, *d_rgb;
+};
+void preprocess_backward(const Launch& L, const GaussDev& g, const CamDev& cam, const float* accum,
+                         const GradsDev& out);
+void debug_keys(const Launch& L, const uint2* ranges, const uint32_t* vals, const uint32_t* key, int ntiles,
+                uint64_t* keys_out);
+void debug_records(const Launch& L, int64_t n, const float4* rec, int32_t* box, float* rec9);
+
+// ---- loss (loss.hip) ---------------------------------------------------------
+struct LossWork {
+    float* partial_maps;   // 3 x (3 H W) SSIM partial derivatives
+    double* block_sums;    // 2 x blocks
+    int max_blocks;
+};
+int64_t loss_map_floats(int H, int W);
+int loss_blocks(int H, int W);
+void loss_forward_backward(const Launch& L, const float* x, const float* y, int H, int W, float lambda,
+                           const LossWork& w, float* loss_dev, float* d_image, int* nonfinite);
+
+// ---- optimiser ---------------------------------------------------------------
+void adam(const Launch& L, float* p, const float* g, float* m, float* v, int64_t n, int step, float lr, float b1,
+          float b2, float eps);
+
+}  // namespace gs3

@@ -1,0 +1,30 @@
+// NTC launchers (internal to libgs3.so).
+#pragma once
+#include "kernels.h"
+
+namespace gs3 {
+
+// Shape of the hash encoding, passed by value to kernels.
+struct NtcDev {
+    int res[16];           // grid resolution per level
+    int64_t off[16];       // first table entry of each level
+    uint32_t dense_mask;   // bit l set: level l is stored densely
+    uint32_t T_mask;       // 2^log2_T - 1
+    float aabb_min[3];
+    float inv_ext[3];
+};
+
+int ntc_mlp_params();
+void ntc_forward(const Launch& L, int precision, const NtcDev& nd, const void* table, const void* mlp,
+                 const float* means, int64_t n, float* dmu, float* dq);
+// g_part holds max_parts x ntc_mlp_params() floats
+void ntc_backward(const Launch& L, int precision, const NtcDev& nd, const void* table, const void* mlp,
+                  const float* means, int64_t n, const float* d_dmu, const float* d_dq, float* g_table, float* g_mlp,
+                  float* g_part, int max_parts);
+void ntc_adam(const Launch& L, int precision, float* p, float* g, float* m, float* v, void* work, int64_t n, float lr,
+              float b1, float b2, float eps, float bc1, float bc2);
+void ntc_refresh_work(const Launch& L, int precision, const float* p, void* work, int64_t n);
+void warmup_loss(const Launch& L, const float* dmu, const float* dq, int64_t n, float* loss, float* gmu, float* gq,
+                 double* bsum);
+
+}  // namespace gs3

@@ -1,0 +1,686 @@
+// Neural Transformation Cache on gfx950 (Sec. 4.1, Eq. 5):
+//   (dmu, dq) = MLP(h(mu)),  h = multi-resolution hash encoding,
+//   MLP = 32 -> 64 (ReLU) -> 64 (ReLU) -> 7, no biases.
+//
+// Work unit: a batch of 16 points per wave.  Lane l owns point l % 16 and
+// levels 4 (l / 16) .. 4 (l / 16) + 3 of the encoding, so the 64 lanes cover
+// the 16 x 16 (point, level) pairs of a batch.  Activations go through LDS in
+// [point][feature] layout; every layer is a 16 x 16 MFMA tile product
+// (v_mfma_f32_16x16x16 f16 / bf16, or 16x16x4 f32), weights staged once per
+// workgroup in LDS.  The backward pass recomputes the forward, propagates
+// the output gradient through the three layers, accumulates the weight
+// gradients with MFMA (contraction over the batch's 16 points) in FP32
+// registers, and scatter-adds the encoding gradient into the FP32 table
+// gradient with global atomics.
+//
+// Half-precision backward: each activation-gradient stage is rescaled by a
+// power of two so that its largest magnitude in the batch sits near 2^13
+// before it is rounded to FP16/BF16; the FP32 results are unscaled exactly.
+#include <algorithm>
+
+#include "kernels.h"
+#include "ntc.h"
+
+namespace gs3 {
+
+namespace {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef __bf16 b4v __attribute__((ext_vector_type(4)));
+
+struct PF32 {
+    using S = float;
+    using AF = float;
+    static constexpr int KPL = 1;
+    static constexpr int KSTEP = 4;
+    __device__ static f4v mfma(AF a, AF b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static S cvt(float x) { return x; }
+    __device__ static float tof(S x) { return x; }
+    static constexpr bool kScaled = false;
+};
+struct PF16 {
+    using S = _Float16;
+    using AF = h4v;
+    static constexpr int KPL = 4;
+    static constexpr int KSTEP = 16;
+    __device__ static f4v mfma(AF a, AF b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
+    __device__ static S cvt(float x) { return (S)x; }
+    __device__ static float tof(S x) { return (float)x; }
+    static constexpr bool kScaled = true;
+};
+struct PBF16 {
+    using S = __bf16;
+    using AF = b4v;
+    static constexpr int KPL = 4;
+    static constexpr int KSTEP = 16;
+    __device__ static f4v mfma(AF a, AF b, f4v c) {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+    __device__ static S cvt(float x) { return (S)x; }
+    __device__ static float tof(S x) { return (float)x; }
+    static constexpr bool kScaled = true;
+};
+
+// A or B fragment, elements base[row * ld + k0 + i] (contiguous in k)
+template <class P>
+__device__ __forceinline__ typename P::AF frag_k_contig(const typename P::S* base, int ld, int row, int k0) {
+    typename P::AF f;
+    if constexpr (P::KPL == 1) {
+        f = base[row * ld + k0];
+    } else {
+#pragma unroll
+        for (int i = 0; i < P::KPL; i++) f[i] = base[row * ld + k0 + i];
+    }
+    return f;
+}
+// fragment with elements base[(k0 + i) * ld + col] (strided in k)
+template <class P>
+__device__ __forceinline__ typename P::AF frag_k_strided(const typename P::S* base, int ld, int col, int k0) {
+    typename P::AF f;
+    if constexpr (P::KPL == 1) {
+        f = base[k0 * ld + col];
+    } else {
+#pragma unroll
+        for (int i = 0; i < P::KPL; i++) f[i] = base[(k0 + i) * ld + col];
+    }
+    return f;
+}
+
+// Row strides (elements) of the LDS arrays; +4 breaks bank regularity.
+constexpr int kMlpParams = 64 * 32 + 64 * 64 + 7 * 64;
+constexpr int LD32 = 32 + 4;
+constexpr int LD64 = 64 + 4;
+constexpr int LD16 = 16 + 4;
+constexpr int kWaves = 4;
+constexpr int kPts = 16;
+
+template <class P>
+__device__ __forceinline__ float2 load2(const typename P::S* table, int64_t entry) {
+    if constexpr (sizeof(typename P::S) == 4) {
+        return *reinterpret_cast<const float2*>(table + 2 * entry);
+    } else {
+        const typename P::S* e = table + 2 * entry;
+        return make_float2(P::tof(e[0]), P::tof(e[1]));
+    }
+}
+
+// normalised position; false when outside [0, 1]^3 (the point is discarded)
+__device__ __forceinline__ bool ntc_normalise(const NtcDev& nd, const float* mu, float x[3]) {
+#pragma clang fp contract(off)
+    bool in = true;
+    for (int k = 0; k < 3; k++) {
+        x[k] = (mu[k] - nd.aabb_min[k]) * nd.inv_ext[k];
+        in = in && (x[k] >= 0.0f) && (x[k] <= 1.0f);
+    }
+    return in;
+}
+
+// corner entries and trilinear weights of level lv
+__device__ __forceinline__ void ntc_corners(const NtcDev& nd, int lv, const float x[3], int64_t ent[8], float wt[8]) {
+    float w[3];
+    uint32_t i0[3];
+    {
+#pragma clang fp contract(off)
+        const int N = nd.res[lv];
+        const float fN = (float)N;
+        for (int k = 0; k < 3; k++) {
+            const float p = x[k] * fN;
+            int c = (int)floorf(p);
+            c = c > N - 1 ? N - 1 : c;
+            c = c < 0 ? 0 : c;
+            i0[k] = (uint32_t)c;
+            w[k] = p - (float)c;
+        }
+    }
+    const int N1 = nd.res[lv] + 1;
+    const bool dense = (nd.dense_mask >> lv) & 1u;
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+        const uint32_t vx = i0[0] + (c & 1), vy = i0[1] + ((c >> 1) & 1), vz = i0[2] + ((c >> 2) & 1);
+        uint32_t idx;
+        if (dense)
+            idx = vx + (uint32_t)N1 * (vy + (uint32_t)N1 * vz);
+        else
+            idx = ((vx * 1u) ^ (vy * 2654435761u) ^ (vz * 805459861u)) & nd.T_mask;
+        ent[c] = nd.off[lv] + (int64_t)idx;
+        wt[c] = ((c & 1) ? w[0] : 1.0f - w[0]) * (((c >> 1) & 1) ? w[1] : 1.0f - w[1]) *
+                (((c >> 2) & 1) ? w[2] : 1.0f - w[2]);
+    }
+}
+
+template <class P>
+__device__ __forceinline__ void load_weights(const typename P::S* __restrict__ mlp, typename P::S* sW1,
+                                             typename P::S* sW2, typename P::S* sW3, typename P::S* sW1t,
+                                             typename P::S* sW2t, typename P::S* sW3t) {
+    using S = typename P::S;
+    const S* W1 = mlp;
+    const S* W2 = mlp + 64 * 32;
+    const S* W3 = mlp + 64 * 32 + 64 * 64;
+    for (int k = threadIdx.x; k < 64 * 32; k += blockDim.x) {
+        const int r = k / 32, c = k % 32;
+        if (sW1) sW1[r * LD32 + c] = W1[k];
+        if (sW1t) sW1t[c * LD64 + r] = W1[k];
+    }
+    for (int k = threadIdx.x; k < 64 * 64; k += blockDim.x) {
+        const int r = k / 64, c = k % 64;
+        if (sW2) sW2[r * LD64 + c] = W2[k];
+        if (sW2t) sW2t[c * LD64 + r] = W2[k];
+    }
+    for (int k = threadIdx.x; k < 16 * 64; k += blockDim.x) {
+        const int r = k / 64, c = k % 64;
+        const S v = r < 7 ? W3[r * 64 + c] : P::cvt(0.0f);
+        if (sW3) sW3[r * LD64 + c] = v;
+        if (sW3t) sW3t[c * LD16 + r] = v;
+    }
+}
+
+// D (16 x 16, rows m0.., cols = points) += W[m0..m0+15][0..K) X[p][0..K)
+template <class P, int K>
+__device__ __forceinline__ f4v layer_tile(const typename P::S* W, int ldw, int m0, const typename P::S* X, int ldx,
+                                          int lane) {
+    f4v acc = {0.f, 0.f, 0.f, 0.f};
+    const int row = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < K / P::KSTEP; ks++) {
+        const int k0 = ks * P::KSTEP + P::KPL * g;
+        acc = P::mfma(frag_k_contig<P>(W, ldw, m0 + row, k0), frag_k_contig<P>(X, ldx, row, k0), acc);
+    }
+    return acc;
+}
+
+// encode this lane's 4 levels of its point into X[p][8 g .. 8 g + 7]
+template <class P>
+__device__ __forceinline__ void encode_lane(const NtcDev& nd, const typename P::S* __restrict__ table,
+                                            const float x[3], int g, typename P::S* X, int p) {
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int lv = 4 * g + j;
+        int64_t ent[8];
+        float wt[8];
+        ntc_corners(nd, lv, x, ent, wt);
+        float e0 = 0.f, e1 = 0.f;
+#pragma unroll
+        for (int c = 0; c < 8; c++) {
+            const float2 v = load2<P>(table, ent[c]);
+            e0 += wt[c] * v.x;
+            e1 += wt[c] * v.y;
+        }
+        X[p * LD32 + 2 * lv] = P::cvt(e0);
+        X[p * LD32 + 2 * lv + 1] = P::cvt(e1);
+    }
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_ntc_fwd(NtcDev nd, const typename P::S* __restrict__ table,
+                                                 const typename P::S* __restrict__ mlp, const float* __restrict__ means,
+                                                 int64_t n, float* __restrict__ dmu, float* __restrict__ dq) {
+    using S = typename P::S;
+    __shared__ S sW1[64 * LD32], sW2[64 * LD64], sW3[16 * LD64];
+    __shared__ S sX[kWaves][kPts * LD32], sH1[kWaves][kPts * LD64], sH2[kWaves][kPts * LD64];
+    load_weights<P>(mlp, sW1, sW2, sW3, nullptr, nullptr, nullptr);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = lane & 15, g = lane >> 4;
+    S* X = sX[w];
+    S* H1 = sH1[w];
+    S* H2 = sH2[w];
+    const int64_t nb = (n + kPts - 1) / kPts;
+    for (int64_t b0 = (int64_t)blockIdx.x * kWaves; b0 < nb; b0 += (int64_t)gridDim.x * kWaves) {
+        const int64_t pt = (b0 + w) * kPts + p;
+        const bool valid = pt < n;
+        float x[3] = {0.f, 0.f, 0.f};
+        bool in = false;
+        if (valid) {
+            const float mu[3] = {means[3 * pt], means[3 * pt + 1], means[3 * pt + 2]};
+            in = ntc_normalise(nd, mu, x);
+        }
+        __syncthreads();   // weights staged / previous batch's reads of X done
+        if (in) {
+            encode_lane<P>(nd, table, x, g, X, p);
+        } else {
+            for (int j = 0; j < 8; j++) X[p * LD32 + 8 * g + j] = P::cvt(0.f);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++) {
+            const f4v a = layer_tile<P, 32>(sW1, LD32, mt * 16, X, LD32, lane);
+            for (int r = 0; r < 4; r++) H1[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(fmaxf(a[r], 0.f));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++) {
+            const f4v a = layer_tile<P, 64>(sW2, LD64, mt * 16, H1, LD64, lane);
+            for (int r = 0; r < 4; r++) H2[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(fmaxf(a[r], 0.f));
+        }
+        __syncthreads();
+        const f4v o = layer_tile<P, 64>(sW3, LD64, 0, H2, LD64, lane);
+        if (valid && g < 2) {
+            if (g == 0) {
+                dmu[3 * pt + 0] = in ? o[0] : 0.f;
+                dmu[3 * pt + 1] = in ? o[1] : 0.f;
+                dmu[3 * pt + 2] = in ? o[2] : 0.f;
+                dq[4 * pt + 0] = in ? o[3] : 1.f;
+            } else {
+                dq[4 * pt + 1] = in ? o[0] : 0.f;
+                dq[4 * pt + 2] = in ? o[1] : 0.f;
+                dq[4 * pt + 3] = in ? o[2] : 0.f;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// power of two s with max * s in [2^12, 2^13); 1 when max is 0
+__device__ __forceinline__ float pow2_scale(float mx) {
+    if (!(mx > 0.f) || !isfinite(mx)) return 1.0f;
+    int e;
+    frexpf(mx, &e);   // mx = f 2^e, f in [0.5, 1)
+    return ldexpf(1.0f, 13 - e);
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S* __restrict__ table,
+                                                 const typename P::S* __restrict__ mlp, const float* __restrict__ means,
+                                                 int64_t n, const float* __restrict__ d_dmu,
+                                                 const float* __restrict__ d_dq, float* __restrict__ g_table,
+                                                 float* __restrict__ g_part) {
+    using S = typename P::S;
+    constexpr int kWElems = 64 * LD32 + 64 * LD64 + 32 * LD64 + 64 * LD64 + 64 * LD16;
+    constexpr int kWBytes = (int)sizeof(S) * kWElems > kMlpParams * 4 ? (int)sizeof(S) * kWElems : kMlpParams * 4;
+    __shared__ __align__(16) unsigned char sWraw[kWBytes];
+    S* sW1 = reinterpret_cast<S*>(sWraw);
+    S* sW2 = sW1 + 64 * LD32;
+    S* sW1t = sW2 + 64 * LD64;
+    S* sW2t = sW1t + 32 * LD64;
+    S* sW3t = sW2t + 64 * LD64;
+    __shared__ S sX[kWaves][kPts * LD32], sH1[kWaves][kPts * LD64], sH2[kWaves][kPts * LD64];
+    __shared__ S sO[kWaves][kPts * LD16];
+    __shared__ float sE[kWaves][kPts * 33];
+    load_weights<P>(mlp, sW1, sW2, nullptr, sW1t, sW2t, sW3t);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = lane & 15, g = lane >> 4, col = lane & 15;
+    S* X = sX[w];
+    S* H1 = sH1[w];
+    S* H2 = sH2[w];
+    S* O = sO[w];
+    float* E = sE[w];
+    f4v gW1[4][2], gW2[4][4], gW3[4];
+    for (int a = 0; a < 4; a++) {
+        for (int b = 0; b < 2; b++) gW1[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < 4; b++) gW2[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
+        gW3[a] = f4v{0.f, 0.f, 0.f, 0.f};
+    }
+    const int64_t nb = (n + kPts - 1) / kPts;
+    for (int64_t b0 = (int64_t)blockIdx.x * kWaves; b0 < nb; b0 += (int64_t)gridDim.x * kWaves) {
+        const int64_t pt = (b0 + w) * kPts + p;
+        const bool valid = pt < n;
+        float x[3] = {0.f, 0.f, 0.f};
+        bool in = false;
+        if (valid) {
+            const float mu[3] = {means[3 * pt], means[3 * pt + 1], means[3 * pt + 2]};
+            in = ntc_normalise(nd, mu, x);
+        }
+        __syncthreads();
+        // 1. encoding
+        if (in) {
+            encode_lane<P>(nd, table, x, g, X, p);
+        } else {
+            for (int j = 0; j < 8; j++) X[p * LD32 + 8 * g + j] = P::cvt(0.f);
+        }
+        // output gradient (lanes of group 0 own the 7 outputs of their point)
+        float dv[4] = {0.f, 0.f, 0.f, 0.f};
+        if (in && g == 0) {
+            dv[0] = d_dmu[3 * pt];
+            dv[1] = d_dmu[3 * pt + 1];
+            dv[2] = d_dmu[3 * pt + 2];
+            dv[3] = d_dq[4 * pt];
+        } else if (in && g == 1) {
+            dv[0] = d_dq[4 * pt + 1];
+            dv[1] = d_dq[4 * pt + 2];
+            dv[2] = d_dq[4 * pt + 3];
+        }
+        float s0 = 1.0f;
+        if (P::kScaled)
+            s0 = pow2_scale(wave_max(fmaxf(fmaxf(fabsf(dv[0]), fabsf(dv[1])), fmaxf(fabsf(dv[2]), fabsf(dv[3])))));
+        for (int r = 0; r < 4; r++) O[p * LD16 + 4 * g + r] = P::cvt(dv[r] * s0);   // rows 8..15 stay zero
+        __syncthreads();
+        // 2. forward recompute
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++) {
+            const f4v a = layer_tile<P, 32>(sW1, LD32, mt * 16, X, LD32, lane);
+            for (int r = 0; r < 4; r++) H1[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(fmaxf(a[r], 0.f));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++) {
+            const f4v a = layer_tile<P, 64>(sW2, LD64, mt * 16, H1, LD64, lane);
+            for (int r = 0; r < 4; r++) H2[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(fmaxf(a[r], 0.f));
+        }
+        __syncthreads();
+        // 3. dW3[o][m] += sum_p dO[p][o] H2[p][m]
+        {
+            const float inv = 1.0f / s0;
+#pragma unroll
+            for (int nt = 0; nt < 4; nt++) {
+                f4v t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < kPts / P::KSTEP; ks++) {
+                    const int k0 = ks * P::KSTEP + P::KPL * g;
+                    t = P::mfma(frag_k_strided<P>(O, LD16, col, k0), frag_k_strided<P>(H2, LD64, nt * 16 + col, k0), t);
+                }
+                gW3[nt] += t * inv;
+            }
+        }
+        // 4. dH2 = (W3^T dO) * [H2 > 0], written over H2 (same positions)
+        f4v d2[4];
+        float m2 = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++) {
+            d2[mt] = layer_tile<P, 16>(sW3t, LD16, mt * 16, O, LD16, lane);
+            for (int r = 0; r < 4; r++) {
+                const bool on = P::tof(H2[p * LD64 + mt * 16 + 4 * g + r]) > 0.f;
+                d2[mt][r] = on ? d2[mt][r] : 0.f;
+                m2 = fmaxf(m2, fabsf(d2[mt][r]));
+            }
+        }
+        float s1 = s0;
+        if (P::kScaled) s1 = s0 * pow2_scale(wave_max(m2));
+        __syncthreads();   // all reads of H2 (step 3) done
+        {
+            const float f = s1 / s0;
+            for (int mt = 0; mt < 4; mt++)
+                for (int r = 0; r < 4; r++) H2[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(d2[mt][r] * f);
+        }
+        __syncthreads();
+        // 5. dW2[m][k] += sum_p dH2[p][m] H1[p][k]
+        {
+            const float inv = 1.0f / s1;
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+                for (int nt = 0; nt < 4; nt++) {
+                    f4v t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < kPts / P::KSTEP; ks++) {
+                        const int k0 = ks * P::KSTEP + P::KPL * g;
+                        t = P::mfma(frag_k_strided<P>(H2, LD64, mt * 16 + col, k0),
+                                    frag_k_strided<P>(H1, LD64, nt * 16 + col, k0), t);
+                    }
+                    gW2[mt][nt] += t * inv;
+                }
+        }
+        // 6. dH1 = (W2^T dH2) * [H1 > 0], written over H1
+        f4v d1[4];
+        float m1 = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++) {
+            d1[mt] = layer_tile<P, 64>(sW2t, LD64, mt * 16, H2, LD64, lane);
+            for (int r = 0; r < 4; r++) {
+                const bool on = P::tof(H1[p * LD64 + mt * 16 + 4 * g + r]) > 0.f;
+                d1[mt][r] = on ? d1[mt][r] : 0.f;
+                m1 = fmaxf(m1, fabsf(d1[mt][r]));
+            }
+        }
+        float s2 = s1;
+        if (P::kScaled) s2 = s1 * pow2_scale(wave_max(m1));
+        __syncthreads();   // all reads of H1 (step 5) done
+        {
+            const float f = s2 / s1;
+            for (int mt = 0; mt < 4; mt++)
+                for (int r = 0; r < 4; r++) H1[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(d1[mt][r] * f);
+        }
+        __syncthreads();
+        // 7. dW1[m][k] += sum_p dH1[p][m] X[p][k];  dX = W1^T dH1
+        {
+            const float inv = 1.0f / s2;
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+                for (int nt = 0; nt < 2; nt++) {
+                    f4v t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < kPts / P::KSTEP; ks++) {
+                        const int k0 = ks * P::KSTEP + P::KPL * g;
+                        t = P::mfma(frag_k_strided<P>(H1, LD64, mt * 16 + col, k0),
+                                    frag_k_strided<P>(X, LD32, nt * 16 + col, k0), t);
+                    }
+                    gW1[mt][nt] += t * inv;
+                }
+#pragma unroll
+            for (int mt = 0; mt < 2; mt++) {
+                const f4v e = layer_tile<P, 64>(sW1t, LD64, mt * 16, H1, LD64, lane);
+                for (int r = 0; r < 4; r++) E[p * 33 + mt * 16 + 4 * g + r] = e[r] * inv;
+            }
+        }
+        __syncthreads();
+        // 8. scatter-add the encoding gradient into the table gradient
+        if (in) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int lv = 4 * g + j;
+                int64_t ent[8];
+                float wt[8];
+                ntc_corners(nd, lv, x, ent, wt);
+                const float e0 = E[p * 33 + 2 * lv], e1 = E[p * 33 + 2 * lv + 1];
+#pragma unroll
+                for (int c = 0; c < 8; c++) {
+                    atomicAdd(g_table + 2 * ent[c], wt[c] * e0);
+                    atomicAdd(g_table + 2 * ent[c] + 1, wt[c] * e1);
+                }
+            }
+        }
+    }
+    // weight-gradient partials of this workgroup: the four waves add their
+    // tiles into LDS (reusing the weight area), then one coalesced row out.
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(sWraw);
+    for (int k = threadIdx.x; k < kMlpParams; k += blockDim.x) red[k] = 0.f;
+    __syncthreads();
+    for (int mt = 0; mt < 4; mt++)
+        for (int nt = 0; nt < 2; nt++)
+            for (int r = 0; r < 4; r++) atomicAdd(red + (mt * 16 + 4 * g + r) * 32 + nt * 16 + col, gW1[mt][nt][r]);
+    for (int mt = 0; mt < 4; mt++)
+        for (int nt = 0; nt < 4; nt++)
+            for (int r = 0; r < 4; r++)
+                atomicAdd(red + 64 * 32 + (mt * 16 + 4 * g + r) * 64 + nt * 16 + col, gW2[mt][nt][r]);
+    for (int nt = 0; nt < 4; nt++)
+        for (int r = 0; r < 4; r++)
+            if (4 * g + r < 7) atomicAdd(red + 64 * 32 + 64 * 64 + (4 * g + r) * 64 + nt * 16 + col, gW3[nt][r]);
+    __syncthreads();
+    float* out = g_part + (int64_t)blockIdx.x * kMlpParams;
+    for (int k = threadIdx.x; k < kMlpParams; k += blockDim.x) out[k] = red[k];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ part, int nparts, int len,
+                                                      float* __restrict__ dst) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= len) return;
+    float s = 0.f;
+    for (int b = 0; b < nparts; b++) s += part[(int64_t)b * len + k];
+    dst[k] += s;
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_ntc_adam(float* __restrict__ p, float* __restrict__ gr, float* __restrict__ m,
+                                                  float* __restrict__ v, typename P::S* __restrict__ work, int64_t n,
+                                                  float lr, float b1, float b2, float eps, float bc1, float bc2) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float g = gr[i];
+    const float mi = b1 * m[i] + (1.f - b1) * g;
+    const float vi = b2 * v[i] + (1.f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    p[i] = pi;
+    gr[i] = 0.f;
+    if (work) work[i] = P::cvt(pi);
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_to_work(const float* __restrict__ p, typename P::S* __restrict__ work,
+                                                 int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) work[i] = P::cvt(p[i]);
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ gr,
+                                              float* __restrict__ m, float* __restrict__ v, int64_t n, float lr,
+                                              float b1, float b2, float eps, float bc1, float bc2) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float g = gr[i];
+    const float mi = b1 * m[i] + (1.f - b1) * g;
+    const float vi = b2 * v[i] + (1.f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// Eq. 7 per point, plus per-block partial sums of the loss
+__global__ __launch_bounds__(256) void k_warmup(const float* __restrict__ dmu, const float* __restrict__ dq, int64_t n,
+                                                float* __restrict__ gmu, float* __restrict__ gq,
+                                                double* __restrict__ bsum) {
+    __shared__ double s[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double L = 0.0;
+    if (i < n) {
+        const float invn = 1.0f / (float)n;
+        float a = 0.f;
+        for (int k = 0; k < 3; k++) {
+            const float d = dmu[3 * i + k];
+            a += fabsf(d);
+            gmu[3 * i + k] = (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f)) * invn;
+        }
+        const float w = dq[4 * i], x = dq[4 * i + 1], y = dq[4 * i + 2], z = dq[4 * i + 3];
+        const float n2 = w * w + x * x + y * y + z * z;
+        float c2 = 0.f;
+        if (n2 > 0.f) {
+            c2 = w * w / n2;
+            const float i4 = 1.0f / (n2 * n2);
+            gq[4 * i] = -(2.f * w * (n2 - w * w) * i4) * invn;
+            gq[4 * i + 1] = (2.f * w * w * x * i4) * invn;
+            gq[4 * i + 2] = (2.f * w * w * y * i4) * invn;
+            gq[4 * i + 3] = (2.f * w * w * z * i4) * invn;
+        } else {
+            for (int k = 0; k < 4; k++) gq[4 * i + k] = 0.f;
+        }
+        L = (double)a - (double)c2;
+    }
+    for (int off = 32; off > 0; off >>= 1) L += __shfl_xor(L, off, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = L;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+__global__ __launch_bounds__(256) void k_warmup_finalize(const double* __restrict__ bsum, int64_t nb, int64_t n,
+                                                         float* __restrict__ loss) {
+    __shared__ double s[4];
+    double a = 0.0;
+    for (int64_t k = threadIdx.x; k < nb; k += 256) a += bsum[k];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) loss[0] = (float)((s[0] + s[1] + s[2] + s[3]) / (double)n);
+}
+
+inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+template <class P>
+void fwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* mlp, const float* means, int64_t n,
+              float* dmu, float* dq) {
+    const int64_t nb = (n + kPts - 1) / kPts;
+    const unsigned grid = (unsigned)std::min<int64_t>((nb + kWaves - 1) / kWaves, 2048);
+    hipLaunchKernelGGL((k_ntc_fwd<P>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
+                       (const typename P::S*)mlp, means, n, dmu, dq);
+}
+
+template <class P>
+void bwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* mlp, const float* means, int64_t n,
+              const float* d_dmu, const float* d_dq, float* g_table, float* g_mlp, float* g_part, int max_parts) {
+    const int64_t nb = (n + kPts - 1) / kPts;
+    const unsigned grid = (unsigned)std::min<int64_t>((nb + kWaves - 1) / kWaves, max_parts);
+    hipLaunchKernelGGL((k_ntc_bwd<P>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
+                       (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(kMlpParams, 256)), dim3(256), 0, L.st, g_part, (int)grid, kMlpParams,
+                       g_mlp);
+}
+
+}  // namespace
+
+int ntc_mlp_params() { return kMlpParams; }
+
+void ntc_forward(const Launch& L, int precision, const NtcDev& nd, const void* table, const void* mlp,
+                 const float* means, int64_t n, float* dmu, float* dq) {
+    if (n <= 0) return;
+    if (L.prof) L.prof->begin("ntc_fwd", L.st);
+    if (precision == 1)
+        fwd_impl<PF16>(L, nd, table, mlp, means, n, dmu, dq);
+    else if (precision == 2)
+        fwd_impl<PBF16>(L, nd, table, mlp, means, n, dmu, dq);
+    else
+        fwd_impl<PF32>(L, nd, table, mlp, means, n, dmu, dq);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void ntc_backward(const Launch& L, int precision, const NtcDev& nd, const void* table, const void* mlp,
+                  const float* means, int64_t n, const float* d_dmu, const float* d_dq, float* g_table, float* g_mlp,
+                  float* g_part, int max_parts) {
+    if (n <= 0) return;
+    if (L.prof) L.prof->begin("ntc_bwd", L.st);
+    if (precision == 1)
+        bwd_impl<PF16>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts);
+    else if (precision == 2)
+        bwd_impl<PBF16>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts);
+    else
+        bwd_impl<PF32>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void ntc_adam(const Launch& L, int precision, float* p, float* g, float* m, float* v, void* work, int64_t n, float lr,
+              float b1, float b2, float eps, float bc1, float bc2) {
+    if (L.prof) L.prof->begin("ntc_adam", L.st);
+    if (precision == 1)
+        hipLaunchKernelGGL((k_ntc_adam<PF16>), dim3(nblk(n, 256)), dim3(256), 0, L.st, p, g, m, v, (_Float16*)work, n,
+                           lr, b1, b2, eps, bc1, bc2);
+    else if (precision == 2)
+        hipLaunchKernelGGL((k_ntc_adam<PBF16>), dim3(nblk(n, 256)), dim3(256), 0, L.st, p, g, m, v, (__bf16*)work, n,
+                           lr, b1, b2, eps, bc1, bc2);
+    else
+        hipLaunchKernelGGL((k_ntc_adam<PF32>), dim3(nblk(n, 256)), dim3(256), 0, L.st, p, g, m, v, (float*)nullptr, n,
+                           lr, b1, b2, eps, bc1, bc2);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void ntc_refresh_work(const Launch& L, int precision, const float* p, void* work, int64_t n) {
+    if (precision == 1)
+        hipLaunchKernelGGL((k_to_work<PF16>), dim3(nblk(n, 256)), dim3(256), 0, L.st, p, (_Float16*)work, n);
+    else if (precision == 2)
+        hipLaunchKernelGGL((k_to_work<PBF16>), dim3(nblk(n, 256)), dim3(256), 0, L.st, p, (__bf16*)work, n);
+}
+
+void adam(const Launch& L, float* p, const float* g, float* m, float* v, int64_t n, int step, float lr, float b1,
+          float b2, float eps) {
+    if (n <= 0) return;
+    const float bc1 = (float)(1.0 - pow((double)b1, (double)step));
+    const float bc2 = (float)(1.0 - pow((double)b2, (double)step));
+    if (L.prof) L.prof->begin("adam", L.st);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(n, 256)), dim3(256), 0, L.st, p, g, m, v, n, lr, b1, b2, eps, bc1, bc2);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void warmup_loss(const Launch& L, const float* dmu, const float* dq, int64_t n, float* loss, float* gmu, float* gq,
+                 double* bsum) {
+    if (n <= 0) return;
+    if (L.prof) L.prof->begin("warmup_loss", L.st);
+    const unsigned nb = nblk(n, 256);
+    hipLaunchKernelGGL(k_warmup, dim3(nb), dim3(256), 0, L.st, dmu, dq, n, gmu, gq, bsum);
+    hipLaunchKernelGGL(k_warmup_finalize, dim3(1), dim3(256), 0, L.st, bsum, (int64_t)nb, n, loss);
+    if (L.prof) L.prof->end(L.st);
+}
+
+}  // namespace gs3

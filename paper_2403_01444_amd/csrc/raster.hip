@@ -1,0 +1,649 @@
+// Tile rasterizer of 3D Gaussians for gfx950 (Sec. 3.2: Eq. 2-4), forward
+// and adjoint, plus the Gaussian transform of Sec. 4.1 fused into the
+// per-Gaussian kernels.
+#include "kernels.h"
+
+namespace gs3 {
+
+namespace {
+
+__device__ __forceinline__ uint32_t pack16(int lo, int hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+
+// ---------------------------------------------------------------------------
+// preprocess: transform, covariance (Eq. 2), EWA projection (Eq. 3), conic,
+// pixel box, tile rectangle, depth key, SH colour, tile count.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_preprocess(GaussDev g, CamDev cam, float4* __restrict__ rec,
+                                                    uint32_t* __restrict__ key, uint2* __restrict__ rect,
+                                                    uint32_t* __restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.n) return;
+    Geo o;
+    if (!geo_forward(g, cam, i, o)) {
+        key[i] = 0xFFFFFFFFu;
+        count[i] = 0;
+        rect[i] = make_uint2(1u, 0u);
+        rec[3 * i + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
+        rec[3 * i + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        rec[3 * i + 2] = make_float4(0.f, __uint_as_float(pack16(1, 1)), __uint_as_float(0u), 0.f);
+        return;
+    }
+    ColourCtx cc;
+    colour_forward(g, cam, i, o, cc);
+    const float A = o.c / o.det, B = -o.b / o.det, C = o.a / o.det;
+    const float op = 1.0f / (1.0f + __expf(-g.opac[i]));
+    rec[3 * i + 0] = make_float4(o.u, o.v, A, B);
+    rec[3 * i + 1] = make_float4(C, op, fmaxf(cc.raw[0], 0.f), fmaxf(cc.raw[1], 0.f));
+    rec[3 * i + 2] = make_float4(fmaxf(cc.raw[2], 0.f), __uint_as_float(pack16(o.x0, o.y0)),
+                                 __uint_as_float(pack16(o.x1, o.y1)), 0.f);
+    const int tx0 = o.x0 / kTile, ty0 = o.y0 / kTile, tx1 = o.x1 / kTile, ty1 = o.y1 / kTile;
+    rect[i] = make_uint2(pack16(tx0, ty0), pack16(tx1, ty1));
+    count[i] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    key[i] = __float_as_uint(o.t[2]);
+}
+
+// ---------------------------------------------------------------------------
+// radix64 ordering: one (tile << 32 | depth bits, index) pair per covered
+// tile, in Gaussian order, then a 64-bit LSD sort and a boundary scan.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_emit(int64_t n, const uint32_t* __restrict__ key,
+                                              const uint2* __restrict__ rect, const uint64_t* __restrict__ offs,
+                                              int tiles_x, uint64_t cap, uint64_t* __restrict__ keys,
+                                              uint32_t* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = key[i];
+    if (k == 0xFFFFFFFFu) return;
+    const uint2 r = rect[i];
+    const int tx0 = r.x & 0xFFFF, ty0 = r.x >> 16, tx1 = r.y & 0xFFFF, ty1 = r.y >> 16;
+    uint64_t off = offs[i];
+    for (int ty = ty0; ty <= ty1; ty++)
+        for (int tx = tx0; tx <= tx1; tx++) {
+            if (off < cap) {
+                keys[off] = ((uint64_t)(ty * tiles_x + tx) << 32) | k;
+                vals[off] = (uint32_t)i;
+            }
+            off++;
+        }
+}
+
+__global__ __launch_bounds__(256) void k_zero_ranges(uint2* ranges, int ntiles) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < ntiles) ranges[t] = make_uint2(0u, 0u);
+}
+
+__global__ __launch_bounds__(256) void k_ranges_from_keys(const uint64_t* __restrict__ keys, int64_t K,
+                                                          uint2* __restrict__ ranges) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= K) return;
+    const uint32_t t = (uint32_t)(keys[k] >> 32);
+    if (k == 0 || (uint32_t)(keys[k - 1] >> 32) != t) ranges[t].x = (uint32_t)k;
+    if (k == K - 1 || (uint32_t)(keys[k + 1] >> 32) != t) ranges[t].y = (uint32_t)(k + 1);
+}
+
+// ---------------------------------------------------------------------------
+// depth-first ordering.  The Gaussians are first sorted by (depth bits,
+// index).  The sorted sequence is cut into chunks of kBinChunk; one wave per
+// chunk walks its Gaussians in order and, for each, the tiles of its
+// rectangle (one tile per lane; the tiles of one Gaussian are distinct, so
+// the lanes never collide).  Pass 1 counts pairs per (tile, chunk); an
+// exclusive scan in tile-major order gives each (tile, chunk) its first
+// slot; pass 2 repeats the walk and writes Gaussian indices at consecutive
+// slots.  Inside a tile the result is ordered by (chunk, position in chunk),
+// i.e. by (depth bits, index): the order a stable (tile, depth) sort gives.
+// ---------------------------------------------------------------------------
+template <bool kScatter>
+__global__ __launch_bounds__(64) void k_bin(const uint32_t* __restrict__ order, int64_t n,
+                                            const uint2* __restrict__ rect, const uint32_t* __restrict__ count,
+                                            int tiles_x, int ntiles, int64_t nchunks, uint32_t* __restrict__ hist,
+                                            const uint64_t* __restrict__ base, uint32_t cap,
+                                            uint32_t* __restrict__ vals) {
+    // ntiles counters (count pass) or write cursors (scatter pass).  A cursor
+    // starts at min(first slot, cap) and moves at most kBinChunk past it, so
+    // with cap < 2^31 it never wraps; slots at or past cap are not written.
+    extern __shared__ uint32_t s_cur[];
+    const int lane = threadIdx.x;
+    const int64_t chunk = blockIdx.x;
+    for (int t = lane; t < ntiles; t += 64) {
+        if (kScatter) {
+            const uint64_t b = base[(int64_t)t * nchunks + chunk];
+            s_cur[t] = b < (uint64_t)cap ? (uint32_t)b : cap;
+        } else {
+            s_cur[t] = 0;
+        }
+    }
+    __syncthreads();
+    const int64_t e0 = chunk * kBinChunk;
+    const int64_t e1 = min(e0 + (int64_t)kBinChunk, n);
+    for (int64_t eb = e0; eb < e1; eb += 64) {
+        // fetch 64 Gaussians of the chunk at once, then walk them in order
+        const int64_t e = eb + lane;
+        uint32_t id = 0, cnt = 0;
+        uint2 r = make_uint2(0u, 0u);
+        if (e < e1) {
+            id = order[e];
+            cnt = count[id];
+            if (cnt) r = rect[id];
+        }
+        const int m = (int)min((int64_t)64, e1 - eb);
+        for (int j = 0; j < m; j++) {
+            const uint32_t cj = __shfl(cnt, j, 64);
+            if (cj == 0) continue;
+            const uint32_t rx = __shfl(r.x, j, 64), ry = __shfl(r.y, j, 64);
+            const uint32_t idj = __shfl(id, j, 64);
+            const int tx0 = rx & 0xFFFF, ty0 = rx >> 16, tx1 = ry & 0xFFFF;
+            const int w = tx1 - tx0 + 1;
+            for (uint32_t k = lane; k < cj; k += 64) {
+                const int t = (ty0 + (int)k / w) * tiles_x + tx0 + (int)k % w;
+                const uint32_t pos = s_cur[t];
+                s_cur[t] = pos + 1u;
+                if (kScatter && pos < cap) vals[pos] = idj;
+            }
+        }
+    }
+    if (!kScatter) {
+        __syncthreads();
+        for (int t = lane; t < ntiles; t += 64) hist[(int64_t)t * nchunks + chunk] = s_cur[t];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ranges_from_hist(const uint64_t* __restrict__ base,
+                                                          const uint64_t* __restrict__ total, int ntiles,
+                                                          int64_t nchunks, uint64_t cap, uint2* __restrict__ ranges,
+                                                          int* __restrict__ overflow) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const uint64_t K = *total;
+    if (t == 0 && K > cap) atomicOr(overflow, 1);
+    if (t >= ntiles) return;
+    uint64_t s = base[(int64_t)t * nchunks];
+    uint64_t e = t + 1 < ntiles ? base[(int64_t)(t + 1) * nchunks] : K;
+    s = s < cap ? s : cap;
+    e = e < cap ? e : cap;
+    ranges[t] = make_uint2((uint32_t)s, (uint32_t)e);
+}
+
+__global__ void k_total_check(const uint64_t* total, uint64_t cap, int* overflow) {
+    if (threadIdx.x == 0 && *total > cap) atomicOr(overflow, 1);
+}
+
+// XCD-aware tile order: consecutive workgroups are dealt round-robin to the
+// eight XCDs, so give each XCD a contiguous band of tiles (neighbouring tiles
+// share most of their Gaussians and hit the same L2).
+__device__ __forceinline__ int tile_of_block(int b, int ntiles) {
+    const int per = (ntiles + 7) / 8;
+    const int xcd = b & 7, k = b >> 3;
+    const int t = xcd * per + k;
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// blend forward (Eq. 4): one workgroup per 16x16 tile, one thread per pixel;
+// the tile's Gaussian records are staged through LDS 256 at a time.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlendThreads) void k_blend_fwd(CamDev cam, int ntiles, const uint2* __restrict__ ranges,
+                                                              const uint32_t* __restrict__ vals,
+                                                              const float4* __restrict__ rec, float* __restrict__ image,
+                                                              float* __restrict__ T_final, uint32_t* __restrict__ last_out) {
+    __shared__ float4 s_w0[kBlendThreads];
+    __shared__ float4 s_w1[kBlendThreads];
+    __shared__ float4 s_w2[kBlendThreads];
+    const int tile = tile_of_block(blockIdx.x, ntiles);
+    if (tile >= ntiles) return;
+    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+    const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+    const bool inside = px < cam.W && py < cam.H;
+    const uint2 rg = ranges[tile];
+    const uint32_t start = rg.x, end = rg.y;
+    const float fpx = (float)px, fpy = (float)py;
+    float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    uint32_t last = 0;
+    bool done = !inside;
+    for (uint32_t b = start; b < end; b += kBlendThreads) {
+        if (__syncthreads_count(done) == kBlendThreads) break;
+        const uint32_t e = b + threadIdx.x;
+        if (e < end) {
+            const uint32_t id = vals[e];
+            s_w0[threadIdx.x] = rec[3 * (int64_t)id + 0];
+            s_w1[threadIdx.x] = rec[3 * (int64_t)id + 1];
+            s_w2[threadIdx.x] = rec[3 * (int64_t)id + 2];
+        }
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)kBlendThreads, end - b);
+        if (!done) {
+            for (int j = 0; j < cnt; j++) {
+                const float4 w2 = s_w2[j];
+                if (!box_contains(__float_as_uint(w2.y), __float_as_uint(w2.z), px, py)) continue;
+                const float4 w0 = s_w0[j], w1 = s_w1[j];
+                float dx, dy, G, raw, alpha;
+                if (!blend_alpha(fpx, fpy, w0, w1, dx, dy, G, raw, alpha)) continue;
+                const float Tn = T * (1.0f - alpha);
+                if (Tn < 1e-4f) {
+                    done = true;
+                    break;
+                }
+                const float wgt = alpha * T;
+                c0 += wgt * w1.z;
+                c1 += wgt * w1.w;
+                c2 += wgt * w2.x;
+                T = Tn;
+                last = b - start + (uint32_t)j + 1u;
+            }
+        }
+    }
+    if (inside) {
+        const int64_t p = (int64_t)py * cam.W + px, P = (int64_t)cam.W * cam.H;
+        image[p] = c0 + T * cam.bg[0];
+        image[P + p] = c1 + T * cam.bg[1];
+        image[2 * P + p] = c2 + T * cam.bg[2];
+        T_final[p] = T;
+        last_out[p] = last;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// blend backward: walk the tile list from the last contributor of any pixel
+// down to the first, recover T_i = T_{i+1} / (1 - alpha_i), keep the colour
+// accumulated behind each contributor, and reduce each Gaussian's nine
+// gradient terms across the wave (then the four waves in LDS) before one
+// global atomic per term and tile.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(CamDev cam, int ntiles, const uint2* __restrict__ ranges,
+                                                              const uint32_t* __restrict__ vals,
+                                                              const float4* __restrict__ rec,
+                                                              const float* __restrict__ d_image,
+                                                              const float* __restrict__ T_final,
+                                                              const uint32_t* __restrict__ last_in,
+                                                              float* __restrict__ accum) {
+    __shared__ float4 s_w0[kBlendThreads];
+    __shared__ float4 s_w1[kBlendThreads];
+    __shared__ float4 s_w2[kBlendThreads];
+    __shared__ uint32_t s_id[kBlendThreads];
+    __shared__ float s_g[kBlendThreads][10];
+    __shared__ uint32_t s_max;
+    const int tile = tile_of_block(blockIdx.x, ntiles);
+    if (tile >= ntiles) return;
+    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+    const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+    const bool inside = px < cam.W && py < cam.H;
+    const uint2 rg = ranges[tile];
+    const uint32_t start = rg.x;
+    const int64_t p = (int64_t)py * cam.W + px, P = (int64_t)cam.W * cam.H;
+    float T = 1.0f;
+    uint32_t last = 0;
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    if (inside) {
+        T = T_final[p];
+        last = last_in[p];
+        g0 = d_image[p];
+        g1 = d_image[P + p];
+        g2 = d_image[2 * P + p];
+    }
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    if (last) atomicMax(&s_max, last);
+    for (int k = threadIdx.x; k < kBlendThreads * 10; k += kBlendThreads) (&s_g[0][0])[k] = 0.f;
+    __syncthreads();
+    const uint32_t maxlast = s_max;
+    const float fpx = (float)px, fpy = (float)py;
+    float b0 = cam.bg[0], b1 = cam.bg[1], b2 = cam.bg[2];   // colour behind the current contributor
+    const int lane = threadIdx.x & 63;
+    if (maxlast == 0) return;
+    for (int64_t jb = ((int64_t)(maxlast - 1) / kBlendThreads) * kBlendThreads; jb >= 0; jb -= kBlendThreads) {
+        const uint32_t e = (uint32_t)jb + threadIdx.x;
+        if (e < maxlast) {
+            const uint32_t id = vals[start + e];
+            s_id[threadIdx.x] = id;
+            s_w0[threadIdx.x] = rec[3 * (int64_t)id + 0];
+            s_w1[threadIdx.x] = rec[3 * (int64_t)id + 1];
+            s_w2[threadIdx.x] = rec[3 * (int64_t)id + 2];
+        }
+        __syncthreads();
+        const int cnt = (int)min((int64_t)kBlendThreads, (int64_t)maxlast - jb);
+        for (int j = cnt - 1; j >= 0; j--) {
+            const uint32_t ej = (uint32_t)jb + (uint32_t)j;
+            float gr[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            bool act = false;
+            if (ej < last) {
+                const float4 w2 = s_w2[j];
+                if (box_contains(__float_as_uint(w2.y), __float_as_uint(w2.z), px, py)) {
+                    const float4 w0 = s_w0[j], w1 = s_w1[j];
+                    float dx, dy, G, raw, alpha;
+                    if (blend_alpha(fpx, fpy, w0, w1, dx, dy, G, raw, alpha)) {
+                        act = true;
+                        T = T / (1.0f - alpha);
+                        const float wgt = alpha * T;
+                        const float cr = w1.z, cg = w1.w, cb = w2.x;
+                        gr[6] = g0 * wgt;
+                        gr[7] = g1 * wgt;
+                        gr[8] = g2 * wgt;
+                        const float dal = T * (g0 * (cr - b0) + g1 * (cg - b1) + g2 * (cb - b2));
+                        b0 = alpha * cr + (1.0f - alpha) * b0;
+                        b1 = alpha * cg + (1.0f - alpha) * b1;
+                        b2 = alpha * cb + (1.0f - alpha) * b2;
+                        if (raw < 0.99f) {
+                            gr[5] = dal * G;
+                            const float dp = dal * raw;
+                            gr[0] = dp * (w0.z * dx + w0.w * dy);
+                            gr[1] = dp * (w0.w * dx + w1.x * dy);
+                            gr[2] = dp * (-0.5f * dx * dx);
+                            gr[3] = dp * (-dx * dy);
+                            gr[4] = dp * (-0.5f * dy * dy);
+                        }
+                    }
+                }
+            }
+            if (__any(act)) {
+#pragma unroll
+                for (int k = 0; k < 9; k++) gr[k] = wave_sum(gr[k]);
+                if (lane == 0) {
+#pragma unroll
+                    for (int k = 0; k < 9; k++) atomicAdd(&s_g[j][k], gr[k]);
+                    s_g[j][9] = 1.0f;
+                }
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < cnt && s_g[threadIdx.x][9] != 0.f) {
+            float* a = accum + 9 * (int64_t)s_id[threadIdx.x];
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                const float v = s_g[threadIdx.x][k];
+                if (v != 0.f) atomicAdd(a + k, v);
+                s_g[threadIdx.x][k] = 0.f;
+            }
+            s_g[threadIdx.x][9] = 0.f;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void quat_rot_adj(const float q[4], const float g[9], float d[4]) {
+    const float w = q[0], x = q[1], y = q[2], z = q[3];
+    d[0] += 2.f * (-z * g[1] + y * g[2] + z * g[3] - x * g[5] - y * g[6] + x * g[7]);
+    d[1] += 2.f * (y * g[1] + z * g[2] + y * g[3] - 2.f * x * g[4] - w * g[5] + z * g[6] + w * g[7] - 2.f * x * g[8]);
+    d[2] += 2.f * (-2.f * y * g[0] + x * g[1] + w * g[2] + x * g[3] + z * g[5] - w * g[6] + z * g[7] - 2.f * y * g[8]);
+    d[3] += 2.f * (-2.f * z * g[0] - w * g[1] + x * g[2] + w * g[3] - 2.f * z * g[4] + y * g[5] + x * g[6] + y * g[7]);
+}
+
+// ---------------------------------------------------------------------------
+// preprocess backward: chain the per-Gaussian 2D gradients through the conic
+// inverse, EWA (with J depending on the camera-space mean), the covariance,
+// the colour (SH and its view direction) and the transform.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_preprocess_bwd(GaussDev g, CamDev cam, const float* __restrict__ accum,
+                                                        GradsDev out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.n) return;
+    Geo o;
+    if (!geo_forward(g, cam, i, o)) return;
+    ColourCtx cc;
+    colour_forward(g, cam, i, o, cc);
+    const float* a9 = accum + 9 * i;
+    const float du = a9[0], dv = a9[1], dA = a9[2], dB = a9[3], dC = a9[4], dop = a9[5];
+    const float drgb[3] = {a9[6], a9[7], a9[8]};
+    if (out.d_uv) { out.d_uv[2 * i] += du; out.d_uv[2 * i + 1] += dv; }
+    if (out.d_conic) { out.d_conic[3 * i] += dA; out.d_conic[3 * i + 1] += dB; out.d_conic[3 * i + 2] += dC; }
+    if (out.d_opacity) out.d_opacity[i] += dop;
+    if (out.d_rgb) for (int k = 0; k < 3; k++) out.d_rgb[3 * i + k] += drgb[k];
+    if (out.d_opac) {
+        const float op = 1.0f / (1.0f + __expf(-g.opac[i]));
+        out.d_opac[i] += dop * op * (1.0f - op);
+    }
+    float dm[3] = {0.f, 0.f, 0.f};
+    float dRp[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float dRh[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+
+    // colour
+    float gch[3];
+    for (int k = 0; k < 3; k++) gch[k] = cc.raw[k] > 0.f ? drgb[k] : 0.f;
+    const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+    const float* sh = g.sh + i * (int64_t)K * 3;
+    float wk[16];
+    {
+        float Y[16];
+        sh_basis(g.sh_degree, cc.dl[0], cc.dl[1], cc.dl[2], Y);
+        for (int k = 0; k < K; k++) {
+            wk[k] = gch[0] * sh[3 * k] + gch[1] * sh[3 * k + 1] + gch[2] * sh[3 * k + 2];
+            if (out.d_sh) {
+                float* ds = out.d_sh + i * (int64_t)K * 3 + 3 * k;
+                ds[0] += gch[0] * Y[k];
+                ds[1] += gch[1] * Y[k];
+                ds[2] += gch[2] * Y[k];
+            }
+        }
+    }
+    float gdl[3];
+    sh_grad(g.sh_degree, cc.dl[0], cc.dl[1], cc.dl[2], wk, gdl[0], gdl[1], gdl[2]);
+    float ddir[3];
+    if (g.dq) {
+        for (int k = 0; k < 3; k++) ddir[k] = cc.Ml[k] * gdl[0] + cc.Ml[3 + k] * gdl[1] + cc.Ml[6 + k] * gdl[2];
+        // Ml = Rh Rp^T, dMl = gdl dir^T:  dRh = dMl Rp, dRp = dMl^T Rh
+        for (int r = 0; r < 3; r++)
+            for (int k = 0; k < 3; k++) {
+                dRh[3 * r + k] += gdl[r] * (cc.dir[0] * o.Rp[k] + cc.dir[1] * o.Rp[3 + k] + cc.dir[2] * o.Rp[6 + k]);
+                dRp[3 * r + k] += cc.dir[r] * (gdl[0] * cc.Rh[k] + gdl[1] * cc.Rh[3 + k] + gdl[2] * cc.Rh[6 + k]);
+            }
+    } else {
+        ddir[0] = gdl[0]; ddir[1] = gdl[1]; ddir[2] = gdl[2];
+    }
+    {
+        const float pd = ddir[0] * cc.dir[0] + ddir[1] * cc.dir[1] + ddir[2] * cc.dir[2];
+        for (int k = 0; k < 3; k++) dm[k] += (ddir[k] - cc.dir[k] * pd) / cc.wn;
+    }
+
+    // conic (A, B, C) = (c, -b, a) / det
+    const float a = o.a, b = o.b, c = o.c, det = o.det, id2 = 1.0f / (det * det), idt = 1.0f / det;
+    const float da = dA * (-c * c * id2) + dB * (b * c * id2) + dC * (idt - a * c * id2);
+    const float db = dA * (2.f * b * c * id2) + dB * (-idt - 2.f * b * b * id2) + dC * (2.f * a * b * id2);
+    const float dc = dA * (idt - a * c * id2) + dB * (a * b * id2) + dC * (-a * a * id2);
+    // Sigma2 = T Sigma T^T: G2 = [[da, db/2], [db/2, dc]]
+    const float G00 = da, G01 = 0.5f * db, G11 = dc;
+    const float T0[3] = {o.T00, o.T01, o.T02}, T1[3] = {o.T10, o.T11, o.T12};
+    const float S[9] = {o.S00, o.S01, o.S02, o.S01, o.S11, o.S12, o.S02, o.S12, o.S22};
+    float dS[9];
+    for (int p = 0; p < 3; p++)
+        for (int q = 0; q < 3; q++)
+            dS[3 * p + q] = T0[p] * (G00 * T0[q] + G01 * T1[q]) + T1[p] * (G01 * T0[q] + G11 * T1[q]);
+    // dT = 2 G2 T Sigma
+    float TS0[3], TS1[3];
+    for (int q = 0; q < 3; q++) {
+        TS0[q] = T0[0] * S[q] + T0[1] * S[3 + q] + T0[2] * S[6 + q];
+        TS1[q] = T1[0] * S[q] + T1[1] * S[3 + q] + T1[2] * S[6 + q];
+    }
+    float dT0[3], dT1[3];
+    for (int q = 0; q < 3; q++) {
+        dT0[q] = 2.f * (G00 * TS0[q] + G01 * TS1[q]);
+        dT1[q] = 2.f * (G01 * TS0[q] + G11 * TS1[q]);
+    }
+    const float* R = cam.R;
+    const float dj00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
+    const float dj02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
+    const float dj11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
+    const float dj12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
+    const float tx = o.t[0], ty = o.t[1], tz = o.t[2], itz = 1.0f / tz, itz2 = itz * itz;
+    const float fx = cam.fx, fy = cam.fy;
+    float dtx = 0.f, dty = 0.f, dtz = 0.f;
+    dtz += dj00 * (-fx * itz2) + dj11 * (-fy * itz2) + dj02 * (fx * o.txc * itz2) + dj12 * (fy * o.tyc * itz2);
+    const float dtxc = dj02 * (-fx * itz), dtyc = dj12 * (-fy * itz);
+    if (!o.clx) { dtx += dtxc * itz; dtz += -dtxc * tx * itz2; }
+    if (!o.cly) { dty += dtyc * itz; dtz += -dtyc * ty * itz2; }
+    dtx += du * fx * itz;
+    dty += dv * fy * itz;
+    dtz += -du * fx * tx * itz2 - dv * fy * ty * itz2;
+    for (int k = 0; k < 3; k++) dm[k] += R[k] * dtx + R[3 + k] * dty + R[6 + k] * dtz;
+
+    // Sigma = M M^T with M = Rp diag(s): dM = 2 dS M
+    float M[9];
+    for (int r = 0; r < 3; r++)
+        for (int k = 0; k < 3; k++) M[3 * r + k] = o.Rp[3 * r + k] * o.s[k];
+    float ds[3] = {0.f, 0.f, 0.f};
+    for (int r = 0; r < 3; r++)
+        for (int k = 0; k < 3; k++) {
+            const float dMrk = 2.f * (dS[3 * r] * M[k] + dS[3 * r + 1] * M[3 + k] + dS[3 * r + 2] * M[6 + k]);
+            dRp[3 * r + k] += dMrk * o.s[k];
+            ds[k] += dMrk * o.Rp[3 * r + k];
+        }
+    if (out.d_log_scales)
+        for (int k = 0; k < 3; k++) out.d_log_scales[3 * i + k] += ds[k] * o.s[k];
+
+    // rotations -> quaternions
+    float dqp[4] = {0.f, 0.f, 0.f, 0.f}, dqh[4] = {0.f, 0.f, 0.f, 0.f};
+    quat_rot_adj(o.qp, dRp, dqp);
+    if (g.dq) {
+        quat_rot_adj(o.qh, dRh, dqh);
+        const float bw = o.dh[0], bx = o.dh[1], by = o.dh[2], bz = o.dh[3];
+        const float aw = o.qh[0], ax = o.qh[1], ay = o.qh[2], az = o.qh[3];
+        // q' = qh (x) dh; gradient with respect to qh is Rb^T dqp, to dh is La^T dqp
+        dqh[0] += bw * dqp[0] + bx * dqp[1] + by * dqp[2] + bz * dqp[3];
+        dqh[1] += -bx * dqp[0] + bw * dqp[1] - bz * dqp[2] + by * dqp[3];
+        dqh[2] += -by * dqp[0] + bz * dqp[1] + bw * dqp[2] - bx * dqp[3];
+        dqh[3] += -bz * dqp[0] - by * dqp[1] + bx * dqp[2] + bw * dqp[3];
+        float ddh[4];
+        ddh[0] = aw * dqp[0] + ax * dqp[1] + ay * dqp[2] + az * dqp[3];
+        ddh[1] = -ax * dqp[0] + aw * dqp[1] + az * dqp[2] - ay * dqp[3];
+        ddh[2] = -ay * dqp[0] - az * dqp[1] + aw * dqp[2] + ax * dqp[3];
+        ddh[3] = -az * dqp[0] + ay * dqp[1] - ax * dqp[2] + aw * dqp[3];
+        if (out.d_dq) {
+            const float pd = o.dh[0] * ddh[0] + o.dh[1] * ddh[1] + o.dh[2] * ddh[2] + o.dh[3] * ddh[3];
+            const bool nz = o.dn > 1e-12f;
+            for (int k = 0; k < 4; k++)
+                out.d_dq[4 * i + k] += nz ? (ddh[k] - o.dh[k] * pd) / o.dn : ddh[k] / o.dn;
+        }
+    } else {
+        for (int k = 0; k < 4; k++) dqh[k] += dqp[k];
+    }
+    if (out.d_quats && o.qn > 0.f) {
+        const float pd = o.qh[0] * dqh[0] + o.qh[1] * dqh[1] + o.qh[2] * dqh[2] + o.qh[3] * dqh[3];
+        for (int k = 0; k < 4; k++) out.d_quats[4 * i + k] += (dqh[k] - o.qh[k] * pd) / o.qn;
+    }
+    for (int k = 0; k < 3; k++) {
+        if (out.d_means) out.d_means[3 * i + k] += dm[k];
+        if (out.d_dmu) out.d_dmu[3 * i + k] += dm[k];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_debug_keys(const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+                                                    const uint32_t* __restrict__ key, int ntiles,
+                                                    uint64_t* __restrict__ keys_out) {
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const uint2 r = ranges[t];
+    for (uint32_t e = r.x + threadIdx.x; e < r.y; e += 256) keys_out[e] = ((uint64_t)t << 32) | key[vals[e]];
+}
+
+__global__ __launch_bounds__(256) void k_debug_records(int64_t n, const float4* __restrict__ rec,
+                                                       int32_t* __restrict__ box, float* __restrict__ rec9) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float4 a = rec[3 * i], b = rec[3 * i + 1], c = rec[3 * i + 2];
+    if (box) {
+        const uint32_t b0 = __float_as_uint(c.y), b1 = __float_as_uint(c.z);
+        box[4 * i + 0] = b0 & 0xFFFF; box[4 * i + 1] = b0 >> 16;
+        box[4 * i + 2] = b1 & 0xFFFF; box[4 * i + 3] = b1 >> 16;
+    }
+    if (rec9) {
+        float v[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x};
+        for (int k = 0; k < 9; k++) rec9[9 * i + k] = v[k];
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+void preprocess(const Launch& L, const GaussDev& g, const CamDev& cam, float4* rec, uint32_t* key, uint2* rect,
+                uint32_t* count) {
+    if (g.n <= 0) return;
+    if (L.prof) L.prof->begin("preprocess_fwd", L.st);
+    hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(g.n, 256)), dim3(256), 0, L.st, g, cam, rec, key, rect, count);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void emit_pairs(const Launch& L, int64_t n, const uint32_t* key, const uint2* rect, const uint64_t* offs, int tiles_x,
+                uint64_t cap, uint64_t* keys, uint32_t* vals) {
+    if (n <= 0) return;
+    if (L.prof) L.prof->begin("emit_keys", L.st);
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(n, 256)), dim3(256), 0, L.st, n, key, rect, offs, tiles_x, cap, keys,
+                       vals);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void ranges_from_keys(const Launch& L, const uint64_t* keys, int64_t K, int ntiles, uint2* ranges) {
+    if (L.prof) L.prof->begin("tile_ranges", L.st);
+    hipLaunchKernelGGL(k_zero_ranges, dim3(blocks_for(ntiles, 256)), dim3(256), 0, L.st, ranges, ntiles);
+    if (K > 0)
+        hipLaunchKernelGGL(k_ranges_from_keys, dim3(blocks_for(K, 256)), dim3(256), 0, L.st, keys, K, ranges);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
+               int tiles_x, int ntiles, uint32_t* hist) {
+    const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
+    if (nchunks == 0) return;
+    if (L.prof) L.prof->begin("bin_count", L.st);
+    hipLaunchKernelGGL((k_bin<false>), dim3((unsigned)nchunks), dim3(64), ntiles * sizeof(uint32_t), L.st, order, n,
+                       rect, count, tiles_x, ntiles, nchunks, hist, (const uint64_t*)nullptr, 0u, (uint32_t*)nullptr);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
+                 int tiles_x, int ntiles, const uint64_t* base, uint64_t cap, uint32_t* vals) {
+    const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
+    if (nchunks == 0) return;
+    if (L.prof) L.prof->begin("bin_scatter", L.st);
+    hipLaunchKernelGGL((k_bin<true>), dim3((unsigned)nchunks), dim3(64), ntiles * sizeof(uint32_t), L.st, order, n,
+                       rect, count, tiles_x, ntiles, nchunks, (uint32_t*)nullptr, base, (uint32_t)cap, vals);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void ranges_from_hist(const Launch& L, const uint64_t* base, const uint64_t* total, int ntiles, int nchunks,
+                      uint64_t cap, uint2* ranges, int* overflow) {
+    if (L.prof) L.prof->begin("tile_ranges", L.st);
+    hipLaunchKernelGGL(k_ranges_from_hist, dim3(blocks_for(ntiles, 256)), dim3(256), 0, L.st, base, total, ntiles,
+                       (int64_t)nchunks, cap, ranges, overflow);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void pairs_total_check(const Launch& L, const uint64_t* total, uint64_t cap, int* overflow) {
+    hipLaunchKernelGGL(k_total_check, dim3(1), dim3(64), 0, L.st, total, cap, overflow);
+}
+
+static unsigned blend_grid(int ntiles) { return (unsigned)(((ntiles + 7) / 8) * 8); }
+
+void blend_forward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals, const float4* rec,
+                   float* image, float* T_final, uint32_t* last) {
+    const int ntiles = cam.tiles_x * cam.tiles_y;
+    if (L.prof) L.prof->begin("blend_fwd", L.st);
+    hipLaunchKernelGGL(k_blend_fwd, dim3(blend_grid(ntiles)), dim3(kBlendThreads), 0, L.st, cam, ntiles, ranges, vals,
+                       rec, image, T_final, last);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void blend_backward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals, const float4* rec,
+                    const float* d_image, const float* T_final, const uint32_t* last, float* accum) {
+    const int ntiles = cam.tiles_x * cam.tiles_y;
+    if (L.prof) L.prof->begin("blend_bwd", L.st);
+    hipLaunchKernelGGL(k_blend_bwd, dim3(blend_grid(ntiles)), dim3(kBlendThreads), 0, L.st, cam, ntiles, ranges, vals,
+                       rec, d_image, T_final, last, accum);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void preprocess_backward(const Launch& L, const GaussDev& g, const CamDev& cam, const float* accum,
+                         const GradsDev& out) {
+    if (g.n <= 0) return;
+    if (L.prof) L.prof->begin("preprocess_bwd", L.st);
+    hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks_for(g.n, 256)), dim3(256), 0, L.st, g, cam, accum, out);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void debug_keys(const Launch& L, const uint2* ranges, const uint32_t* vals, const uint32_t* key, int ntiles,
+                uint64_t* keys_out) {
+    hipLaunchKernelGGL(k_debug_keys, dim3((unsigned)ntiles), dim3(256), 0, L.st, ranges, vals, key, ntiles, keys_out);
+}
+
+void debug_records(const Launch& L, int64_t n, const float4* rec, int32_t* box, float* rec9) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_debug_records, dim3(blocks_for(n, 256)), dim3(256), 0, L.st, n, rec, box, rec9);
+}
+
+}  // namespace gs3

@@ -1,0 +1,263 @@
+// Prefix sums and a stable LSD radix sort for gfx950 (wave64).
+//
+// Scan: three kernels (per-block reduce, single-block scan of the block
+// sums, per-block rescan with the block prefix).  Each block owns 2048
+// consecutive items (256 threads x 8).
+//
+// Radix sort: 8-bit digits, one histogram kernel and one scatter kernel per
+// pass.  A block owns 2048 consecutive items; wave w takes the 512 items
+// starting at w*512 in eight rounds of 64.  Inside a round the lanes that
+// share a digit are found with eight ballots (one per digit bit); a lane's
+// rank is the number of earlier lanes with its digit plus the wave's running
+// count for that digit.  Items keep their order (block, wave, round, lane),
+// so each pass is stable and the sort orders ties by their input position.
+#include "kernels.h"
+
+namespace gs3 {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 8;
+constexpr int kTileItems = kThreads * kItems;
+
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x, int lane) {
+    for (int off = 1; off < 64; off <<= 1) {
+        uint64_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const Tin* __restrict__ in, int64_t n,
+                                                          uint64_t* __restrict__ bsum) {
+    __shared__ uint64_t s_w[kThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; k++)
+        if (base + k < n) s += (uint64_t)in[base + k];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < kThreads / 64; w++) t += s_w[w];
+        bsum[blockIdx.x] = t;
+    }
+}
+
+// One block: exclusive scan of nb block sums in place; total to *total.
+__global__ __launch_bounds__(kThreads) void k_scan_bsums(uint64_t* __restrict__ bsum, int64_t nb,
+                                                         uint64_t* __restrict__ total) {
+    __shared__ uint64_t s_w[kThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kThreads) {
+        int64_t i = b0 + threadIdx.x;
+        uint64_t v = i < nb ? bsum[i] : 0;
+        uint64_t x = wave_incl_scan(v, lane);
+        if (lane == 63) s_w[w] = x;
+        __syncthreads();
+        uint64_t pre = 0, tot = 0;
+        for (int k = 0; k < kThreads / 64; k++) {
+            if (k < w) pre += s_w[k];
+            tot += s_w[k];
+        }
+        if (i < nb) bsum[i] = carry + pre + x - v;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kThreads) void k_scan_down(const Tin* __restrict__ in, int64_t n,
+                                                        const uint64_t* __restrict__ bpre, Tout* __restrict__ out) {
+    __shared__ uint64_t s_w[kThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
+    uint64_t v[kItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; k++) {
+        v[k] = base + k < n ? (uint64_t)in[base + k] : 0;
+        s += v[k];
+    }
+    uint64_t x = wave_incl_scan(s, lane);
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    uint64_t pre = bpre[blockIdx.x];
+    for (int k = 0; k < w; k++) pre += s_w[k];
+    uint64_t run = pre + x - s;
+#pragma unroll
+    for (int k = 0; k < kItems; k++) {
+        if (base + k < n) out[base + k] = (Tout)run;
+        run += v[k];
+    }
+}
+
+template <typename Tout>
+void scan_impl(const Launch& L, const uint32_t* in, int64_t n, Tout* out, uint64_t* total, uint64_t* tmp) {
+    int64_t nb = (n + kTileItems - 1) / kTileItems;
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kThreads), 0, L.st, tmp, (int64_t)0, total);
+        return;
+    }
+    if (L.prof) L.prof->begin("scan", L.st);
+    hipLaunchKernelGGL((k_scan_reduce<uint32_t>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kThreads), 0, L.st, tmp, nb, total);
+    hipLaunchKernelGGL((k_scan_down<uint32_t, Tout>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, in, n, tmp, out);
+    if (L.prof) L.prof->end(L.st);
+}
+
+__device__ __forceinline__ uint64_t match_digit(uint32_t d) {
+    uint64_t m = ~0ull;
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        m &= bit ? bal : ~bal;
+    }
+    return m;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const K* __restrict__ keys, int64_t n, int shift,
+                                                         uint32_t* __restrict__ hist, int64_t nblocks) {
+    __shared__ uint32_t s_h[256];
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kTileItems + w * (64 * kItems);
+    for (int r = 0; r < kItems; r++) {
+        const int64_t idx = base + r * 64 + lane;
+        const bool valid = idx < n;
+        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & 0xFFu : 0u;
+        const uint64_t peers = match_digit(d) & __ballot(valid);
+        if (valid && __popcll(peers & ((1ull << lane) - 1ull)) == 0) atomicAdd(&s_h[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = s_h[threadIdx.x];
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                            K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                            int64_t n, int shift, const uint32_t* __restrict__ offs,
+                                                            int64_t nblocks) {
+    __shared__ uint32_t s_cnt[4][256];
+    __shared__ uint32_t s_base[4][256];
+    for (int k = threadIdx.x; k < 4 * 256; k += kThreads) (&s_cnt[0][0])[k] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kTileItems + w * (64 * kItems);
+    K key[kItems];
+    uint32_t val[kItems], rank[kItems], dig[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; r++) {
+        const int64_t idx = base + r * 64 + lane;
+        const bool valid = idx < n;
+        key[r] = valid ? kin[idx] : (K)0;
+        val[r] = valid ? vin[idx] : 0u;
+        const uint32_t d = (uint32_t)(key[r] >> shift) & 0xFFu;
+        dig[r] = d;
+        const uint64_t peers = match_digit(d) & __ballot(valid);
+        const uint32_t before = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+        const uint32_t cur = s_cnt[w][d];
+        rank[r] = cur + before;
+        if (valid && before == 0) s_cnt[w][d] = cur + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;
+        uint32_t run = offs[(int64_t)d * nblocks + blockIdx.x];
+        for (int k = 0; k < 4; k++) {
+            s_base[k][d] = run;
+            run += s_cnt[k][d];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; r++) {
+        const int64_t idx = base + r * 64 + lane;
+        if (idx < n) {
+            const uint32_t pos = s_base[w][dig[r]] + rank[r];
+            kout[pos] = key[r];
+            vout[pos] = val[r];
+        }
+    }
+}
+
+template <typename K>
+int radix_impl(const Launch& L, K* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist, uint64_t* tmp) {
+    int cur = 0;
+    if (n <= 1) return cur;
+    const int64_t nb = (n + kTileItems - 1) / kTileItems;
+    const int64_t hn = nb * 256;
+    for (int shift = 0; shift < bits; shift += 8) {
+        if (L.prof) L.prof->begin("radix_pass", L.st);
+        hipLaunchKernelGGL((k_radix_hist<K>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, keys[cur], n, shift, hist,
+                           nb);
+        Launch inner{L.st, nullptr};
+        scan_impl<uint32_t>(inner, hist, hn, hist, (uint64_t*)(tmp), tmp + 1);
+        hipLaunchKernelGGL((k_radix_scatter<K>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, keys[cur], vals[cur],
+                           keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, nb);
+        if (L.prof) L.prof->end(L.st);
+        cur ^= 1;
+    }
+    return cur;
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_f32(float* p, float v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_iota_u32(uint32_t* p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (uint32_t)i;
+}
+
+}  // namespace
+
+int64_t scan_tmp_words(int64_t n) { return (n + kTileItems - 1) / kTileItems + 2; }
+
+void scan_u32_to_u64(const Launch& L, const uint32_t* in, int64_t n, uint64_t* out, uint64_t* total, uint64_t* tmp) {
+    scan_impl<uint64_t>(L, in, n, out, total, tmp);
+}
+
+void scan_u32_to_u32(const Launch& L, const uint32_t* in, int64_t n, uint32_t* out, uint64_t* total, uint64_t* tmp) {
+    scan_impl<uint32_t>(L, in, n, out, total, tmp);
+}
+
+int64_t radix_hist_words(int64_t n) { return ((n + kTileItems - 1) / kTileItems) * 256; }
+
+int radix_sort_u32(const Launch& L, uint32_t* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist,
+                   uint64_t* tmp) {
+    return radix_impl<uint32_t>(L, keys, vals, n, bits, hist, tmp);
+}
+
+int radix_sort_u64(const Launch& L, uint64_t* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist,
+                   uint64_t* tmp) {
+    return radix_impl<uint64_t>(L, keys, vals, n, bits, hist, tmp);
+}
+
+void fill_u32(const Launch& L, uint32_t* p, uint32_t v, int64_t n) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.st, p, v, n);
+}
+void fill_f32(const Launch& L, float* p, float v, int64_t n) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.st, p, v, n);
+}
+void iota_u32(const Launch& L, uint32_t* p, int64_t n) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_iota_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.st, p, n);
+}
+
+}  // namespace gs3

@@ -1,0 +1,496 @@
+"""ctypes binding of libgs3.so (include/gs3.h): argument marshalling only.
+
+Every step of the hot path runs in the library's HIP kernels; PyTorch only
+provides device memory (contiguous float32 tensors on the GPU) and the
+stream.  The module-level functions carry the C names; `Context` wraps them.
+Importing this module never falls back to anything: when libgs3.so is not
+built, or the GPU is missing, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgs3.so")
+
+GS3_OK, GS3_EINVAL, GS3_ENOMEM, GS3_EHIP, GS3_ECAPACITY, GS3_ENONFINITE, GS3_ESTATE = 0, -1, -2, -3, -4, -5, -6
+GS3_F32, GS3_F16, GS3_BF16 = 0, 1, 2
+GS3_SORT_DEPTH_FIRST, GS3_SORT_RADIX64 = 0, 1
+PRECISIONS = {"f32": GS3_F32, "f16": GS3_F16, "bf16": GS3_BF16}
+SORT_MODES = {"depth_first": GS3_SORT_DEPTH_FIRST, "radix64": GS3_SORT_RADIX64}
+_STATUS = {0: "GS3_OK", -1: "GS3_EINVAL", -2: "GS3_ENOMEM", -3: "GS3_EHIP", -4: "GS3_ECAPACITY",
+           -5: "GS3_ENONFINITE", -6: "GS3_ESTATE"}
+
+
+class GS3Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class NtcConfigC(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("feats", C.c_int32), ("log2_T", C.c_int32), ("hidden", C.c_int32),
+                ("precision", C.c_int32), ("res", C.c_int32 * 16), ("aabb_min", C.c_float * 3),
+                ("inv_extent", C.c_float * 3)]
+
+
+class ConfigC(C.Structure):
+    _fields_ = [("max_gaussians", C.c_int64), ("max_pairs", C.c_int64), ("max_width", C.c_int32),
+                ("max_height", C.c_int32), ("num_slots", C.c_int32), ("sort_mode", C.c_int32),
+                ("enable_ntc", C.c_int32), ("reserved", C.c_int32), ("ntc", NtcConfigC)]
+
+
+class GaussiansC(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("reserved", C.c_int32), ("means", C.c_void_p),
+                ("quats", C.c_void_p), ("log_scales", C.c_void_p), ("opacity_logits", C.c_void_p),
+                ("sh", C.c_void_p)]
+
+
+class CameraC(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("near_z", C.c_float), ("world_to_cam", C.c_float * 12),
+                ("cam_pos", C.c_float * 3), ("bg", C.c_float * 3)]
+
+
+GRAD_FIELDS = ("d_means", "d_quats", "d_log_scales", "d_opacity_logits", "d_sh", "d_dmu", "d_dq", "d_uv",
+               "d_conic", "d_opacity", "d_rgb")
+
+
+class GradsC(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in GRAD_FIELDS]
+
+
+EXPORTED = ("gs3_create", "gs3_destroy", "gs3_last_error", "gs3_set_stream", "gs3_ntc_num_params",
+            "gs3_ntc_load", "gs3_ntc_save", "gs3_ntc_forward", "gs3_ntc_backward", "gs3_ntc_step",
+            "gs3_ntc_grads", "gs3_ntc_zero_grads", "gs3_warmup_loss", "gs3_render", "gs3_render_backward",
+            "gs3_loss", "gs3_adam", "gs3_debug_counts", "gs3_debug_pairs", "gs3_debug_ranges",
+            "gs3_debug_gaussians", "gs3_debug_pixels", "gs3_check_flags", "gs3_profile_enable",
+            "gs3_profile_reset", "gs3_profile_query")
+
+_lib = None
+
+
+def lib():
+    """Load libgs3.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2403_01444_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_float
+    sig = {
+        "gs3_create": [C.POINTER(ConfigC), C.POINTER(vp)],
+        "gs3_destroy": [vp],
+        "gs3_last_error": [vp],
+        "gs3_set_stream": [vp, vp],
+        "gs3_ntc_num_params": [vp, C.POINTER(i64)],
+        "gs3_ntc_load": [vp, vp, i64],
+        "gs3_ntc_save": [vp, vp, i64],
+        "gs3_ntc_forward": [vp, vp, i64, vp, vp],
+        "gs3_ntc_backward": [vp, vp, i64, vp, vp],
+        "gs3_ntc_step": [vp, f32, f32, f32, f32],
+        "gs3_ntc_grads": [vp, vp, i64],
+        "gs3_ntc_zero_grads": [vp],
+        "gs3_warmup_loss": [vp, vp, vp, i64, vp, vp, vp],
+        "gs3_render": [vp, i32, C.POINTER(GaussiansC), vp, vp, C.POINTER(CameraC), vp],
+        "gs3_render_backward": [vp, i32, vp, C.POINTER(GradsC)],
+        "gs3_loss": [vp, vp, vp, i32, i32, f32, vp, vp],
+        "gs3_adam": [vp, vp, vp, vp, vp, i64, i32, f32, f32, f32, f32],
+        "gs3_debug_counts": [vp, i32, C.POINTER(i64), C.POINTER(i32)],
+        "gs3_debug_pairs": [vp, i32, vp, vp, i64],
+        "gs3_debug_ranges": [vp, i32, vp],
+        "gs3_debug_gaussians": [vp, i32, vp, vp, vp],
+        "gs3_debug_pixels": [vp, i32, vp, vp],
+        "gs3_check_flags": [vp],
+        "gs3_profile_enable": [vp, i32],
+        "gs3_profile_reset": [vp],
+        "gs3_profile_query": [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.gs3_destroy.restype = None
+    L.gs3_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def camera_struct(cam) -> CameraC:
+    c = CameraC()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy, c.near_z = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy), float(cam.near)
+    for k, v in enumerate(np.asarray(cam.world_to_cam, np.float32).reshape(-1)):
+        c.world_to_cam[k] = float(v)
+    for k in range(3):
+        c.cam_pos[k] = float(cam.cam_pos[k])
+        c.bg[k] = float(cam.bg[k])
+    return c
+
+
+@dataclass
+class GaussiansGPU:
+    """Frozen Gaussians resident on the GPU (float32, contiguous)."""
+    means: "object"
+    quats: "object"
+    log_scales: "object"
+    opacity_logits: "object"
+    sh: "object"
+    sh_degree: int
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @staticmethod
+    def from_host(g, device="cuda"):
+        import torch
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        return GaussiansGPU(t(g.means), t(g.quats), t(g.log_scales), t(g.opacity_logits), t(g.sh), g.sh_degree)
+
+    def struct(self) -> GaussiansC:
+        n = self.n
+        k = (self.sh_degree + 1) ** 2
+        return GaussiansC(n, self.sh_degree, 0, _ptr(self.means, numel=3 * n, name="means"),
+                          _ptr(self.quats, numel=4 * n, name="quats"),
+                          _ptr(self.log_scales, numel=3 * n, name="log_scales"),
+                          _ptr(self.opacity_logits, numel=n, name="opacity_logits"),
+                          _ptr(self.sh, numel=3 * k * n, name="sh"))
+
+
+def _check(ctx_handle, status: int):
+    if status != GS3_OK:
+        msg = lib().gs3_last_error(ctx_handle)
+        raise GS3Error(status, msg.decode() if msg else "")
+
+
+# ---------------------------------------------------------------------------
+# module-level functions with the C names (ctx = opaque handle)
+# ---------------------------------------------------------------------------
+
+def gs3_create(cfg: ConfigC):
+    h = C.c_void_p()
+    s = lib().gs3_create(C.byref(cfg), C.byref(h))
+    if s != GS3_OK:
+        raise GS3Error(s, "gs3_create failed")
+    return h
+
+
+def gs3_destroy(h):
+    lib().gs3_destroy(h)
+
+
+def gs3_last_error(h) -> str:
+    msg = lib().gs3_last_error(h)
+    return msg.decode() if msg else ""
+
+
+def gs3_set_stream(h, stream_ptr: int):
+    _check(h, lib().gs3_set_stream(h, C.c_void_p(stream_ptr)))
+
+
+def gs3_ntc_num_params(h) -> int:
+    n = C.c_int64()
+    _check(h, lib().gs3_ntc_num_params(h, C.byref(n)))
+    return n.value
+
+
+def gs3_ntc_load(h, params: np.ndarray):
+    p = np.ascontiguousarray(params, np.float32)
+    _check(h, lib().gs3_ntc_load(h, C.c_void_p(p.ctypes.data), p.size))
+
+
+def gs3_ntc_save(h, n: int) -> np.ndarray:
+    out = np.zeros(n, np.float32)
+    _check(h, lib().gs3_ntc_save(h, C.c_void_p(out.ctypes.data), n))
+    return out
+
+
+def gs3_ntc_forward(h, means, dmu, dq):
+    n = means.shape[0]
+    _check(h, lib().gs3_ntc_forward(h, _ptr(means, numel=3 * n), n, _ptr(dmu, numel=3 * n), _ptr(dq, numel=4 * n)))
+
+
+def gs3_ntc_backward(h, means, d_dmu, d_dq):
+    n = means.shape[0]
+    _check(h, lib().gs3_ntc_backward(h, _ptr(means, numel=3 * n), n, _ptr(d_dmu, numel=3 * n),
+                                     _ptr(d_dq, numel=4 * n)))
+
+
+def gs3_ntc_step(h, lr, beta1, beta2, eps):
+    _check(h, lib().gs3_ntc_step(h, lr, beta1, beta2, eps))
+
+
+def gs3_ntc_grads(h, out):
+    _check(h, lib().gs3_ntc_grads(h, _ptr(out), out.numel()))
+
+
+def gs3_ntc_zero_grads(h):
+    _check(h, lib().gs3_ntc_zero_grads(h))
+
+
+def gs3_warmup_loss(h, dmu, dq, loss, d_dmu, d_dq):
+    n = dmu.shape[0]
+    _check(h, lib().gs3_warmup_loss(h, _ptr(dmu, numel=3 * n), _ptr(dq, numel=4 * n), n, _ptr(loss),
+                                    _ptr(d_dmu, numel=3 * n), _ptr(d_dq, numel=4 * n)))
+
+
+def gs3_render(h, slot, gs: GaussiansGPU, dmu, dq, cam, image):
+    n = gs.n
+    gsc = gs.struct()
+    camc = camera_struct(cam)
+    _check(h, lib().gs3_render(h, slot, C.byref(gsc), _ptr(dmu, numel=3 * n, name="dmu"),
+                               _ptr(dq, numel=4 * n, name="dq"), C.byref(camc),
+                               _ptr(image, numel=3 * cam.width * cam.height, name="image")))
+
+
+def gs3_render_backward(h, slot, d_image, grads: dict):
+    gr = GradsC(*[_ptr(grads.get(k), name=k) for k in GRAD_FIELDS])
+    _check(h, lib().gs3_render_backward(h, slot, _ptr(d_image, name="d_image"), C.byref(gr)))
+
+
+def gs3_loss(h, image, target, height, width, lam, loss, d_image):
+    N = 3 * height * width
+    _check(h, lib().gs3_loss(h, _ptr(image, numel=N), _ptr(target, numel=N), height, width, lam, _ptr(loss),
+                             _ptr(d_image, numel=N)))
+
+
+def gs3_adam(h, param, grad, m, v, step, lr, beta1, beta2, eps):
+    n = param.numel()
+    _check(h, lib().gs3_adam(h, _ptr(param), _ptr(grad, numel=n), _ptr(m, numel=n), _ptr(v, numel=n), n, step,
+                             lr, beta1, beta2, eps))
+
+
+def gs3_debug_counts(h, slot):
+    k, ov = C.c_int64(), C.c_int32()
+    s = lib().gs3_debug_counts(h, slot, C.byref(k), C.byref(ov))
+    if s not in (GS3_OK, GS3_ECAPACITY):
+        _check(h, s)
+    return k.value, ov.value
+
+
+def gs3_debug_pairs(h, slot, keys, vals):
+    _check(h, lib().gs3_debug_pairs(h, slot, _ptr(keys), _ptr(vals), keys.numel()))
+
+
+def gs3_debug_ranges(h, slot, ranges):
+    _check(h, lib().gs3_debug_ranges(h, slot, _ptr(ranges)))
+
+
+def gs3_debug_gaussians(h, slot, key, box, rec):
+    _check(h, lib().gs3_debug_gaussians(h, slot, _ptr(key), _ptr(box), _ptr(rec)))
+
+
+def gs3_debug_pixels(h, slot, T_final, last):
+    _check(h, lib().gs3_debug_pixels(h, slot, _ptr(T_final), _ptr(last)))
+
+
+def gs3_check_flags(h):
+    _check(h, lib().gs3_check_flags(h))
+
+
+def gs3_profile_enable(h, on: bool):
+    _check(h, lib().gs3_profile_enable(h, 1 if on else 0))
+
+
+def gs3_profile_reset(h):
+    _check(h, lib().gs3_profile_reset(h))
+
+
+def gs3_profile_query(h, kernel: str):
+    ms, n = C.c_double(), C.c_int64()
+    _check(h, lib().gs3_profile_query(h, kernel.encode(), C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+
+def make_config(max_gaussians: int, max_pairs: int, max_width: int, max_height: int, num_slots: int = 1,
+                sort_mode: str = "depth_first", ntc=None, precision: str = "f32") -> ConfigC:
+    cfg = ConfigC()
+    cfg.max_gaussians = int(max_gaussians)
+    cfg.max_pairs = int(max_pairs)
+    cfg.max_width, cfg.max_height = int(max_width), int(max_height)
+    cfg.num_slots = int(num_slots)
+    cfg.sort_mode = SORT_MODES[sort_mode]
+    cfg.enable_ntc = 1 if ntc is not None else 0
+    if ntc is not None:
+        cfg.ntc.levels, cfg.ntc.feats, cfg.ntc.log2_T, cfg.ntc.hidden = ntc.levels, ntc.feats, ntc.log2_T, ntc.hidden
+        cfg.ntc.precision = PRECISIONS[precision]
+        for l, r in enumerate(ntc.resolutions()):
+            cfg.ntc.res[l] = r
+        inv = ntc.inv_extent()
+        for k in range(3):
+            cfg.ntc.aabb_min[k] = float(np.float32(ntc.aabb_min[k]))
+            cfg.ntc.inv_extent[k] = float(inv[k])
+    return cfg
+
+
+class Context:
+    """Owns one gs3 context; launches on torch's current stream by default."""
+
+    def __init__(self, max_gaussians, max_pairs, max_width, max_height, num_slots=1, sort_mode="depth_first",
+                 ntc=None, precision="f32", device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("gs3 needs a GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device or "cuda")
+        self.ntc_cfg = ntc
+        self.precision = precision
+        with torch.cuda.device(self.device):
+            self.h = gs3_create(make_config(max_gaussians, max_pairs, max_width, max_height, num_slots, sort_mode,
+                                            ntc, precision))
+        self.use_current_stream()
+        self.n_params = gs3_ntc_num_params(self.h) if ntc is not None else 0
+
+    def use_current_stream(self):
+        import torch
+        gs3_set_stream(self.h, torch.cuda.current_stream(self.device).cuda_stream)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            gs3_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- allocation helpers (torch memory only)
+    def empty(self, *shape, dtype=None):
+        import torch
+        return torch.empty(*shape, dtype=dtype or torch.float32, device=self.device)
+
+    def zeros(self, *shape, dtype=None):
+        import torch
+        return torch.zeros(*shape, dtype=dtype or torch.float32, device=self.device)
+
+    # -- NTC
+    def ntc_load(self, params):
+        gs3_ntc_load(self.h, params)
+
+    def ntc_save(self):
+        return gs3_ntc_save(self.h, self.n_params)
+
+    def ntc_forward(self, means, dmu=None, dq=None):
+        n = means.shape[0]
+        dmu = self.empty(n, 3) if dmu is None else dmu
+        dq = self.empty(n, 4) if dq is None else dq
+        gs3_ntc_forward(self.h, means, dmu, dq)
+        return dmu, dq
+
+    def ntc_backward(self, means, d_dmu, d_dq):
+        gs3_ntc_backward(self.h, means, d_dmu, d_dq)
+
+    def ntc_step(self, lr=0.002, beta1=0.9, beta2=0.99, eps=1e-15):
+        gs3_ntc_step(self.h, lr, beta1, beta2, eps)
+
+    def ntc_grads(self):
+        out = self.empty(self.n_params)
+        gs3_ntc_grads(self.h, out)
+        return out
+
+    def ntc_zero_grads(self):
+        gs3_ntc_zero_grads(self.h)
+
+    def warmup_loss(self, dmu, dq):
+        n = dmu.shape[0]
+        loss = self.empty(1)
+        g_mu, g_q = self.empty(n, 3), self.empty(n, 4)
+        gs3_warmup_loss(self.h, dmu, dq, loss, g_mu, g_q)
+        return loss, g_mu, g_q
+
+    # -- render
+    def render(self, gs: GaussiansGPU, cam, dmu=None, dq=None, slot=0, image=None):
+        image = self.empty(3, cam.height, cam.width) if image is None else image
+        gs3_render(self.h, slot, gs, dmu, dq, cam, image)
+        return image
+
+    def render_backward(self, d_image, grads: dict, slot=0):
+        gs3_render_backward(self.h, slot, d_image, grads)
+        return grads
+
+    def loss(self, image, target, lam=0.2, loss=None, d_image=None):
+        _, H, W = image.shape
+        loss = self.empty(1) if loss is None else loss
+        d_image = self.empty(3, H, W) if d_image is None else d_image
+        gs3_loss(self.h, image, target, H, W, lam, loss, d_image)
+        return loss, d_image
+
+    def adam(self, param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-15):
+        gs3_adam(self.h, param, grad, m, v, step, lr, beta1, beta2, eps)
+
+    # -- inspection
+    def debug_counts(self, slot=0):
+        return gs3_debug_counts(self.h, slot)
+
+    def debug_pairs(self, slot=0):
+        import torch
+        K, ov = gs3_debug_counts(self.h, slot)
+        keys = torch.empty(max(K, 1), dtype=torch.int64, device=self.device)
+        vals = torch.empty(max(K, 1), dtype=torch.int32, device=self.device)
+        gs3_debug_pairs(self.h, slot, keys, vals)
+        return keys[:K], vals[:K]
+
+    def debug_ranges(self, cam, slot=0):
+        import torch
+        tiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+        r = torch.empty(tiles, 2, dtype=torch.int32, device=self.device)
+        gs3_debug_ranges(self.h, slot, r)
+        return r
+
+    def debug_gaussians(self, n, slot=0):
+        import torch
+        key = torch.empty(n, dtype=torch.int32, device=self.device)
+        box = torch.empty(n, 4, dtype=torch.int32, device=self.device)
+        rec = torch.empty(n, 9, dtype=torch.float32, device=self.device)
+        gs3_debug_gaussians(self.h, slot, key, box, rec)
+        return key, box, rec
+
+    def debug_pixels(self, cam, slot=0):
+        import torch
+        T = torch.empty(cam.height, cam.width, dtype=torch.float32, device=self.device)
+        last = torch.empty(cam.height, cam.width, dtype=torch.int32, device=self.device)
+        gs3_debug_pixels(self.h, slot, T, last)
+        return T, last
+
+    def check_flags(self):
+        gs3_check_flags(self.h)
+
+    def profile(self, on=True):
+        gs3_profile_enable(self.h, on)
+
+    def profile_reset(self):
+        gs3_profile_reset(self.h)
+
+    def profile_query(self, kernel):
+        return gs3_profile_query(self.h, kernel)

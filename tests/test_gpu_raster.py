@@ -1,0 +1,190 @@
+"""GPU parity of the rasterizer against the CPU oracle (through the C ABI).
+
+Bars: sort keys, Gaussian indices and tile ranges bit-exact; images within
+1e-4 of the oracle's maximum over non-ambiguous pixels; gradients within
+1e-3 (max norm) excluding Gaussians that reach an ambiguous pixel.
+"""
+import numpy as np
+import pytest
+
+from oracle import raster as orc
+from paper_2403_01444_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gs3():
+    from paper_2403_01444_amd import gs3
+    return gs3
+
+
+def make_ctx(n, cam, sort_mode="depth_first", max_pairs=1 << 22):
+    return _gs3().Context(max(n, 1), max_pairs, cam.width, cam.height, sort_mode=sort_mode)
+
+
+def rand_transform(n, seed, mu_sigma=0.02, q_sigma=0.2):
+    rng = np.random.default_rng(seed)
+    dmu = (rng.normal(size=(n, 3)) * mu_sigma).astype(np.float32)
+    dq = (np.array([1, 0, 0, 0]) + rng.normal(size=(n, 4)) * q_sigma).astype(np.float32)
+    return dmu, dq
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rel_err(a, b):
+    return float(np.abs(np.asarray(a, np.float64) - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+CASES = [
+    ("small-2k-64px", 0, False),
+    ("small-2k-64px", 1, True),
+    ("grad-200-32px", 2, True),
+]
+
+
+def _scene(name, seed, transform):
+    g, cams, _, _ = synth.workload(name, seed=seed)
+    cam = cams[0]
+    dmu = dq = None
+    if transform:
+        dmu, dq = rand_transform(g.n, seed + 10)
+    return g, cam, dmu, dq
+
+
+@pytest.mark.parametrize("sort_mode", ["depth_first", "radix64"])
+@pytest.mark.parametrize("name,seed,transform", CASES)
+def test_pairs_and_ranges_bit_exact(name, seed, transform, sort_mode):
+    g, cam, dmu, dq = _scene(name, seed, transform)
+    ctx = make_ctx(g.n, cam, sort_mode)
+    gg = _gs3().GaussiansGPU.from_host(g)
+    ctx.render(gg, cam, None if dmu is None else cuda(dmu), None if dq is None else cuda(dq))
+    keys, vals = ctx.debug_pairs()
+    ranges = ctx.debug_ranges(cam)
+    rk, rv, rr = orc.sorted_pairs(g, cam, dmu, dq)
+    assert keys.shape[0] == rk.shape[0]
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), rk)
+    assert np.array_equal(vals.cpu().numpy().view(np.uint32), rv)
+    assert np.array_equal(ranges.cpu().numpy().view(np.uint32), rr)
+    # per-Gaussian decisions
+    key, box, rec = ctx.debug_gaussians(g.n)
+    pre = orc.preprocess(g, cam, dmu, dq)
+    vis = pre["visible"].astype(bool)
+    k = key.cpu().numpy().view(np.uint32)
+    assert np.array_equal(k[vis], pre["key"][vis]) and np.all(k[~vis] == 0xFFFFFFFF)
+    assert np.array_equal(box.cpu().numpy()[vis], pre["box"][vis])
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,seed,transform", CASES + [("ring-50k-256px", 3, True)])
+def test_image_matches_oracle(name, seed, transform):
+    g, cam, dmu, dq = _scene(name, seed, transform)
+    ctx = make_ctx(g.n, cam, max_pairs=1 << 24)
+    gg = _gs3().GaussiansGPU.from_host(g)
+    img = ctx.render(gg, cam, None if dmu is None else cuda(dmu), None if dq is None else cuda(dq))
+    T, last = ctx.debug_pixels(cam)
+    ref = orc.render(g, cam, dmu, dq)
+    amb = ref["ambiguous"].astype(bool)
+    P = amb.size
+    assert amb.sum() <= max(1e-4 * P, 0), amb.sum()
+    ok = ~amb
+    err = np.abs(img.cpu().numpy() - ref["image"])[:, ok].max() / np.abs(ref["image"]).max()
+    assert err < 1e-4, err
+    assert np.abs(T.cpu().numpy() - ref["T_final"])[ok].max() < 1e-4
+    ctx.close()
+
+
+def _grads_gpu(ctx, g, dmu, dq, full):
+    n, K = g.n, (g.sh_degree + 1) ** 2
+    shapes = dict(d_dmu=(n, 3), d_dq=(n, 4))
+    if full:
+        shapes.update(d_means=(n, 3), d_quats=(n, 4), d_log_scales=(n, 3), d_opacity_logits=(n,),
+                      d_sh=(n, K, 3), d_uv=(n, 2), d_conic=(n, 3), d_opacity=(n,), d_rgb=(n, 3))
+    return {k: torch.zeros(s, dtype=torch.float32, device="cuda") for k, s in shapes.items()}
+
+
+@pytest.mark.parametrize("name,seed,full", [("small-2k-64px", 4, False), ("grad-200-32px", 5, True),
+                                            ("ring-50k-256px", 6, False)])
+def test_gradients_match_oracle(name, seed, full):
+    g, cam, dmu, dq = _scene(name, seed, True)
+    ctx = make_ctx(g.n, cam, max_pairs=1 << 24)
+    gg = _gs3().GaussiansGPU.from_host(g)
+    tdmu, tdq = cuda(dmu), cuda(dq)
+    ctx.render(gg, cam, tdmu, tdq)
+    w = np.random.default_rng(seed).normal(size=(3, cam.height, cam.width)).astype(np.float32)
+    grads = _grads_gpu(ctx, g, dmu, dq, full)
+    ctx.render_backward(cuda(w), grads)
+    ref = orc.render_backward(g, cam, w.astype(np.float64), dmu, dq)
+    keep = ~ref["touched_ambiguous"]
+    for k, v in grads.items():
+        a = v.cpu().numpy()[keep]
+        b = ref[k][keep]
+        assert rel_err(a, b) < 1e-3, (k, rel_err(a, b))
+    ctx.close()
+
+
+def test_ragged_image_and_culled_gaussians():
+    g, _, _, _ = synth.workload("small-2k-64px", seed=7)
+    cam = synth.look_at_camera(50, 37, bg=(0.1, 0.2, 0.3))
+    g.means[:100] = np.array([0.0, 0.0, -5.0], np.float32)   # behind the camera: culled
+    ctx = make_ctx(g.n, cam)
+    gg = _gs3().GaussiansGPU.from_host(g)
+    img = ctx.render(gg, cam)
+    ref = orc.render(g, cam)
+    ok = ~ref["ambiguous"].astype(bool)
+    assert np.abs(img.cpu().numpy() - ref["image"])[:, ok].max() < 1e-4 * np.abs(ref["image"]).max()
+    keys, vals = ctx.debug_pairs()
+    rk, rv, rr = orc.sorted_pairs(g, cam)
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), rk)
+    ctx.close()
+
+
+def test_empty_scene_gives_background():
+    cam = synth.look_at_camera(40, 24, bg=(0.25, 0.5, 0.75))
+    g = synth.make_gaussians(0, 0, 0)
+    ctx = make_ctx(1, cam)
+    gg = _gs3().GaussiansGPU.from_host(g)
+    img = ctx.render(gg, cam).cpu().numpy()
+    for ch, b in enumerate((0.25, 0.5, 0.75)):
+        assert np.all(img[ch] == np.float32(b))
+    assert ctx.debug_counts()[0] == 0
+    ctx.close()
+
+
+def test_pair_overflow_is_reported_not_written():
+    gs3 = _gs3()
+    g, cams, _, _ = synth.workload("small-2k-64px", seed=8)
+    cam = cams[0]
+    rk, _, _ = orc.sorted_pairs(g, cam)
+    for mode in ("depth_first", "radix64"):
+        ctx = make_ctx(g.n, cam, mode, max_pairs=len(rk) // 2)
+        gg = gs3.GaussiansGPU.from_host(g)
+        try:
+            ctx.render(gg, cam)
+            K, ov = ctx.debug_counts()
+            assert ov == 1 and K == len(rk)
+        except gs3.GS3Error as e:
+            assert e.status == gs3.GS3_ECAPACITY
+        with pytest.raises(gs3.GS3Error):
+            ctx.check_flags()
+        ctx.close()
+
+
+def test_invalid_arguments_return_errors():
+    gs3 = _gs3()
+    cam = synth.look_at_camera(32, 32)
+    ctx = make_ctx(10, cam)
+    g = synth.make_gaussians(20, 0, 0)     # more than max_gaussians
+    with pytest.raises(gs3.GS3Error) as e:
+        ctx.render(gs3.GaussiansGPU.from_host(g), cam)
+    assert e.value.status == gs3.GS3_EINVAL
+    big = synth.look_at_camera(64, 64)
+    with pytest.raises(gs3.GS3Error):
+        ctx.render(gs3.GaussiansGPU.from_host(synth.make_gaussians(5, 0, 0)), big)
+    with pytest.raises(gs3.GS3Error) as e:
+        ctx.render_backward(torch.zeros(3, 32, 32, device="cuda"), {}, slot=0)
+    assert e.value.status == gs3.GS3_ESTATE
+    ctx.close()
