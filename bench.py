@@ -1,0 +1,257 @@
+"""Stage-1 benchmark: 3DGStream NTC training iterations/s on one MI355X.
+
+One step = one Stage-1 iteration on the workload `arc-300k-1352px` (300K
+Gaussians with SH degree 3, 20 training views at 1352x1014 on a forward arc,
+targets rendered from a seeded rigid-plus-sinusoidal motion of the scene):
+NTC query at every mean, transform + render of one view, L1 + D-SSIM loss,
+backward through renderer and NTC, Adam step.  Inputs are resident in HBM
+before timing starts.  Also reported: render FPS of the held-out view with
+and without the NTC, the FP32 direct-optimisation comparator's iterations/s,
+per-kernel device times, the roofline position of the dominant kernel, and
+the CPU oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Stage-1 train iters/s + render FPS, 300K Gaussians @1352x1014, vs FP32 direct"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="arc-300k-1352px")
+    ap.add_argument("--precision", default="f16", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--sort-mode", default="depth_first", choices=["depth_first", "radix64"])
+    ap.add_argument("--warmup-iters", type=int, default=3000, help="NTC warm-up (Eq. 7) iterations before timing")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-direct", action="store_true")
+    ap.add_argument("--render-reps", type=int, default=50)
+    return ap.parse_args()
+
+
+def algorithmic_bytes(name, st):
+    """Bytes the method itself must move per launch of `name`."""
+    n, P, walked, S = st["n"], st["pixels"], st["walked"], st["sh_floats"]
+    if name == "preprocess_fwd":
+        return n * (12 + 16 + 12 + 4 + 4 * S + 12 + 16 + 48 + 4 + 8 + 4)
+    if name == "blend_fwd":
+        return P * 20 + walked * (4 + 48)
+    if name == "blend_bwd":
+        return P * 20 + walked * (4 + 48) + st["contrib_pairs"] * 36
+    if name == "preprocess_bwd":
+        return n * (36 + 12 + 16 + 12 + 4 + 4 * S + 12 + 16 + 12 + 16)
+    if name == "ntc_fwd":
+        return n * (12 + 28) + st["table_bytes"]
+    if name == "ntc_bwd":
+        return n * (12 + 28) + st["table_bytes"] + 4 * st["table_entries"] * 2
+    if name == "loss":
+        return P * (12 + 12 + 12) + P * 36 * 2
+    if name in ("bin_count", "bin_scatter"):
+        return n * 16 + (st["K"] * 4 if name == "bin_scatter" else 0)
+    return None
+
+
+def cpu_baseline(workload, g, cams, targets_np, params, cfg):
+    """The oracle timed on a bounded sample of one Stage-1 iteration.
+
+    Sample: NTC forward + backward on 60,000 of the N means, and render +
+    loss + render backward of a 96-row band through the image centre (a
+    camera cropped to those rows; the band's pixels are exactly the full
+    image's).  Time is scaled to the full iteration: NTC part x N / 60,000,
+    image part x H / 96.
+    """
+    from oracle import loss as oloss
+    from oracle import ntc as ontc
+    from oracle import optim as oopt
+    from oracle import raster as orc
+    from paper_2403_01444_amd import synth
+    cam = cams[0]
+    rows = 96
+    y0 = cam.height // 2 - rows // 2
+    band = synth.Camera(cam.width, rows, cam.fx, cam.fy, cam.cx, cam.cy - y0, cam.near, cam.world_to_cam,
+                        cam.cam_pos, cam.bg)
+    spec = ontc.NTCSpec(cfg)
+    ns = 60000
+    idx = np.random.default_rng(0).choice(g.n, ns, replace=False)
+    t0 = time.perf_counter()
+    dmu_s, dq_s, cache = ontc.forward(spec, params, g.means[idx])
+    gmu = np.zeros_like(dmu_s)
+    gq = np.zeros_like(dq_s)
+    grad = ontc.backward(spec, params, cache, gmu + 1e-6, gq + 1e-6)
+    oopt.adam(params, grad, np.zeros_like(grad), np.zeros_like(grad), 1, 0.002, 0.9, 0.99, 1e-15)
+    t_ntc = time.perf_counter() - t0
+    dmu = np.zeros((g.n, 3), np.float32)
+    dq = np.tile(np.array([1, 0, 0, 0], np.float32), (g.n, 1))
+    t0 = time.perf_counter()
+    out = orc.render(g, band, dmu, dq)
+    L, dL = oloss.stage1_loss(out["image"], targets_np[0][:, y0:y0 + rows, :].astype(np.float64), 0.2)
+    orc.render_backward(g, band, dL, dmu, dq)
+    t_img = time.perf_counter() - t0
+    est = t_ntc * g.n / ns + t_img * cam.height / rows
+    return {"value": round(1.0 / est, 6), "unit": "iters/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"NTC fwd+bwd+Adam on {ns} of {g.n} means (x{g.n / ns:.0f}) and render+loss+backward "
+                      f"of a {rows}-row band of view 0 (x{cam.height / rows:.1f}); float64 oracle, "
+                      f"{t_ntc:.1f}s + {t_img:.1f}s measured, {est:.1f}s per iteration estimated"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the Stage-1 step of one frame is a single-GPU job here); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2403_01444_amd import gs3, synth, train
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    g, cams, held, nxt = synth.workload(args.workload, seed=0)
+    cfg = synth.NTCConfig()
+    W = max(c.width for c in cams + held)
+    H = max(c.height for c in cams + held)
+    max_pairs = 120_000_000
+    ctx = gs3.Context(g.n, max_pairs, W, H, num_slots=1, sort_mode=args.sort_mode, ntc=cfg,
+                      precision=args.precision)
+    gg = gs3.GaussiansGPU.from_host(g)
+    gn = gs3.GaussiansGPU.from_host(nxt)
+    targets = [ctx.render(gn, c).clone() for c in cams]
+    held_t = [ctx.render(gn, c).clone() for c in held]
+    ctx.check_flags()
+
+    # NTC warm-up (Eq. 7) on noise-augmented means, then Stage 1
+    params0 = synth.ntc_init_params(cfg, 0)
+    ctx.ntc_load(params0)
+    wp = torch.from_numpy(synth.warmup_points(g.means, cfg, 1)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    train.warmup(ctx, wp, args.warmup_iters)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    params_warm = ctx.ntc_save()
+    ctx.ntc_load(params_warm)
+
+    st1 = train.Stage1NTC(ctx, gg, cams, targets, lam=0.2)
+    for _ in range(args.warmup):
+        st1.step()
+    torch.cuda.synchronize()
+    ctx.check_flags()
+    ctx.profile(True)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st1.step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.profile(False)
+    ctx.check_flags()
+    kernels = {}
+    for name in ("ntc_fwd", "preprocess_fwd", "radix_pass", "bin_count", "scan", "bin_scatter", "tile_ranges",
+                 "blend_fwd", "loss", "blend_bwd", "preprocess_bwd", "ntc_bwd", "ntc_adam"):
+        ms, cnt = ctx.profile_query(name)
+        if cnt:
+            kernels[name] = {"ms_per_launch": ms / cnt, "launches_per_step": cnt / args.steps}
+    iters_per_s = args.steps / elapsed
+
+    # pair count and walked list entries for the last rendered view
+    K, ov = ctx.debug_counts()
+    T, last = ctx.debug_pixels(cams[0])
+    ctx.render(gg, cams[0], *st1.transform())
+    T, last = ctx.debug_pixels(cams[0])
+    lastn = last.cpu().numpy()
+    th, tw = (cams[0].height + 15) // 16, (cams[0].width + 15) // 16
+    pad = np.zeros((th * 16, tw * 16), np.int64)
+    pad[:lastn.shape[0], :lastn.shape[1]] = lastn
+    walked = int(pad.reshape(th, 16, tw, 16).max(axis=(1, 3)).sum())
+    K0, _ = ctx.debug_counts()
+
+    # render FPS on the held-out view: NTC query + transform + raster (and raster alone)
+    hc = held[0]
+    img = ctx.empty(3, hc.height, hc.width)
+    dmu, dq = st1.dmu, st1.dq
+    for _ in range(3):
+        ctx.ntc_forward(gg.means, dmu, dq)
+        ctx.render(gg, hc, dmu, dq, image=img)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.render_reps):
+        ctx.ntc_forward(gg.means, dmu, dq)
+        ctx.render(gg, hc, dmu, dq, image=img)
+    torch.cuda.synchronize()
+    fps = args.render_reps / (time.perf_counter() - t0)
+    psnr_ntc = train.psnr(img, held_t[0])
+    t0 = time.perf_counter()
+    for _ in range(args.render_reps):
+        ctx.render(gg, hc, image=img)
+    torch.cuda.synchronize()
+    fps_plain = args.render_reps / (time.perf_counter() - t0)
+
+    # FP32 direct optimisation comparator (same renderer and loss)
+    direct = None
+    if not args.no_direct:
+        d = train.Stage1Direct(ctx, gg, cams, targets, lam=0.2)
+        for _ in range(args.warmup):
+            d.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            d.step()
+        torch.cuda.synchronize()
+        direct = args.steps / (time.perf_counter() - t0)
+
+    # roofline of the dominant kernel (by device time per step)
+    n_table_entries = cfg.num_table_params() // 2
+    st = dict(n=g.n, pixels=cams[0].width * cams[0].height, walked=walked, sh_floats=3 * (g.sh_degree + 1) ** 2,
+              K=K0, contrib_pairs=walked, table_bytes=n_table_entries * 2 * (4 if args.precision == "f32" else 2),
+              table_entries=n_table_entries)
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"] * kernels[k]["launches_per_step"]) if kernels else None
+    roof = None
+    if dom is not None:
+        b = algorithmic_bytes(dom, st)
+        if b is not None:
+            gbs = b / (kernels[dom]["ms_per_launch"] * 1e-3) / 1e9
+            roof = {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                    "algorithmic_bytes_per_launch": int(b)}
+
+    base = None
+    if not args.no_cpu_baseline:
+        base = cpu_baseline(args.workload, g, cams, [targets[0].cpu().numpy()], params_warm, cfg)
+
+    res = {
+        "metric": METRIC, "value": round(iters_per_s, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1000.0 * elapsed / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": f"f32 raster + {args.precision} NTC",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "gaussians": g.n, "sh_degree": g.sh_degree,
+                   "width": cams[0].width, "height": cams[0].height, "views": len(cams),
+                   "ntc_precision": args.precision, "sort_mode": args.sort_mode},
+        "s_per_frame_150_iters": round(150.0 / iters_per_s, 4),
+        "render_fps_with_ntc": round(fps, 2), "render_fps_without_ntc": round(fps_plain, 2),
+        "direct_f32_iters_per_s": None if direct is None else round(direct, 3),
+        "pairs_per_view": int(K0), "walked_entries": walked, "heldout_psnr_after_steps": round(psnr_ntc, 3),
+        "warmup_s": round(t_warm, 3), "warmup_iters": args.warmup_iters,
+        "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in kernels.items()},
+        "roofline": roof, "cpu_baseline": base,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -210,6 +210,11 @@ gs3_status gs3_loss(gs3_ctx* ctx, const float* image, const float* target, int32
 gs3_status gs3_adam(gs3_ctx* ctx, float* param, const float* grad, float* m, float* v, int64_t n,
                     int32_t step, float lr, float beta1, float beta2, float eps);
 
+/* Set n floats of DEVICE memory to zero with a fill kernel on the context
+ * stream (no memset node, so it is safe inside captured graphs); used to
+ * clear gradient outputs between iterations. */
+gs3_status gs3_zero(gs3_ctx* ctx, float* dev, int64_t n);
+
 /* ---- Inspection (parity tests, benchmarks) ------------------------------- */
 
 /* Number of (Gaussian, tile) pairs of the slot's last render and its overflow

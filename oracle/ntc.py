@@ -17,9 +17,15 @@ and otherwise through the spatial hash (x * 1) ^ (y * 2654435761) ^
 (z * 805459861) mod T of the instant-NGP encoding the paper follows; the
 cell index is floor(x_n N_l) clamped to N_l - 1; the MLP has no biases.
 
-The cell index is an integer decision, so it is taken in single precision
-exactly as the GPU takes it (x_n and x_n * N_l rounded to float32); the
-trilinear weights and everything after are float64.
+The lattice coordinate p = x_n N_l decides the cell, so it is evaluated in
+single precision exactly as the GPU evaluates it (x_n and x_n * N_l rounded
+to float32); the cell is floor(p) and the trilinear weights are the exact
+fractional parts p - floor(p); everything after is float64.
+
+A hidden unit whose pre-activation lies within rounding reach of zero may
+switch its ReLU the other way on the GPU; relu_margins() reports, per point,
+the smallest |z| / sum |w x| over both hidden layers so that parity tests can
+set aside the few points where that can happen.
 
 Mixed-precision emulation (`precision` = "f16" / "bf16"): table entries,
 weights and forward activations (encoding, h1, h2) are rounded to the
@@ -96,13 +102,12 @@ def corners(spec: NTCSpec, means: np.ndarray):
     means = np.asarray(means, np.float32)
     xn32 = (means - spec.aabb_min) * spec.inv_ext                      # float32, as the GPU
     inside = np.all((xn32 >= 0) & (xn32 <= 1), axis=1)
-    xn64 = (means.astype(np.float64) - spec.aabb_min.astype(np.float64)) * spec.inv_ext.astype(np.float64)
     rows, wts = [], []
     for l, N in enumerate(spec.res):
         p32 = xn32 * np.float32(N)
         i0 = np.minimum(np.floor(p32).astype(np.int64), N - 1)
         i0 = np.maximum(i0, 0)
-        w = xn64 * N - i0                                               # float64 fractions
+        w = p32.astype(np.float64) - i0                                 # exact fractions
         dense = (N + 1) ** 3 <= spec.T
         r = np.zeros((means.shape[0], 8), np.int64)
         wt = np.ones((means.shape[0], 8))
@@ -174,3 +179,47 @@ def backward(spec: NTCSpec, params: np.ndarray, cache: dict, d_dmu: np.ndarray, 
         for c in range(8):
             np.add.at(dtable, cache["rows"][l][:, c], cache["wts"][l][:, c:c + 1] * g)
     return np.concatenate([dtable.reshape(-1), dW1.reshape(-1), dW2.reshape(-1), dW3.reshape(-1)])
+
+
+def relu_ambiguous(spec: NTCSpec, params: np.ndarray, means: np.ndarray, precision: str = "f32",
+                   acc_rel: float = 2e-6) -> np.ndarray:
+    """Points whose ReLU masks single precision could take the other way.
+
+    A hidden unit j is at risk when |z_j| is within the float32 accumulation
+    error of the GPU (acc_rel x sum_k |W_jk x_k|).  With half-precision storage
+    an input x_k (encoding or h1) is also at risk when its float32 value,
+    uncertain by acc_rel x sum |terms| as well, straddles a rounding boundary
+    of the storage type; the point is flagged when replacing x_k by the other
+    rounding would change the sign of some z_j.  Returns a boolean mask.
+    """
+    table, W1, W2, W3 = spec.split(params)
+    rs = lambda a: round_storage(a, precision)
+    inside, rows, wts = corners(spec, means)
+    tab = rs(table)
+    n = means.shape[0]
+    enc = np.zeros((n, spec.in_dim))
+    mag = np.zeros((n, spec.in_dim))
+    for l in range(spec.L):
+        for c in range(8):
+            t = wts[l][:, c:c + 1] * tab[rows[l][:, c]]
+            enc[:, spec.F * l:spec.F * (l + 1)] += t
+            mag[:, spec.F * l:spec.F * (l + 1)] += np.abs(t)
+    flag = np.zeros(n, bool)
+    x_val, x_err = enc, acc_rel * mag
+    for W in (rs(W1), rs(W2)):
+        x = rs(x_val)
+        z = x @ W.T
+        s = np.abs(x) @ np.abs(W).T
+        flag |= np.any(np.abs(z) <= acc_rel * s, axis=1)
+        if precision != "f32":
+            lo, hi = rs(x_val - x_err), rs(x_val + x_err)
+            for alt in (lo, hi):
+                d = alt - x                                   # nonzero where a rounding can differ
+                ii, kk = np.nonzero(d)
+                if ii.size:
+                    zz = z[ii] + d[ii, kk][:, None] * W[:, kk].T
+                    flag[ii[np.any(np.sign(zz) != np.sign(z[ii]), axis=1)]] = True
+        x_val = np.maximum(z, 0.0)
+        x_err = acc_rel * s
+    flag &= inside
+    return flag

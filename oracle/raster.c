@@ -631,7 +631,11 @@ static int64_t walk_pixel(const scene_t* s, int x, int y, double* T_out, double 
         double G = exp(power);
         double raw = q->opacity * G;
         double alpha = raw < 0.99 ? raw : 0.99;
-        if (fabs(alpha - 1.0 / 255.0) < 1e-6 || fabs(raw - 0.99) < 1e-6) *ambig = 1;
+        /* single precision reaches alpha to ~1e-6 relative (power from
+         * float32 mean, conic and exp) and the transmittance product to
+         * ~1e-4 relative after a few hundred factors: decisions within those
+         * margins may go the other way on the GPU */
+        if (fabs(alpha - 1.0 / 255.0) < 2e-6 / 255.0 || fabs(raw - 0.99) < 2e-6 || power > -1e-6) *ambig = 1;
         if (alpha < 1.0 / 255.0) continue;
         double Tn = T * (1.0 - alpha);
         if (fabs(Tn - 1e-4) < 1e-8) *ambig = 1;

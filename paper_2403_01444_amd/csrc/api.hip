@@ -475,6 +475,13 @@ gs3_status gs3_adam(gs3_ctx* c, float* param, const float* grad, float* m, float
     return c->check_launch("adam");
 }
 
+gs3_status gs3_zero(gs3_ctx* c, float* dev, int64_t n) {
+    if (!c) return GS3_EINVAL;
+    if (n < 0 || (n > 0 && !dev)) return c->fail(GS3_EINVAL, "zero: bad arguments");
+    fill_f32(c->L(), dev, 0.f, n);
+    return c->check_launch("zero");
+}
+
 /* ---- inspection ----------------------------------------------------------- */
 
 gs3_status gs3_debug_counts(gs3_ctx* c, int32_t slot, int64_t* num_pairs, int32_t* overflow) {

@@ -67,7 +67,7 @@ class GradsC(C.Structure):
 EXPORTED = ("gs3_create", "gs3_destroy", "gs3_last_error", "gs3_set_stream", "gs3_ntc_num_params",
             "gs3_ntc_load", "gs3_ntc_save", "gs3_ntc_forward", "gs3_ntc_backward", "gs3_ntc_step",
             "gs3_ntc_grads", "gs3_ntc_zero_grads", "gs3_warmup_loss", "gs3_render", "gs3_render_backward",
-            "gs3_loss", "gs3_adam", "gs3_debug_counts", "gs3_debug_pairs", "gs3_debug_ranges",
+            "gs3_loss", "gs3_adam", "gs3_zero", "gs3_debug_counts", "gs3_debug_pairs", "gs3_debug_ranges",
             "gs3_debug_gaussians", "gs3_debug_pixels", "gs3_check_flags", "gs3_profile_enable",
             "gs3_profile_reset", "gs3_profile_query")
 
@@ -101,6 +101,7 @@ def lib():
         "gs3_render_backward": [vp, i32, vp, C.POINTER(GradsC)],
         "gs3_loss": [vp, vp, vp, i32, i32, f32, vp, vp],
         "gs3_adam": [vp, vp, vp, vp, vp, i64, i32, f32, f32, f32, f32],
+        "gs3_zero": [vp, vp, i64],
         "gs3_debug_counts": [vp, i32, C.POINTER(i64), C.POINTER(i32)],
         "gs3_debug_pairs": [vp, i32, vp, vp, i64],
         "gs3_debug_ranges": [vp, i32, vp],
@@ -286,6 +287,10 @@ def gs3_adam(h, param, grad, m, v, step, lr, beta1, beta2, eps):
                              lr, beta1, beta2, eps))
 
 
+def gs3_zero(h, t):
+    _check(h, lib().gs3_zero(h, _ptr(t, name="zero target"), t.numel()))
+
+
 def gs3_debug_counts(h, slot):
     k, ov = C.c_int64(), C.c_int32()
     s = lib().gs3_debug_counts(h, slot, C.byref(k), C.byref(ov))
@@ -448,6 +453,10 @@ class Context:
 
     def adam(self, param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-15):
         gs3_adam(self.h, param, grad, m, v, step, lr, beta1, beta2, eps)
+
+    def zero(self, *tensors):
+        for t in tensors:
+            gs3_zero(self.h, t)
 
     # -- inspection
     def debug_counts(self, slot=0):

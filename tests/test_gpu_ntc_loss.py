@@ -18,6 +18,11 @@ torch = pytest.importorskip("torch")
 # number on one side only (one unit in the last place of one operand).
 TOL_FWD = {"f32": 1e-4, "f16": 2e-3, "bf16": 1.6e-2}
 TOL_BWD = {"f32": 1e-3, "f16": 4e-3, "bf16": 3e-2}
+# Points whose ReLU masks the GPU could take the other way (a pre-activation
+# within float32 accumulation error of zero, or an input whose storage
+# rounding can land on the other side and move a pre-activation across zero)
+# get a zero output gradient in the backward parity test; the oracle finds
+# them (relu_ambiguous) and they must stay rare.
 
 
 def cuda(a):
@@ -43,7 +48,7 @@ def ntc_ctx(cfg, n, precision):
 
 
 @pytest.mark.parametrize("precision", ["f32", "f16", "bf16"])
-@pytest.mark.parametrize("n", [1, 37, 5000])
+@pytest.mark.parametrize("n", [1, 37, 5000, 50000])
 def test_ntc_forward_backward(precision, n):
     cfg = synth.NTCConfig()
     params, spec = trained_like_params(cfg, 1)
@@ -59,6 +64,10 @@ def test_ntc_forward_backward(precision, n):
     assert rel_err(out, ref) < TOL_FWD[precision], rel_err(out, ref)
     g_mu = rng.normal(size=(n, 3)).astype(np.float32) * 1e-3
     g_q = rng.normal(size=(n, 4)).astype(np.float32) * 1e-3
+    near = ontc.relu_ambiguous(spec, params, means, precision)
+    assert near.mean() < 0.02, near.mean()
+    g_mu[near] = 0.0
+    g_q[near] = 0.0
     ctx.ntc_backward(m, cuda(g_mu), cuda(g_q))
     grad = ctx.ntc_grads().cpu().numpy()
     ref_g = ontc.backward(spec, params, cache, g_mu, g_q, precision)
