@@ -71,7 +71,8 @@ typedef struct {
     int32_t num_slots;               /* renders whose state is kept for backward, 1..8 */
     int32_t sort_mode;               /* GS3_SORT_DEPTH_FIRST (default) | GS3_SORT_RADIX64 */
     int32_t enable_ntc;              /* 0: rasterizer only */
-    int32_t reserved;
+    int32_t grad_record_log2;        /* log2 capacity of the backward blend's per-pair gradient
+                                        records (0 = 23); pairs past it use atomics */
     gs3_ntc_config ntc;
 } gs3_config;
 
@@ -164,6 +165,17 @@ gs3_status gs3_ntc_forward(gs3_ctx* ctx, const float* means, int64_t n, float* d
  * backward, then the hash-table scatter-add). */
 gs3_status gs3_ntc_backward(gs3_ctx* ctx, const float* means, int64_t n,
                             const float* d_dmu, const float* d_dq);
+
+/* Per-frame setup for gs3_ntc_backward on frozen means (Stage 1 keeps the
+ * previous frame's Gaussians frozen, Sec. 4.1): for every (mean, level,
+ * corner) the table entry and trilinear weight are computed once and the
+ * contributions are sorted by entry.  Afterwards gs3_ntc_backward calls with
+ * the SAME `means` pointer and n add the table gradient by a per-entry sum
+ * (no atomics, fixed order).  The caller guarantees that the contents of
+ * `means` do not change until the next gs3_ntc_prepare; a call with another
+ * pointer or n uses the atomic scatter.  Allocates device memory on first
+ * use or growth (about 1 KB per mean) and synchronises. */
+gs3_status gs3_ntc_prepare(gs3_ctx* ctx, const float* means, int64_t n);
 
 /* One Adam step on the NTC parameters with the accumulated gradients,
  * then zero the gradients and refresh the FP16/BF16 working copy. */

@@ -69,6 +69,9 @@ struct Slot {
     float* T_final = nullptr;
     uint32_t* last = nullptr;
     uint64_t* total = nullptr;
+    uint64_t* goff = nullptr;        // exclusive scan of the tile counts
+    uint32_t* gpos = nullptr;        // per Gaussian and rectangle tile: slot of that pair
+    uint32_t* tile_walk = nullptr;   // list entries walked per tile by the forward blend
     bool valid = false;
     GaussDev g{};
     CamDev cam{};
@@ -91,8 +94,12 @@ struct gs3_ctx {
     uint64_t* scan_tmp = nullptr;
     uint32_t* bin_hist = nullptr;
     uint64_t* bin_base = nullptr;
-    uint64_t* offs = nullptr;
     float* accum = nullptr;
+    uint32_t* walk_off = nullptr;
+    uint64_t* walk_total = nullptr;
+    uint64_t* goff_total = nullptr;
+    float* grec = nullptr;
+    int64_t grec_cap = 0;
     int* flags = nullptr;   // [0] pair overflow, [1] non-finite loss
     float* loss_maps = nullptr;
     double* loss_bsum = nullptr;
@@ -105,6 +112,15 @@ struct gs3_ctx {
     float* g_part = nullptr;
     int max_parts = 0;
     double* warm_bsum = nullptr;
+    // per-frame contribution lists of the table gradient
+    NtcCsr csr;
+    const float* csr_means = nullptr;
+    int64_t csr_n = -1, csr_cap = 0;
+    std::vector<void*> csr_allocs;
+    uint32_t* csr_keys[2] = {nullptr, nullptr};
+    uint32_t* csr_vals[2] = {nullptr, nullptr};
+    uint32_t* csr_hist = nullptr;
+    uint64_t* csr_tmp = nullptr;
     EventProfiler prof;
     bool prof_on = false;
 
@@ -149,6 +165,7 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
         (cfg->sort_mode != GS3_SORT_DEPTH_FIRST && cfg->sort_mode != GS3_SORT_RADIX64))
         return GS3_EINVAL;
     if (tiles_of(cfg->max_width, cfg->max_height) > GS3_MAX_TILES) return GS3_EINVAL;
+    if ((cfg->max_width + kTile - 1) / kTile > 2048) return GS3_EINVAL;
     gs3_ctx* c = new gs3_ctx();
     c->cfg = *cfg;
     c->max_tiles = tiles_of(cfg->max_width, cfg->max_height);
@@ -159,7 +176,8 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
     for (auto& s : c->slots) {
         ok = ok && c->alloc(&s.rec, 3 * N) && c->alloc(&s.key, N) && c->alloc(&s.rect, N) && c->alloc(&s.count, N) &&
              c->alloc(&s.vals[0], PK) && c->alloc(&s.ranges, c->max_tiles) && c->alloc(&s.T_final, PX) &&
-             c->alloc(&s.last, PX) && c->alloc(&s.total, 1);
+             c->alloc(&s.last, PX) && c->alloc(&s.total, 1) && c->alloc(&s.goff, N) && c->alloc(&s.gpos, PK) &&
+             c->alloc(&s.tile_walk, c->max_tiles);
         if (ok && cfg->sort_mode == GS3_SORT_RADIX64)
             ok = c->alloc(&s.vals[1], PK) && c->alloc(&s.pkeys[0], PK) && c->alloc(&s.pkeys[1], PK);
     }
@@ -171,10 +189,15 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
          c->alloc(&c->dvals[1], N) && c->alloc(&c->radix_hist, hist_words) &&
          c->alloc(&c->scan_tmp, scan_tmp_words(scan_items) + 4) && c->alloc(&c->accum, 9 * N) &&
          c->alloc(&c->flags, 4) && c->alloc(&c->loss_maps, loss_map_floats(cfg->max_height, cfg->max_width)) &&
+         c->alloc(&c->walk_off, c->max_tiles) && c->alloc(&c->walk_total, 1) && c->alloc(&c->goff_total, 1) &&
          c->alloc(&c->loss_bsum, 2 * (int64_t)loss_blocks(cfg->max_height, cfg->max_width));
+    {
+        const int lg = cfg->grad_record_log2 > 0 ? std::min(cfg->grad_record_log2, 30) : 23;
+        c->grec_cap = std::min<int64_t>(PK, (int64_t)1 << lg);
+        ok = ok && c->alloc(&c->grec, 9 * c->grec_cap);
+    }
     if (ok && cfg->sort_mode == GS3_SORT_DEPTH_FIRST)
         ok = c->alloc(&c->bin_hist, bin_words) && c->alloc(&c->bin_base, bin_words);
-    if (ok && cfg->sort_mode == GS3_SORT_RADIX64) ok = c->alloc(&c->offs, N);
     if (ok && cfg->enable_ntc) {
         const gs3_ntc_config& nc = cfg->ntc;
         if (nc.levels != 16 || nc.feats != 2 || nc.hidden != 64 || nc.log2_T < 10 || nc.log2_T > 22 ||
@@ -233,6 +256,7 @@ void gs3_destroy(gs3_ctx* ctx) {
     if (!ctx) return;
     hipDeviceSynchronize();
     for (void* p : ctx->allocs) hipFree(p);
+    for (void* p : ctx->csr_allocs) hipFree(p);
     delete ctx;
 }
 
@@ -304,9 +328,53 @@ gs3_status gs3_ntc_backward(gs3_ctx* c, const float* means, int64_t n, const flo
     if (n < 0 || (n > 0 && (!means || !d_dmu || !d_dq))) return c->fail(GS3_EINVAL, "ntc_backward: bad arguments");
     const void *table, *mlp;
     ntc_ptrs(c, &table, &mlp);
+    const bool prepared = means == c->csr_means && n == c->csr_n;
     ntc_backward(c->L(), c->cfg.ntc.precision, c->nd, table, mlp, means, n, d_dmu, d_dq, c->g,
-                 c->g + c->n_table_floats, c->g_part, c->max_parts);
+                 c->g + c->n_table_floats, c->g_part, c->max_parts, prepared ? &c->csr : nullptr);
     return c->check_launch("ntc_backward");
+}
+
+gs3_status gs3_ntc_prepare(gs3_ctx* c, const float* means, int64_t n) {
+    if (!c) return GS3_EINVAL;
+    if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
+    if (n < 1 || n > c->cfg.max_gaussians || n >= ((int64_t)1 << 25) || !means)
+        return c->fail(GS3_EINVAL, "ntc_prepare: bad arguments");
+    c->csr_means = nullptr;
+    c->csr_n = -1;
+    const int64_t m = n * 128;
+    if (n > c->csr_cap) {
+        hipDeviceSynchronize();
+        for (void* p : c->csr_allocs) hipFree(p);
+        c->csr_allocs.clear();
+        auto get = [&](void** out, size_t bytes) {
+            *out = nullptr;
+            if (hipMalloc(out, bytes) != hipSuccess) return false;
+            c->csr_allocs.push_back(*out);
+            return true;
+        };
+        const int64_t entries = c->n_table_floats / 2;
+        bool ok = get((void**)&c->csr_keys[0], m * 4) && get((void**)&c->csr_keys[1], m * 4) &&
+                  get((void**)&c->csr_vals[0], m * 4) && get((void**)&c->csr_vals[1], m * 4) &&
+                  get((void**)&c->csr_hist, radix_hist_words(m) * 4) &&
+                  get((void**)&c->csr_tmp, (scan_tmp_words(radix_hist_words(m)) + 4) * 8) &&
+                  get((void**)&c->csr.rows, entries * 8) && get((void**)&c->csr.w, m * 4) &&
+                  get((void**)&c->csr.denc, n * 32 * 4);
+        if (!ok) {
+            for (void* p : c->csr_allocs) hipFree(p);
+            c->csr_allocs.clear();
+            c->csr_cap = 0;
+            return c->fail(GS3_ENOMEM, "ntc_prepare: allocation failed");
+        }
+        c->csr_cap = n;
+        c->csr.entries = entries;
+    }
+    ntc_csr_build(c->L(), c->nd, means, n, c->csr, c->csr_keys, c->csr_vals, c->csr_hist, c->csr_tmp);
+    if (hipStreamSynchronize(c->st) != hipSuccess) return c->fail(GS3_EHIP, "ntc_prepare: sync failed");
+    gs3_status s = c->check_launch("ntc_prepare");
+    if (s != GS3_OK) return s;
+    c->csr_means = means;
+    c->csr_n = n;
+    return GS3_OK;
 }
 
 gs3_status gs3_ntc_step(gs3_ctx* c, float lr, float beta1, float beta2, float eps) {
@@ -399,9 +467,11 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
             const int r = radix_sort_u32(L, c->dkeys, c->dvals, n, 32, c->radix_hist, c->scan_tmp);
             const uint32_t* order = c->dvals[r];
             const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
-            bin_count(L, order, n, sl.rect, sl.count, cd.tiles_x, ntiles, c->bin_hist);
+            scan_u32_to_u64(L, sl.count, n, sl.goff, c->goff_total, c->scan_tmp);
+            bin_count(L, order, n, sl.rect, sl.count, cd.tiles_x, cd.tiles_y, c->bin_hist);
             scan_u32_to_u64(L, c->bin_hist, (int64_t)ntiles * nchunks, c->bin_base, sl.total, c->scan_tmp);
-            bin_scatter(L, order, n, sl.rect, sl.count, cd.tiles_x, ntiles, c->bin_base, cap, sl.vals[0]);
+            bin_scatter(L, order, n, sl.rect, sl.count, cd.tiles_x, cd.tiles_y, c->bin_base, cap, sl.vals[0],
+                        sl.goff, sl.gpos);
             ranges_from_hist(L, c->bin_base, sl.total, ntiles, (int)nchunks, cap, sl.ranges, c->flags);
         } else {
             fill_u32(L, (uint32_t*)sl.ranges, 0u, 2 * (int64_t)ntiles);
@@ -409,8 +479,8 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
         }
         sl.K_host = -1;
     } else {
-        scan_u32_to_u64(L, sl.count, n, c->offs, sl.total, c->scan_tmp);
-        emit_pairs(L, n, sl.key, sl.rect, c->offs, cd.tiles_x, cap, sl.pkeys[0], sl.vals[0]);
+        scan_u32_to_u64(L, sl.count, n, sl.goff, sl.total, c->scan_tmp);
+        emit_pairs(L, n, sl.key, sl.rect, sl.goff, cd.tiles_x, cap, sl.pkeys[0], sl.vals[0]);
         uint64_t K = 0;
         if (hipMemcpyAsync(&K, sl.total, 8, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
             hipStreamSynchronize(c->st) != hipSuccess)
@@ -424,8 +494,9 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
         while ((1 << tb) < ntiles) tb++;
         sl.cur = radix_sort_u64(L, sl.pkeys, sl.vals, (int64_t)K, 32 + tb, c->radix_hist, c->scan_tmp);
         ranges_from_keys(L, sl.pkeys[sl.cur], (int64_t)K, ntiles, sl.ranges);
+        gpos_from_pairs(L, sl.pkeys[sl.cur], sl.vals[sl.cur], (int64_t)K, sl.rect, sl.goff, cd.tiles_x, cap, sl.gpos);
     }
-    blend_forward(L, cd, sl.ranges, sl.vals[sl.cur], sl.rec, image, sl.T_final, sl.last);
+    blend_forward(L, cd, sl.ranges, sl.vals[sl.cur], sl.rec, image, sl.T_final, sl.last, sl.tile_walk);
     gs3_status st = c->check_launch("render");
     if (st != GS3_OK) return st;
     sl.g = gd;
@@ -442,14 +513,20 @@ gs3_status gs3_render_backward(gs3_ctx* c, int32_t slot, const float* d_image, c
     if (!sl.valid) return c->fail(GS3_ESTATE, "render_backward before a successful render on this slot");
     Launch L = c->L();
     const int64_t n = sl.g.n;
+    const int ntiles = sl.cam.tiles_x * sl.cam.tiles_y;
     fill_f32(L, c->accum, 0.f, 9 * n);
-    blend_backward(L, sl.cam, sl.ranges, sl.vals[sl.cur], sl.rec, d_image, sl.T_final, sl.last, c->accum);
+    scan_u32_to_u32(L, sl.tile_walk, ntiles, c->walk_off, c->walk_total, c->scan_tmp);
+    GatherDev ga;
+    ga.rect = sl.rect; ga.goff = sl.goff; ga.gpos = sl.gpos; ga.ranges = sl.ranges; ga.tile_walk = sl.tile_walk;
+    ga.walk_off = c->walk_off; ga.grec = c->grec; ga.grec_cap = (uint64_t)c->grec_cap;
+    ga.cap = (uint64_t)c->cfg.max_pairs;
+    blend_backward(L, sl.cam, sl.ranges, sl.vals[sl.cur], sl.rec, d_image, sl.T_final, sl.last, ga, c->accum);
     GradsDev gd;
     gd.d_means = out->d_means; gd.d_quats = out->d_quats; gd.d_log_scales = out->d_log_scales;
     gd.d_opac = out->d_opacity_logits; gd.d_sh = out->d_sh; gd.d_dmu = sl.g.dmu ? out->d_dmu : nullptr;
     gd.d_dq = sl.g.dq ? out->d_dq : nullptr; gd.d_uv = out->d_uv; gd.d_conic = out->d_conic;
     gd.d_opacity = out->d_opacity; gd.d_rgb = out->d_rgb;
-    preprocess_backward(L, sl.g, sl.cam, c->accum, gd);
+    preprocess_backward(L, sl.g, sl.cam, c->accum, ga, gd);
     return c->check_launch("render_backward");
 }
 

@@ -324,4 +324,24 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_add(float x) {
+    const int moved = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kCtrl, kRowMask, 0xF, false);
+    return x + __builtin_bit_cast(float, moved);
+}
+
+// Sum over the 64 lanes with DPP moves (no LDS traffic); the result is
+// returned uniformly (read from lane 63).  Steps: pairs and quads
+// (quad_perm), 8 and 16 lanes (row_half_mirror, row_mirror), then rows
+// (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3).
+__device__ __forceinline__ float wave_sum_dpp(float x) {
+    x = dpp_add<0xB1, 0xF>(x);    // quad_perm [1,0,3,2]
+    x = dpp_add<0x4E, 0xF>(x);    // quad_perm [2,3,0,1]
+    x = dpp_add<0x141, 0xF>(x);   // row_half_mirror
+    x = dpp_add<0x140, 0xF>(x);   // row_mirror
+    x = dpp_add<0x142, 0xA>(x);   // row_bcast:15
+    x = dpp_add<0x143, 0xC>(x);   // row_bcast:31
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
+}
+
 }  // namespace gs3

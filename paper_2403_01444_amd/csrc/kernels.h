@@ -49,27 +49,48 @@ void emit_pairs(const Launch& L, int64_t n, const uint32_t* key, const uint2* re
 void ranges_from_keys(const Launch& L, const uint64_t* keys, int64_t K, int ntiles, uint2* ranges);
 // depth-first path: per-chunk tile histograms of depth-ordered Gaussians,
 // then an order-preserving scatter of Gaussian indices.
-constexpr int kBinChunk = 1024;
+constexpr int kBinChunk = 2048;
 void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
-               int tiles_x, int ntiles, uint32_t* hist);
+               int tiles_x, int tiles_y, uint32_t* hist);
+// also records, for each Gaussian's k-th rectangle tile, the slot of that
+// pair: gpos[goff[id] + k] (goff = exclusive scan of the tile counts)
 void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
-                 int tiles_x, int ntiles, const uint64_t* base, uint64_t cap, uint32_t* vals);
+                 int tiles_x, int tiles_y, const uint64_t* base, uint64_t cap, uint32_t* vals, const uint64_t* goff,
+                 uint32_t* gpos);
+void gpos_from_pairs(const Launch& L, const uint64_t* keys, const uint32_t* vals, int64_t K, const uint2* rect,
+                     const uint64_t* goff, int tiles_x, uint64_t cap, uint32_t* gpos);
 void ranges_from_hist(const Launch& L, const uint64_t* base, const uint64_t* total, int ntiles, int nchunks,
                       uint64_t cap, uint2* ranges, int* overflow);
 void pairs_total_check(const Launch& L, const uint64_t* total, uint64_t cap, int* overflow);
 
+// Per-pair gradient records of the backward blend: walked entries of tile t
+// (list positions [start_t, start_t + tile_walk[t])) get compact indices
+// walk_off[t] + (position - start_t); term c of entry w lives at
+// grec[c * grec_cap + w].  Entries past grec_cap fall back to atomics.
+struct GatherDev {
+    const uint2* rect;
+    const uint64_t* goff;
+    const uint32_t* gpos;
+    const uint2* ranges;
+    const uint32_t* tile_walk;
+    const uint32_t* walk_off;
+    float* grec;
+    uint64_t grec_cap;
+    uint64_t cap;   // pair capacity (gpos length)
+};
+
 void blend_forward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals, const float4* rec,
-                   float* image, float* T_final, uint32_t* last);
+                   float* image, float* T_final, uint32_t* last, uint32_t* tile_walk);
 void blend_backward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals,
                     const float4* rec, const float* d_image, const float* T_final, const uint32_t* last,
-                    float* accum);
+                    const GatherDev& ga, float* accum);
 
 struct GradsDev {
     float *d_means, *d_quats, *d_log_scales, *d_opac, *d_sh, *d_dmu, *d_dq;
     float *d_uv, *d_conic, *d_opacity, *d_rgb;
 };
 void preprocess_backward(const Launch& L, const GaussDev& g, const CamDev& cam, const float* accum,
-                         const GradsDev& out);
+                         const GatherDev& ga, const GradsDev& out);
 void debug_keys(const Launch& L, const uint2* ranges, const uint32_t* vals, const uint32_t* key, int ntiles,
                 uint64_t* keys_out);
 void debug_records(const Launch& L, int64_t n, const float4* rec, int32_t* box, float* rec9);

@@ -14,13 +14,25 @@ struct NtcDev {
     float inv_ext[3];
 };
 
+// Per-frame contribution lists of the table gradient (see ntc.hip).
+struct NtcCsr {
+    int64_t entries = 0;      // table entries
+    uint2* rows = nullptr;    // [entries]: [start, end) into pid / w
+    uint32_t* pid = nullptr;  // point << 7 | level << 3 | corner, sorted by entry
+    float* w = nullptr;       // trilinear weight of each contribution
+    float* denc = nullptr;    // n x 32 encoding gradient of the current backward
+};
+
 int ntc_mlp_params();
+// keys/vals: two ping-pong buffers of n * 128 u32 each; hist: radix_hist_words(n * 128)
+void ntc_csr_build(const Launch& L, const NtcDev& nd, const float* means, int64_t n, NtcCsr& csr, uint32_t* keys[2],
+                   uint32_t* vals[2], uint32_t* hist, uint64_t* tmp);
 void ntc_forward(const Launch& L, int precision, const NtcDev& nd, const void* table, const void* mlp,
                  const float* means, int64_t n, float* dmu, float* dq);
 // g_part holds max_parts x ntc_mlp_params() floats
 void ntc_backward(const Launch& L, int precision, const NtcDev& nd, const void* table, const void* mlp,
                   const float* means, int64_t n, const float* d_dmu, const float* d_dq, float* g_table, float* g_mlp,
-                  float* g_part, int max_parts);
+                  float* g_part, int max_parts, const NtcCsr* csr);
 void ntc_adam(const Launch& L, int precision, float* p, float* g, float* m, float* v, void* work, int64_t n, float lr,
               float b1, float b2, float eps, float bc1, float bc2);
 void ntc_refresh_work(const Launch& L, int precision, const float* p, void* work, int64_t n);

@@ -282,12 +282,15 @@ __device__ __forceinline__ float pow2_scale(float mx) {
     return ldexpf(1.0f, 13 - e);
 }
 
-template <class P>
+// kCSR: write the encoding gradient (n x 32 floats) to `denc` for the
+// per-entry gather of the prepared contribution lists; otherwise scatter-add
+// it into the table gradient with atomics.
+template <class P, bool kCSR>
 __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S* __restrict__ table,
                                                  const typename P::S* __restrict__ mlp, const float* __restrict__ means,
                                                  int64_t n, const float* __restrict__ d_dmu,
                                                  const float* __restrict__ d_dq, float* __restrict__ g_table,
-                                                 float* __restrict__ g_part) {
+                                                 float* __restrict__ g_part, float* __restrict__ denc) {
     using S = typename P::S;
     constexpr int kWElems = 64 * LD32 + 64 * LD64 + 32 * LD64 + 64 * LD64 + 64 * LD16;
     constexpr int kWBytes = (int)sizeof(S) * kWElems > kMlpParams * 4 ? (int)sizeof(S) * kWElems : kMlpParams * 4;
@@ -453,12 +456,18 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
 #pragma unroll
             for (int mt = 0; mt < 2; mt++) {
                 const f4v e = layer_tile<P, 64>(sW1t, LD64, mt * 16, H1, LD64, lane);
-                for (int r = 0; r < 4; r++) E[p * 33 + mt * 16 + 4 * g + r] = e[r] * inv;
+                if (kCSR) {
+                    if (valid)
+                        *reinterpret_cast<float4*>(denc + 32 * pt + mt * 16 + 4 * g) =
+                            make_float4(e[0] * inv, e[1] * inv, e[2] * inv, e[3] * inv);
+                } else {
+                    for (int r = 0; r < 4; r++) E[p * 33 + mt * 16 + 4 * g + r] = e[r] * inv;
+                }
             }
         }
         __syncthreads();
         // 8. scatter-add the encoding gradient into the table gradient
-        if (in) {
+        if (!kCSR && in) {
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const int lv = 4 * g + j;
@@ -493,6 +502,83 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
     __syncthreads();
     float* out = g_part + (int64_t)blockIdx.x * kMlpParams;
     for (int k = threadIdx.x; k < kMlpParams; k += blockDim.x) out[k] = red[k];
+}
+
+// ---------------------------------------------------------------------------
+// Per-frame contribution lists.  The means are frozen during Stage 1, so
+// every (point, level, corner) contribution to the table gradient has a fixed
+// entry and a fixed trilinear weight for the whole frame.  They are sorted
+// by entry once; each iteration then sums, per entry, weight x encoding
+// gradient of the contributing points (no atomics, fixed summation order).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_csr_contrib(NtcDev nd, const float* __restrict__ means, int64_t n,
+                                                     uint32_t sentinel, uint32_t* __restrict__ key,
+                                                     uint32_t* __restrict__ pid) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (point, level)
+    if (t >= n * 16) return;
+    const int64_t pt = t >> 4;
+    const int lv = (int)(t & 15);
+    const float mu[3] = {means[3 * pt], means[3 * pt + 1], means[3 * pt + 2]};
+    float x[3];
+    const bool in = ntc_normalise(nd, mu, x);
+    int64_t ent[8];
+    float wt[8];
+    ntc_corners(nd, lv, x, ent, wt);
+    for (int c = 0; c < 8; c++) {
+        key[8 * t + c] = in ? (uint32_t)ent[c] : sentinel;
+        pid[8 * t + c] = ((uint32_t)pt << 7) | ((uint32_t)lv << 3) | (uint32_t)c;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_csr_rows(const uint32_t* __restrict__ key, int64_t m, uint32_t sentinel,
+                                                  uint2* __restrict__ rows) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= m) return;
+    const uint32_t e = key[k];
+    if (e == sentinel) return;
+    if (k == 0 || key[k - 1] != e) rows[e].x = (uint32_t)k;
+    if (k == m - 1 || key[k + 1] != e) rows[e].y = (uint32_t)(k + 1);
+}
+
+__global__ __launch_bounds__(256) void k_csr_weights(NtcDev nd, const float* __restrict__ means,
+                                                     const uint32_t* __restrict__ key, const uint32_t* __restrict__ pid,
+                                                     int64_t m, uint32_t sentinel, float* __restrict__ w) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= m) return;
+    if (key[k] == sentinel) {
+        w[k] = 0.f;
+        return;
+    }
+    const uint32_t c = pid[k];
+    const int64_t pt = c >> 7;
+    const int lv = (c >> 3) & 15, corner = c & 7;
+    const float mu[3] = {means[3 * pt], means[3 * pt + 1], means[3 * pt + 2]};
+    float x[3];
+    ntc_normalise(nd, mu, x);
+    int64_t ent[8];
+    float wt[8];
+    ntc_corners(nd, lv, x, ent, wt);
+    w[k] = wt[corner];
+}
+
+__global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ rows, const uint32_t* __restrict__ pid,
+                                                    const float* __restrict__ w, const float* __restrict__ denc,
+                                                    int64_t entries, float* __restrict__ g_table) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= entries) return;
+    const uint2 r = rows[e];
+    float a0 = 0.f, a1 = 0.f;
+    for (uint32_t k = r.x; k < r.y; k++) {
+        const uint32_t c = pid[k];
+        const float2 d = *reinterpret_cast<const float2*>(denc + 32 * (int64_t)(c >> 7) + 2 * ((c >> 3) & 15));
+        const float wk = w[k];
+        a0 += wk * d.x;
+        a1 += wk * d.y;
+    }
+    if (r.y > r.x) {
+        g_table[2 * e] += a0;
+        g_table[2 * e + 1] += a1;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ part, int nparts, int len,
@@ -601,11 +687,21 @@ void fwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* 
 
 template <class P>
 void bwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* mlp, const float* means, int64_t n,
-              const float* d_dmu, const float* d_dq, float* g_table, float* g_mlp, float* g_part, int max_parts) {
+              const float* d_dmu, const float* d_dq, float* g_table, float* g_mlp, float* g_part, int max_parts,
+              const NtcCsr* csr) {
     const int64_t nb = (n + kPts - 1) / kPts;
     const unsigned grid = (unsigned)std::min<int64_t>((nb + kWaves - 1) / kWaves, max_parts);
-    hipLaunchKernelGGL((k_ntc_bwd<P>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
-                       (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part);
+    if (csr) {
+        hipLaunchKernelGGL((k_ntc_bwd<P, true>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
+                           (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, csr->denc);
+        if (L.prof) L.prof->end(L.st);
+        if (L.prof) L.prof->begin("ntc_scatter", L.st);
+        hipLaunchKernelGGL(k_csr_gather, dim3(nblk(csr->entries, 256)), dim3(256), 0, L.st, csr->rows, csr->pid,
+                           csr->w, csr->denc, csr->entries, g_table);
+    } else {
+        hipLaunchKernelGGL((k_ntc_bwd<P, false>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
+                           (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, (float*)nullptr);
+    }
     hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(kMlpParams, 256)), dim3(256), 0, L.st, g_part, (int)grid, kMlpParams,
                        g_mlp);
 }
@@ -629,15 +725,34 @@ void ntc_forward(const Launch& L, int precision, const NtcDev& nd, const void* t
 
 void ntc_backward(const Launch& L, int precision, const NtcDev& nd, const void* table, const void* mlp,
                   const float* means, int64_t n, const float* d_dmu, const float* d_dq, float* g_table, float* g_mlp,
-                  float* g_part, int max_parts) {
+                  float* g_part, int max_parts, const NtcCsr* csr) {
     if (n <= 0) return;
     if (L.prof) L.prof->begin("ntc_bwd", L.st);
     if (precision == 1)
-        bwd_impl<PF16>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts);
+        bwd_impl<PF16>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts, csr);
     else if (precision == 2)
-        bwd_impl<PBF16>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts);
+        bwd_impl<PBF16>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts, csr);
     else
-        bwd_impl<PF32>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts);
+        bwd_impl<PF32>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts, csr);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void ntc_csr_build(const Launch& L, const NtcDev& nd, const float* means, int64_t n, NtcCsr& csr, uint32_t* keys[2],
+                   uint32_t* vals[2], uint32_t* hist, uint64_t* tmp) {
+    const int64_t m = n * 128;
+    const uint32_t sentinel = (uint32_t)csr.entries;
+    int bits = 1;
+    while (((int64_t)1 << bits) <= csr.entries) bits++;
+    if (L.prof) L.prof->begin("ntc_prepare", L.st);
+    hipLaunchKernelGGL(k_csr_contrib, dim3(nblk(n * 16, 256)), dim3(256), 0, L.st, nd, means, n, sentinel, keys[0],
+                       vals[0]);
+    Launch inner{L.st, nullptr};
+    const int r = radix_sort_u32(inner, keys, vals, m, bits, hist, tmp);
+    csr.pid = vals[r];
+    fill_u32(inner, reinterpret_cast<uint32_t*>(csr.rows), 0u, 2 * csr.entries);
+    hipLaunchKernelGGL(k_csr_rows, dim3(nblk(m, 256)), dim3(256), 0, L.st, keys[r], m, sentinel, csr.rows);
+    hipLaunchKernelGGL(k_csr_weights, dim3(nblk(m, 256)), dim3(256), 0, L.st, nd, means, keys[r], csr.pid, m, sentinel,
+                       csr.w);
     if (L.prof) L.prof->end(L.st);
 }
 

@@ -67,6 +67,22 @@ __global__ __launch_bounds__(256) void k_emit(int64_t n, const uint32_t* __restr
         }
 }
 
+__global__ __launch_bounds__(256) void k_gpos_from_pairs(const uint64_t* __restrict__ keys,
+                                                         const uint32_t* __restrict__ vals, int64_t K,
+                                                         const uint2* __restrict__ rect,
+                                                         const uint64_t* __restrict__ goff, int tiles_x, uint64_t cap,
+                                                         uint32_t* __restrict__ gpos) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= K) return;
+    const uint32_t id = vals[p];
+    const uint32_t t = (uint32_t)(keys[p] >> 32);
+    const int tx = (int)(t % (uint32_t)tiles_x), ty = (int)(t / (uint32_t)tiles_x);
+    const uint2 r = rect[id];
+    const int tx0 = r.x & 0xFFFF, ty0 = r.x >> 16, tx1 = r.y & 0xFFFF;
+    const uint64_t k = goff[id] + (uint64_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+    if (k < cap) gpos[k] = (uint32_t)p;
+}
+
 __global__ __launch_bounds__(256) void k_zero_ranges(uint2* ranges, int ntiles) {
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t < ntiles) ranges[t] = make_uint2(0u, 0u);
@@ -83,68 +99,91 @@ __global__ __launch_bounds__(256) void k_ranges_from_keys(const uint64_t* __rest
 
 // ---------------------------------------------------------------------------
 // depth-first ordering.  The Gaussians are first sorted by (depth bits,
-// index).  The sorted sequence is cut into chunks of kBinChunk; one wave per
-// chunk walks its Gaussians in order and, for each, the tiles of its
-// rectangle (one tile per lane; the tiles of one Gaussian are distinct, so
-// the lanes never collide).  Pass 1 counts pairs per (tile, chunk); an
-// exclusive scan in tile-major order gives each (tile, chunk) its first
-// slot; pass 2 repeats the walk and writes Gaussian indices at consecutive
-// slots.  Inside a tile the result is ordered by (chunk, position in chunk),
-// i.e. by (depth bits, index): the order a stable (tile, depth) sort gives.
+// index).  The sorted sequence is cut into chunks of kBinChunk.  A workgroup
+// stages one chunk's tile rectangles in LDS; each of its four waves owns one
+// tile row and walks the chunk in order, taking 64 Gaussians per step and
+// visiting (ballot, lowest set bit first) those whose rectangle spans its
+// row; the lanes cover the rectangle's columns, so one wave updates each
+// tile's cursor and the tiles of one Gaussian never collide.  Pass 1 counts
+// pairs per (tile, chunk); an exclusive scan in tile-major order gives each
+// (tile, chunk) its first slot; pass 2 repeats the walk and writes Gaussian
+// indices at consecutive slots.  Inside a tile the result is ordered by
+// (chunk, position in chunk), i.e. by (depth bits, index): the order a stable
+// (tile, depth) sort gives.
 // ---------------------------------------------------------------------------
+constexpr int kBinRowsPerBlock = 4;
+
 template <bool kScatter>
-__global__ __launch_bounds__(64) void k_bin(const uint32_t* __restrict__ order, int64_t n,
-                                            const uint2* __restrict__ rect, const uint32_t* __restrict__ count,
-                                            int tiles_x, int ntiles, int64_t nchunks, uint32_t* __restrict__ hist,
-                                            const uint64_t* __restrict__ base, uint32_t cap,
-                                            uint32_t* __restrict__ vals) {
-    // ntiles counters (count pass) or write cursors (scatter pass).  A cursor
-    // starts at min(first slot, cap) and moves at most kBinChunk past it, so
-    // with cap < 2^31 it never wraps; slots at or past cap are not written.
-    extern __shared__ uint32_t s_cur[];
-    const int lane = threadIdx.x;
+__global__ __launch_bounds__(256) void k_bin_rows(const uint32_t* __restrict__ order, int64_t n,
+                                                  const uint2* __restrict__ rect, const uint32_t* __restrict__ count,
+                                                  int tiles_x, int tiles_y, int64_t nchunks,
+                                                  uint32_t* __restrict__ hist, const uint64_t* __restrict__ base,
+                                                  uint32_t cap, uint32_t* __restrict__ vals,
+                                                  const uint64_t* __restrict__ goff, uint32_t* __restrict__ gpos) {
+    // A cursor starts at min(first slot, cap) and moves at most kBinChunk
+    // past it, so with cap < 2^31 it never wraps; slots at or past cap are
+    // not written.
+    __shared__ uint2 s_rect[kBinChunk];
+    __shared__ uint32_t s_id[kBinChunk];
+    __shared__ uint32_t s_goff[kScatter ? kBinChunk : 1];
+    extern __shared__ uint32_t s_cur_all[];   // kBinRowsPerBlock x tiles_x cursors
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t chunk = blockIdx.x;
-    for (int t = lane; t < ntiles; t += 64) {
+    const int row = blockIdx.y * kBinRowsPerBlock + w;
+    uint32_t* s_cur = s_cur_all + w * tiles_x;
+    const int64_t e0 = chunk * kBinChunk;
+    const int m = (int)min((int64_t)kBinChunk, n - e0);
+    for (int e = threadIdx.x; e < m; e += 256) {
+        const uint32_t id = order[e0 + e];
+        s_id[e] = id;
+        s_rect[e] = count[id] ? rect[id] : make_uint2(0xFFFF0000u, 0u);   // empty: no row spans
         if (kScatter) {
-            const uint64_t b = base[(int64_t)t * nchunks + chunk];
-            s_cur[t] = b < (uint64_t)cap ? (uint32_t)b : cap;
-        } else {
-            s_cur[t] = 0;
+            const uint64_t go = goff[id];
+            s_goff[e] = go < (uint64_t)cap ? (uint32_t)go : cap;
         }
     }
-    __syncthreads();
-    const int64_t e0 = chunk * kBinChunk;
-    const int64_t e1 = min(e0 + (int64_t)kBinChunk, n);
-    for (int64_t eb = e0; eb < e1; eb += 64) {
-        // fetch 64 Gaussians of the chunk at once, then walk them in order
-        const int64_t e = eb + lane;
-        uint32_t id = 0, cnt = 0;
-        uint2 r = make_uint2(0u, 0u);
-        if (e < e1) {
-            id = order[e];
-            cnt = count[id];
-            if (cnt) r = rect[id];
-        }
-        const int m = (int)min((int64_t)64, e1 - eb);
-        for (int j = 0; j < m; j++) {
-            const uint32_t cj = __shfl(cnt, j, 64);
-            if (cj == 0) continue;
-            const uint32_t rx = __shfl(r.x, j, 64), ry = __shfl(r.y, j, 64);
-            const uint32_t idj = __shfl(id, j, 64);
-            const int tx0 = rx & 0xFFFF, ty0 = rx >> 16, tx1 = ry & 0xFFFF;
-            const int w = tx1 - tx0 + 1;
-            for (uint32_t k = lane; k < cj; k += 64) {
-                const int t = (ty0 + (int)k / w) * tiles_x + tx0 + (int)k % w;
-                const uint32_t pos = s_cur[t];
-                s_cur[t] = pos + 1u;
-                if (kScatter && pos < cap) vals[pos] = idj;
+    if (row < tiles_y) {
+        for (int tx = lane; tx < tiles_x; tx += 64) {
+            if (kScatter) {
+                const uint64_t b = base[((int64_t)row * tiles_x + tx) * nchunks + chunk];
+                s_cur[tx] = b < (uint64_t)cap ? (uint32_t)b : cap;
+            } else {
+                s_cur[tx] = 0u;
             }
         }
     }
-    if (!kScatter) {
-        __syncthreads();
-        for (int t = lane; t < ntiles; t += 64) hist[(int64_t)t * nchunks + chunk] = s_cur[t];
+    __syncthreads();
+    if (row >= tiles_y) return;
+    for (int eb = 0; eb < m; eb += 64) {
+        const int e = eb + lane;
+        bool covers = false;
+        if (e < m) {
+            const uint2 r = s_rect[e];
+            covers = (int)(r.x >> 16) <= row && row <= (int)(r.y >> 16);
+        }
+        uint64_t mask = __ballot(covers);
+        while (mask) {
+            const int j = __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            const uint2 r = s_rect[eb + j];
+            const uint32_t idj = s_id[eb + j];
+            const int tx0 = (int)(r.x & 0xFFFF), tx1 = (int)(r.y & 0xFFFF);
+            // slot of this Gaussian's k-th rectangle tile in its own pair range
+            const uint32_t k0 = kScatter ? s_goff[eb + j] + (uint32_t)((row - (int)(r.x >> 16)) * (tx1 - tx0 + 1)) : 0u;
+            for (int tx = tx0 + lane; tx <= tx1; tx += 64) {
+                const uint32_t pos = s_cur[tx];
+                s_cur[tx] = pos + 1u;
+                if (kScatter && pos < cap) {
+                    vals[pos] = idj;
+                    const uint32_t k = k0 + (uint32_t)(tx - tx0);
+                    if (k < cap) gpos[k] = pos;
+                }
+            }
+        }
     }
+    if (!kScatter)
+        for (int tx = lane; tx < tiles_x; tx += 64)
+            hist[((int64_t)row * tiles_x + tx) * nchunks + chunk] = s_cur[tx];
 }
 
 __global__ __launch_bounds__(256) void k_ranges_from_hist(const uint64_t* __restrict__ base,
@@ -183,7 +222,9 @@ __device__ __forceinline__ int tile_of_block(int b, int ntiles) {
 __global__ __launch_bounds__(kBlendThreads) void k_blend_fwd(CamDev cam, int ntiles, const uint2* __restrict__ ranges,
                                                               const uint32_t* __restrict__ vals,
                                                               const float4* __restrict__ rec, float* __restrict__ image,
-                                                              float* __restrict__ T_final, uint32_t* __restrict__ last_out) {
+                                                              float* __restrict__ T_final, uint32_t* __restrict__ last_out,
+                                                              uint32_t* __restrict__ tile_walk) {
+    __shared__ uint32_t s_walk;
     __shared__ float4 s_w0[kBlendThreads];
     __shared__ float4 s_w1[kBlendThreads];
     __shared__ float4 s_w2[kBlendThreads];
@@ -238,6 +279,11 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_fwd(CamDev cam, int nti
         T_final[p] = T;
         last_out[p] = last;
     }
+    if (threadIdx.x == 0) s_walk = 0u;
+    __syncthreads();
+    if (last) atomicMax(&s_walk, last);
+    __syncthreads();
+    if (threadIdx.x == 0) tile_walk[tile] = s_walk;
 }
 
 // ---------------------------------------------------------------------------
@@ -253,20 +299,25 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(CamDev cam, int nti
                                                               const float* __restrict__ d_image,
                                                               const float* __restrict__ T_final,
                                                               const uint32_t* __restrict__ last_in,
+                                                              const uint32_t* __restrict__ tile_walk,
+                                                              const uint32_t* __restrict__ walk_off,
+                                                              float* __restrict__ grec, uint32_t grec_cap,
                                                               float* __restrict__ accum) {
     __shared__ float4 s_w0[kBlendThreads];
     __shared__ float4 s_w1[kBlendThreads];
     __shared__ float4 s_w2[kBlendThreads];
     __shared__ uint32_t s_id[kBlendThreads];
-    __shared__ float s_g[kBlendThreads][10];
-    __shared__ uint32_t s_max;
+    __shared__ float s_g[4][9][kBlendThreads];   // per-wave sums, [wave][term][entry]
     const int tile = tile_of_block(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
+    const uint32_t maxlast = tile_walk[tile];
+    if (maxlast == 0) return;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
     const bool inside = px < cam.W && py < cam.H;
     const uint2 rg = ranges[tile];
     const uint32_t start = rg.x;
+    const uint32_t woff = walk_off[tile];
     const int64_t p = (int64_t)py * cam.W + px, P = (int64_t)cam.W * cam.H;
     float T = 1.0f;
     uint32_t last = 0;
@@ -278,16 +329,9 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(CamDev cam, int nti
         g1 = d_image[P + p];
         g2 = d_image[2 * P + p];
     }
-    if (threadIdx.x == 0) s_max = 0;
-    __syncthreads();
-    if (last) atomicMax(&s_max, last);
-    for (int k = threadIdx.x; k < kBlendThreads * 10; k += kBlendThreads) (&s_g[0][0])[k] = 0.f;
-    __syncthreads();
-    const uint32_t maxlast = s_max;
     const float fpx = (float)px, fpy = (float)py;
     float b0 = cam.bg[0], b1 = cam.bg[1], b2 = cam.bg[2];   // colour behind the current contributor
-    const int lane = threadIdx.x & 63;
-    if (maxlast == 0) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int64_t jb = ((int64_t)(maxlast - 1) / kBlendThreads) * kBlendThreads; jb >= 0; jb -= kBlendThreads) {
         const uint32_t e = (uint32_t)jb + threadIdx.x;
         if (e < maxlast) {
@@ -334,24 +378,26 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(CamDev cam, int nti
             }
             if (__any(act)) {
 #pragma unroll
-                for (int k = 0; k < 9; k++) gr[k] = wave_sum(gr[k]);
-                if (lane == 0) {
+                for (int k = 0; k < 9; k++) gr[k] = wave_sum_dpp(gr[k]);
+            }
+            if (lane == 0) {
 #pragma unroll
-                    for (int k = 0; k < 9; k++) atomicAdd(&s_g[j][k], gr[k]);
-                    s_g[j][9] = 1.0f;
-                }
+                for (int k = 0; k < 9; k++) s_g[wv][k][j] = gr[k];
             }
         }
         __syncthreads();
-        if ((int)threadIdx.x < cnt && s_g[threadIdx.x][9] != 0.f) {
-            float* a = accum + 9 * (int64_t)s_id[threadIdx.x];
+        if ((int)threadIdx.x < cnt) {
+            const uint32_t widx = woff + (uint32_t)jb + threadIdx.x;   // compact index of this walked entry
+            const bool fits = widx < grec_cap;
 #pragma unroll
             for (int k = 0; k < 9; k++) {
-                const float v = s_g[threadIdx.x][k];
-                if (v != 0.f) atomicAdd(a + k, v);
-                s_g[threadIdx.x][k] = 0.f;
+                const float v = ((s_g[0][k][threadIdx.x] + s_g[1][k][threadIdx.x]) + s_g[2][k][threadIdx.x]) +
+                                s_g[3][k][threadIdx.x];
+                if (fits)
+                    grec[(int64_t)k * grec_cap + widx] = v;
+                else if (v != 0.f)
+                    atomicAdd(accum + 9 * (int64_t)s_id[threadIdx.x] + k, v);
             }
-            s_g[threadIdx.x][9] = 0.f;
         }
         __syncthreads();
     }
@@ -371,14 +417,32 @@ __device__ __forceinline__ void quat_rot_adj(const float q[4], const float g[9],
 // the colour (SH and its view direction) and the transform.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussDev g, CamDev cam, const float* __restrict__ accum,
-                                                        GradsDev out) {
+                                                        GatherDev ga, GradsDev out) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= g.n) return;
     Geo o;
     if (!geo_forward(g, cam, i, o)) return;
     ColourCtx cc;
     colour_forward(g, cam, i, o, cc);
-    const float* a9 = accum + 9 * i;
+    // the nine 2D gradient terms: fallback atomics plus this Gaussian's walked
+    // entries, visited in its tile-rectangle order
+    float a9[9];
+    for (int k = 0; k < 9; k++) a9[k] = accum[9 * i + k];
+    {
+        const uint2 r = ga.rect[i];
+        const int tx0 = r.x & 0xFFFF, ty0 = r.x >> 16, tx1 = r.y & 0xFFFF, ty1 = r.y >> 16;
+        uint64_t k = ga.goff[i];
+        for (int ty = ty0; ty <= ty1; ty++)
+            for (int tx = tx0; tx <= tx1; tx++, k++) {
+                if (k >= ga.cap) continue;
+                const int t = ty * cam.tiles_x + tx;
+                const uint32_t rel = ga.gpos[k] - ga.ranges[t].x;
+                if (rel >= ga.tile_walk[t]) continue;
+                const uint32_t widx = ga.walk_off[t] + rel;
+                if (widx >= ga.grec_cap) continue;
+                for (int c = 0; c < 9; c++) a9[c] += ga.grec[(int64_t)c * ga.grec_cap + widx];
+            }
+    }
     const float du = a9[0], dv = a9[1], dA = a9[2], dB = a9[3], dC = a9[4], dop = a9[5];
     const float drgb[3] = {a9[6], a9[7], a9[8]};
     if (out.d_uv) { out.d_uv[2 * i] += du; out.d_uv[2 * i + 1] += dv; }
@@ -577,23 +641,35 @@ void ranges_from_keys(const Launch& L, const uint64_t* keys, int64_t K, int ntil
 }
 
 void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
-               int tiles_x, int ntiles, uint32_t* hist) {
+               int tiles_x, int tiles_y, uint32_t* hist) {
     const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_count", L.st);
-    hipLaunchKernelGGL((k_bin<false>), dim3((unsigned)nchunks), dim3(64), ntiles * sizeof(uint32_t), L.st, order, n,
-                       rect, count, tiles_x, ntiles, nchunks, hist, (const uint64_t*)nullptr, 0u, (uint32_t*)nullptr);
+    dim3 grid((unsigned)nchunks, (unsigned)((tiles_y + kBinRowsPerBlock - 1) / kBinRowsPerBlock));
+    hipLaunchKernelGGL((k_bin_rows<false>), grid, dim3(256), kBinRowsPerBlock * tiles_x * sizeof(uint32_t), L.st, order, n, rect, count, tiles_x, tiles_y, nchunks,
+                       hist, (const uint64_t*)nullptr, 0u, (uint32_t*)nullptr, (const uint64_t*)nullptr,
+                       (uint32_t*)nullptr);
     if (L.prof) L.prof->end(L.st);
 }
 
 void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
-                 int tiles_x, int ntiles, const uint64_t* base, uint64_t cap, uint32_t* vals) {
+                 int tiles_x, int tiles_y, const uint64_t* base, uint64_t cap, uint32_t* vals, const uint64_t* goff,
+                 uint32_t* gpos) {
     const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_scatter", L.st);
-    hipLaunchKernelGGL((k_bin<true>), dim3((unsigned)nchunks), dim3(64), ntiles * sizeof(uint32_t), L.st, order, n,
-                       rect, count, tiles_x, ntiles, nchunks, (uint32_t*)nullptr, base, (uint32_t)cap, vals);
+    dim3 grid((unsigned)nchunks, (unsigned)((tiles_y + kBinRowsPerBlock - 1) / kBinRowsPerBlock));
+    hipLaunchKernelGGL((k_bin_rows<true>), grid, dim3(256), kBinRowsPerBlock * tiles_x * sizeof(uint32_t), L.st,
+                       order, n, rect, count, tiles_x, tiles_y, nchunks, (uint32_t*)nullptr, base, (uint32_t)cap, vals,
+                       goff, gpos);
     if (L.prof) L.prof->end(L.st);
+}
+
+void gpos_from_pairs(const Launch& L, const uint64_t* keys, const uint32_t* vals, int64_t K, const uint2* rect,
+                     const uint64_t* goff, int tiles_x, uint64_t cap, uint32_t* gpos) {
+    if (K <= 0) return;
+    hipLaunchKernelGGL(k_gpos_from_pairs, dim3(blocks_for(K, 256)), dim3(256), 0, L.st, keys, vals, K, rect, goff,
+                       tiles_x, cap, gpos);
 }
 
 void ranges_from_hist(const Launch& L, const uint64_t* base, const uint64_t* total, int ntiles, int nchunks,
@@ -611,28 +687,29 @@ void pairs_total_check(const Launch& L, const uint64_t* total, uint64_t cap, int
 static unsigned blend_grid(int ntiles) { return (unsigned)(((ntiles + 7) / 8) * 8); }
 
 void blend_forward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals, const float4* rec,
-                   float* image, float* T_final, uint32_t* last) {
+                   float* image, float* T_final, uint32_t* last, uint32_t* tile_walk) {
     const int ntiles = cam.tiles_x * cam.tiles_y;
     if (L.prof) L.prof->begin("blend_fwd", L.st);
     hipLaunchKernelGGL(k_blend_fwd, dim3(blend_grid(ntiles)), dim3(kBlendThreads), 0, L.st, cam, ntiles, ranges, vals,
-                       rec, image, T_final, last);
+                       rec, image, T_final, last, tile_walk);
     if (L.prof) L.prof->end(L.st);
 }
 
 void blend_backward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals, const float4* rec,
-                    const float* d_image, const float* T_final, const uint32_t* last, float* accum) {
+                    const float* d_image, const float* T_final, const uint32_t* last, const GatherDev& ga,
+                    float* accum) {
     const int ntiles = cam.tiles_x * cam.tiles_y;
     if (L.prof) L.prof->begin("blend_bwd", L.st);
     hipLaunchKernelGGL(k_blend_bwd, dim3(blend_grid(ntiles)), dim3(kBlendThreads), 0, L.st, cam, ntiles, ranges, vals,
-                       rec, d_image, T_final, last, accum);
+                       rec, d_image, T_final, last, ga.tile_walk, ga.walk_off, ga.grec, (uint32_t)ga.grec_cap, accum);
     if (L.prof) L.prof->end(L.st);
 }
 
 void preprocess_backward(const Launch& L, const GaussDev& g, const CamDev& cam, const float* accum,
-                         const GradsDev& out) {
+                         const GatherDev& ga, const GradsDev& out) {
     if (g.n <= 0) return;
     if (L.prof) L.prof->begin("preprocess_bwd", L.st);
-    hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks_for(g.n, 256)), dim3(256), 0, L.st, g, cam, accum, out);
+    hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks_for(g.n, 256)), dim3(256), 0, L.st, g, cam, accum, ga, out);
     if (L.prof) L.prof->end(L.st);
 }
 

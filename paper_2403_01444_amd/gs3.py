@@ -41,7 +41,7 @@ class NtcConfigC(C.Structure):
 class ConfigC(C.Structure):
     _fields_ = [("max_gaussians", C.c_int64), ("max_pairs", C.c_int64), ("max_width", C.c_int32),
                 ("max_height", C.c_int32), ("num_slots", C.c_int32), ("sort_mode", C.c_int32),
-                ("enable_ntc", C.c_int32), ("reserved", C.c_int32), ("ntc", NtcConfigC)]
+                ("enable_ntc", C.c_int32), ("grad_record_log2", C.c_int32), ("ntc", NtcConfigC)]
 
 
 class GaussiansC(C.Structure):
@@ -65,7 +65,7 @@ class GradsC(C.Structure):
 
 
 EXPORTED = ("gs3_create", "gs3_destroy", "gs3_last_error", "gs3_set_stream", "gs3_ntc_num_params",
-            "gs3_ntc_load", "gs3_ntc_save", "gs3_ntc_forward", "gs3_ntc_backward", "gs3_ntc_step",
+            "gs3_ntc_load", "gs3_ntc_save", "gs3_ntc_forward", "gs3_ntc_backward", "gs3_ntc_prepare", "gs3_ntc_step",
             "gs3_ntc_grads", "gs3_ntc_zero_grads", "gs3_warmup_loss", "gs3_render", "gs3_render_backward",
             "gs3_loss", "gs3_adam", "gs3_zero", "gs3_debug_counts", "gs3_debug_pairs", "gs3_debug_ranges",
             "gs3_debug_gaussians", "gs3_debug_pixels", "gs3_check_flags", "gs3_profile_enable",
@@ -93,6 +93,7 @@ def lib():
         "gs3_ntc_save": [vp, vp, i64],
         "gs3_ntc_forward": [vp, vp, i64, vp, vp],
         "gs3_ntc_backward": [vp, vp, i64, vp, vp],
+        "gs3_ntc_prepare": [vp, vp, i64],
         "gs3_ntc_step": [vp, f32, f32, f32, f32],
         "gs3_ntc_grads": [vp, vp, i64],
         "gs3_ntc_zero_grads": [vp],
@@ -243,6 +244,11 @@ def gs3_ntc_backward(h, means, d_dmu, d_dq):
                                      _ptr(d_dq, numel=4 * n)))
 
 
+def gs3_ntc_prepare(h, means):
+    n = means.shape[0]
+    _check(h, lib().gs3_ntc_prepare(h, _ptr(means, numel=3 * n), n))
+
+
 def gs3_ntc_step(h, lr, beta1, beta2, eps):
     _check(h, lib().gs3_ntc_step(h, lr, beta1, beta2, eps))
 
@@ -338,7 +344,7 @@ def gs3_profile_query(h, kernel: str):
 # ---------------------------------------------------------------------------
 
 def make_config(max_gaussians: int, max_pairs: int, max_width: int, max_height: int, num_slots: int = 1,
-                sort_mode: str = "depth_first", ntc=None, precision: str = "f32") -> ConfigC:
+                sort_mode: str = "depth_first", ntc=None, precision: str = "f32", grad_record_log2: int = 0) -> ConfigC:
     cfg = ConfigC()
     cfg.max_gaussians = int(max_gaussians)
     cfg.max_pairs = int(max_pairs)
@@ -346,6 +352,7 @@ def make_config(max_gaussians: int, max_pairs: int, max_width: int, max_height: 
     cfg.num_slots = int(num_slots)
     cfg.sort_mode = SORT_MODES[sort_mode]
     cfg.enable_ntc = 1 if ntc is not None else 0
+    cfg.grad_record_log2 = int(grad_record_log2)
     if ntc is not None:
         cfg.ntc.levels, cfg.ntc.feats, cfg.ntc.log2_T, cfg.ntc.hidden = ntc.levels, ntc.feats, ntc.log2_T, ntc.hidden
         cfg.ntc.precision = PRECISIONS[precision]
@@ -362,7 +369,7 @@ class Context:
     """Owns one gs3 context; launches on torch's current stream by default."""
 
     def __init__(self, max_gaussians, max_pairs, max_width, max_height, num_slots=1, sort_mode="depth_first",
-                 ntc=None, precision="f32", device=None):
+                 ntc=None, precision="f32", device=None, grad_record_log2=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("gs3 needs a GPU (torch.cuda.is_available() is False)")
@@ -371,7 +378,7 @@ class Context:
         self.precision = precision
         with torch.cuda.device(self.device):
             self.h = gs3_create(make_config(max_gaussians, max_pairs, max_width, max_height, num_slots, sort_mode,
-                                            ntc, precision))
+                                            ntc, precision, grad_record_log2))
         self.use_current_stream()
         self.n_params = gs3_ntc_num_params(self.h) if ntc is not None else 0
 
@@ -415,6 +422,9 @@ class Context:
 
     def ntc_backward(self, means, d_dmu, d_dq):
         gs3_ntc_backward(self.h, means, d_dmu, d_dq)
+
+    def ntc_prepare(self, means):
+        gs3_ntc_prepare(self.h, means)
 
     def ntc_step(self, lr=0.002, beta1=0.9, beta2=0.99, eps=1e-15):
         gs3_ntc_step(self.h, lr, beta1, beta2, eps)

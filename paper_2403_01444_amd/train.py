@@ -44,6 +44,8 @@ class Stage1NTC:
         self.img, self.dimg = ctx.empty(3 * H * W), ctx.empty(3 * H * W)
         self.loss = ctx.empty(1)
         self.views = _Views(len(cams), seed)
+        # per-frame setup: the means stay frozen for the whole of Stage 1
+        ctx.ntc_prepare(gauss.means)
 
     def step(self) -> int:
         ctx, cam = self.ctx, None
@@ -111,6 +113,7 @@ def warmup(ctx: gs3.Context, points, iters: int = 3000, lr: float = 0.002, betas
     dmu, dq = ctx.empty(n, 3), ctx.empty(n, 4)
     loss = ctx.empty(1)
     gmu, gq = ctx.empty(n, 3), ctx.empty(n, 4)
+    ctx.ntc_prepare(points)          # the warm-up points stay fixed
     for _ in range(iters):
         ctx.ntc_forward(points, dmu, dq)
         gs3.gs3_warmup_loss(ctx.h, dmu, dq, loss, gmu, gq)
@@ -124,3 +127,46 @@ def psnr(img, target) -> float:
     d = (img.clamp(0, 1) - target.clamp(0, 1)).double()
     mse = float((d * d).mean())
     return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
+
+
+def logged_run(step, evaluate, iters: int, every: int = 10):
+    """Run `step` iters times; every `every` iterations record (iterations,
+    training seconds so far, evaluate()).  Training time is measured over
+    synchronised blocks of `every` steps and excludes the evaluations."""
+    import time
+
+    import torch
+    log = []
+    t_train = 0.0
+    done = 0
+    while done < iters:
+        k = min(every, iters - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            step()
+        torch.cuda.synchronize()
+        t_train += time.perf_counter() - t0
+        done += k
+        log.append((done, t_train, evaluate()))
+    return log
+
+
+def equal_psnr(ntc_log, direct_log, ntc_iters: int = 150, slack_db: float = 0.1):
+    """NTC at `ntc_iters` iterations reaches P*; the direct optimiser's time to
+    reach P* - slack is the wall time of its first logged point at or above
+    it (None if never).  Returns a dict of the comparison."""
+    at = [r for r in ntc_log if r[0] == ntc_iters]
+    if not at:
+        raise ValueError("the NTC log has no point at the requested iteration")
+    _, t_ntc, p_star = at[0]
+    hit = [r for r in direct_log if r[2] >= p_star - slack_db]
+    d150 = [r for r in direct_log if r[0] == ntc_iters]
+    return {
+        "ntc_iters": ntc_iters, "ntc_psnr": p_star, "ntc_seconds": t_ntc,
+        "direct_iters_to_match": hit[0][0] if hit else None,
+        "direct_seconds_to_match": hit[0][1] if hit else None,
+        "direct_psnr_at_same_iters": d150[0][2] if d150 else None,
+        "direct_seconds_at_same_iters": d150[0][1] if d150 else None,
+        "direct_best_psnr": max(r[2] for r in direct_log),
+    }

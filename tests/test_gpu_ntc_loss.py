@@ -47,9 +47,10 @@ def ntc_ctx(cfg, n, precision):
     return gs3.Context(n, 1 << 10, 16, 16, ntc=cfg, precision=precision)
 
 
+@pytest.mark.parametrize("prepared", [False, True])
 @pytest.mark.parametrize("precision", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("n", [1, 37, 5000, 50000])
-def test_ntc_forward_backward(precision, n):
+def test_ntc_forward_backward(precision, n, prepared):
     cfg = synth.NTCConfig()
     params, spec = trained_like_params(cfg, 1)
     rng = np.random.default_rng(n)
@@ -68,6 +69,8 @@ def test_ntc_forward_backward(precision, n):
     assert near.mean() < 0.02, near.mean()
     g_mu[near] = 0.0
     g_q[near] = 0.0
+    if prepared:
+        ctx.ntc_prepare(m)
     ctx.ntc_backward(m, cuda(g_mu), cuda(g_q))
     grad = ctx.ntc_grads().cpu().numpy()
     ref_g = ontc.backward(spec, params, cache, g_mu, g_q, precision)
@@ -137,4 +140,27 @@ def test_loss_matches_oracle(lam, hw):
     L, dL = oloss.stage1_loss(x.astype(np.float64), y.astype(np.float64), lam)
     assert abs(loss.item() - L) < 1e-5 * max(1, abs(L))
     assert rel_err(d.cpu().numpy(), dL) < 1e-4, rel_err(d.cpu().numpy(), dL)
+    ctx.close()
+
+
+def test_prepared_backward_is_deterministic_and_accumulates():
+    cfg = synth.NTCConfig()
+    params, spec = trained_like_params(cfg, 5)
+    n = 20000
+    rng = np.random.default_rng(9)
+    means = cuda(rng.uniform(-1.1, 1.1, size=(n, 3)).astype(np.float32))
+    gm, gq = cuda(rng.normal(size=(n, 3)).astype(np.float32)), cuda(rng.normal(size=(n, 4)).astype(np.float32))
+    ctx = ntc_ctx(cfg, n, "f16")
+    ctx.ntc_load(params)
+    ctx.ntc_prepare(means)
+    ctx.ntc_backward(means, gm, gq)
+    a = ctx.ntc_grads().cpu().numpy()
+    ctx.ntc_zero_grads()
+    ctx.ntc_backward(means, gm, gq)
+    b = ctx.ntc_grads().cpu().numpy()
+    t = spec.n_table
+    assert np.array_equal(a[:t], b[:t])          # the table part has a fixed summation order
+    ctx.ntc_backward(means, gm, gq)
+    c = ctx.ntc_grads().cpu().numpy()
+    np.testing.assert_allclose(c, 2 * b, rtol=1e-5, atol=1e-9)
     ctx.close()

@@ -20,8 +20,9 @@ def _gs3():
     return gs3
 
 
-def make_ctx(n, cam, sort_mode="depth_first", max_pairs=1 << 22):
-    return _gs3().Context(max(n, 1), max_pairs, cam.width, cam.height, sort_mode=sort_mode)
+def make_ctx(n, cam, sort_mode="depth_first", max_pairs=1 << 22, grad_record_log2=0):
+    return _gs3().Context(max(n, 1), max_pairs, cam.width, cam.height, sort_mode=sort_mode,
+                          grad_record_log2=grad_record_log2)
 
 
 def rand_transform(n, seed, mu_sigma=0.02, q_sigma=0.2):
@@ -108,11 +109,14 @@ def _grads_gpu(ctx, g, dmu, dq, full):
     return {k: torch.zeros(s, dtype=torch.float32, device="cuda") for k, s in shapes.items()}
 
 
-@pytest.mark.parametrize("name,seed,full", [("small-2k-64px", 4, False), ("grad-200-32px", 5, True),
-                                            ("ring-50k-256px", 6, False)])
-def test_gradients_match_oracle(name, seed, full):
+@pytest.mark.parametrize("name,seed,full,sort_mode,rec_log2", [
+    ("small-2k-64px", 4, False, "depth_first", 0), ("grad-200-32px", 5, True, "depth_first", 0),
+    ("ring-50k-256px", 6, False, "depth_first", 0), ("small-2k-64px", 4, False, "radix64", 0),
+    # per-pair record buffer of 16 entries: nearly every pair takes the atomic fallback
+    ("small-2k-64px", 4, True, "depth_first", 4)])
+def test_gradients_match_oracle(name, seed, full, sort_mode, rec_log2):
     g, cam, dmu, dq = _scene(name, seed, True)
-    ctx = make_ctx(g.n, cam, max_pairs=1 << 24)
+    ctx = make_ctx(g.n, cam, sort_mode=sort_mode, max_pairs=1 << 24, grad_record_log2=rec_log2)
     gg = _gs3().GaussiansGPU.from_host(g)
     tdmu, tdq = cuda(dmu), cuda(dq)
     ctx.render(gg, cam, tdmu, tdq)
@@ -189,4 +193,22 @@ def test_invalid_arguments_return_errors():
     with pytest.raises(gs3.GS3Error) as e:
         ctx.render_backward(torch.zeros(3, 32, 32, device="cuda"), {}, slot=0)
     assert e.value.status == gs3.GS3_ESTATE
+    ctx.close()
+
+
+def test_backward_is_deterministic():
+    """Without the atomic fallback the backward has a fixed summation order."""
+    g, cam, dmu, dq = _scene("ring-50k-256px", 11, True)
+    ctx = make_ctx(g.n, cam, max_pairs=1 << 24)
+    gg = _gs3().GaussiansGPU.from_host(g)
+    tdmu, tdq = cuda(dmu), cuda(dq)
+    ctx.render(gg, cam, tdmu, tdq)
+    w = cuda(np.random.default_rng(0).normal(size=(3, cam.height, cam.width)).astype(np.float32))
+    outs = []
+    for _ in range(2):
+        grads = _grads_gpu(ctx, g, dmu, dq, False)
+        ctx.render_backward(w, grads)
+        outs.append({k: v.cpu().numpy() for k, v in grads.items()})
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
     ctx.close()
