@@ -71,8 +71,11 @@ typedef struct {
     int32_t num_slots;               /* renders whose state is kept for backward, 1..8 */
     int32_t sort_mode;               /* GS3_SORT_DEPTH_FIRST (default) | GS3_SORT_RADIX64 */
     int32_t enable_ntc;              /* 0: rasterizer only */
-    int32_t grad_record_log2;        /* log2 capacity of the backward blend's per-pair gradient
-                                        records (0 = 23); pairs past it use atomics */
+    int32_t grad_record_log2;        /* 0: the backward blend accumulates per-Gaussian gradients
+                                        with atomics (fastest).  k > 0: deterministic mode, each
+                                        walked (tile, Gaussian) pair writes its sums to a record
+                                        buffer of 2^k pairs, gathered per Gaussian in a fixed order;
+                                        pairs past the buffer fall back to atomics */
     gs3_ntc_config ntc;
 } gs3_config;
 
@@ -140,6 +143,22 @@ const char* gs3_last_error(const gs3_ctx* ctx);
 /* Launch all further work of this context on `hip_stream` (a hipStream_t;
  * NULL = the default stream). */
 gs3_status gs3_set_stream(gs3_ctx* ctx, void* hip_stream);
+
+/* ---- Per-frame setup ------------------------------------------------------ */
+
+/* Spatial order of n means: perm (n u32, DEVICE) lists the indices sorted
+ * by the 30-bit Morton code of (mean - aabb_min) * inv_extent (clamped to
+ * [0, 1], 10 bits per axis), ties by index.  Stage 1 keeps the Gaussians
+ * frozen for the whole frame (Sec. 4.1), so reordering them once per frame
+ * is free to choose; neighbouring Gaussians then share hash-grid cells and
+ * cache lines. */
+gs3_status gs3_morton_order(gs3_ctx* ctx, const float* means, int64_t n, const float aabb_min[3],
+                            const float inv_extent[3], uint32_t* perm);
+
+/* dst[i, :] = src[perm[i], :] for n rows of row_floats floats (DEVICE;
+ * dst must not alias src). */
+gs3_status gs3_gather_rows(gs3_ctx* ctx, const float* src, const uint32_t* perm, int64_t n, int32_t row_floats,
+                           float* dst);
 
 /* ---- Neural Transformation Cache (Sec. 4.1, Eq. 5) ----------------------- */
 

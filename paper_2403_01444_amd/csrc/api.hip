@@ -176,8 +176,8 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
     for (auto& s : c->slots) {
         ok = ok && c->alloc(&s.rec, 3 * N) && c->alloc(&s.key, N) && c->alloc(&s.rect, N) && c->alloc(&s.count, N) &&
              c->alloc(&s.vals[0], PK) && c->alloc(&s.ranges, c->max_tiles) && c->alloc(&s.T_final, PX) &&
-             c->alloc(&s.last, PX) && c->alloc(&s.total, 1) && c->alloc(&s.goff, N) && c->alloc(&s.gpos, PK) &&
-             c->alloc(&s.tile_walk, c->max_tiles);
+             c->alloc(&s.last, PX) && c->alloc(&s.total, 1) && c->alloc(&s.goff, N) &&
+             c->alloc(&s.gpos, cfg->grad_record_log2 > 0 ? PK : 1) && c->alloc(&s.tile_walk, c->max_tiles);
         if (ok && cfg->sort_mode == GS3_SORT_RADIX64)
             ok = c->alloc(&s.vals[1], PK) && c->alloc(&s.pkeys[0], PK) && c->alloc(&s.pkeys[1], PK);
     }
@@ -191,9 +191,8 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
          c->alloc(&c->flags, 4) && c->alloc(&c->loss_maps, loss_map_floats(cfg->max_height, cfg->max_width)) &&
          c->alloc(&c->walk_off, c->max_tiles) && c->alloc(&c->walk_total, 1) && c->alloc(&c->goff_total, 1) &&
          c->alloc(&c->loss_bsum, 2 * (int64_t)loss_blocks(cfg->max_height, cfg->max_width));
-    {
-        const int lg = cfg->grad_record_log2 > 0 ? std::min(cfg->grad_record_log2, 30) : 23;
-        c->grec_cap = std::min<int64_t>(PK, (int64_t)1 << lg);
+    if (cfg->grad_record_log2 > 0) {
+        c->grec_cap = std::min<int64_t>(PK, (int64_t)1 << std::min(cfg->grad_record_log2, 30));
         ok = ok && c->alloc(&c->grec, 9 * c->grec_cap);
     }
     if (ok && cfg->sort_mode == GS3_SORT_DEPTH_FIRST)
@@ -227,7 +226,7 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
         }
         c->n_table_floats = off * 2;
         c->n_params = c->n_table_floats + ntc_mlp_params();
-        c->max_parts = 2048;
+        c->max_parts = 512;   // one workgroup per CU pair: the backward loops over its point batches
         ok = c->alloc(&c->p, c->n_params) && c->alloc(&c->g, c->n_params) && c->alloc(&c->m, c->n_params) &&
              c->alloc(&c->v, c->n_params) && c->alloc((float**)&c->work, c->n_params) &&
              c->alloc(&c->g_part, (int64_t)c->max_parts * ntc_mlp_params()) && c->alloc(&c->warm_bsum, (N + 255) / 256);
@@ -266,6 +265,31 @@ gs3_status gs3_set_stream(gs3_ctx* ctx, void* hip_stream) {
     if (!ctx) return GS3_EINVAL;
     ctx->st = (hipStream_t)hip_stream;
     return GS3_OK;
+}
+
+/* ---- per-frame setup ------------------------------------------------------ */
+
+gs3_status gs3_morton_order(gs3_ctx* c, const float* means, int64_t n, const float aabb_min[3],
+                            const float inv_extent[3], uint32_t* perm) {
+    if (!c) return GS3_EINVAL;
+    if (n < 0 || n > c->cfg.max_gaussians || (n > 0 && (!means || !perm)) || !aabb_min || !inv_extent)
+        return c->fail(GS3_EINVAL, "morton_order: bad arguments");
+    if (n == 0) return GS3_OK;
+    Launch L = c->L();
+    morton_codes(L, means, n, aabb_min, inv_extent, c->dkeys[0], c->dvals[0]);
+    const int r = radix_sort_u32(L, c->dkeys, c->dvals, n, 30, c->radix_hist, c->scan_tmp);
+    if (hipMemcpyAsync(perm, c->dvals[r], (size_t)n * 4, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "morton_order: copy failed");
+    return c->check_launch("morton_order");
+}
+
+gs3_status gs3_gather_rows(gs3_ctx* c, const float* src, const uint32_t* perm, int64_t n, int32_t row_floats,
+                           float* dst) {
+    if (!c) return GS3_EINVAL;
+    if (n < 0 || row_floats < 1 || (n > 0 && (!src || !perm || !dst || src == dst)))
+        return c->fail(GS3_EINVAL, "gather_rows: bad arguments");
+    gather_rows(c->L(), src, perm, n, row_floats, dst);
+    return c->check_launch("gather_rows");
 }
 
 /* ---- NTC ---------------------------------------------------------------- */
@@ -471,7 +495,7 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
             bin_count(L, order, n, sl.rect, sl.count, cd.tiles_x, cd.tiles_y, c->bin_hist);
             scan_u32_to_u64(L, c->bin_hist, (int64_t)ntiles * nchunks, c->bin_base, sl.total, c->scan_tmp);
             bin_scatter(L, order, n, sl.rect, sl.count, cd.tiles_x, cd.tiles_y, c->bin_base, cap, sl.vals[0],
-                        sl.goff, sl.gpos);
+                        sl.goff, c->grec_cap > 0 ? sl.gpos : nullptr);
             ranges_from_hist(L, c->bin_base, sl.total, ntiles, (int)nchunks, cap, sl.ranges, c->flags);
         } else {
             fill_u32(L, (uint32_t*)sl.ranges, 0u, 2 * (int64_t)ntiles);
@@ -494,7 +518,9 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
         while ((1 << tb) < ntiles) tb++;
         sl.cur = radix_sort_u64(L, sl.pkeys, sl.vals, (int64_t)K, 32 + tb, c->radix_hist, c->scan_tmp);
         ranges_from_keys(L, sl.pkeys[sl.cur], (int64_t)K, ntiles, sl.ranges);
-        gpos_from_pairs(L, sl.pkeys[sl.cur], sl.vals[sl.cur], (int64_t)K, sl.rect, sl.goff, cd.tiles_x, cap, sl.gpos);
+        if (c->grec_cap > 0)
+            gpos_from_pairs(L, sl.pkeys[sl.cur], sl.vals[sl.cur], (int64_t)K, sl.rect, sl.goff, cd.tiles_x, cap,
+                            sl.gpos);
     }
     blend_forward(L, cd, sl.ranges, sl.vals[sl.cur], sl.rec, image, sl.T_final, sl.last, sl.tile_walk);
     gs3_status st = c->check_launch("render");
@@ -515,12 +541,13 @@ gs3_status gs3_render_backward(gs3_ctx* c, int32_t slot, const float* d_image, c
     const int64_t n = sl.g.n;
     const int ntiles = sl.cam.tiles_x * sl.cam.tiles_y;
     fill_f32(L, c->accum, 0.f, 9 * n);
-    scan_u32_to_u32(L, sl.tile_walk, ntiles, c->walk_off, c->walk_total, c->scan_tmp);
+    if (c->grec_cap > 0) scan_u32_to_u32(L, sl.tile_walk, ntiles, c->walk_off, c->walk_total, c->scan_tmp);
     GatherDev ga;
     ga.rect = sl.rect; ga.goff = sl.goff; ga.gpos = sl.gpos; ga.ranges = sl.ranges; ga.tile_walk = sl.tile_walk;
     ga.walk_off = c->walk_off; ga.grec = c->grec; ga.grec_cap = (uint64_t)c->grec_cap;
     ga.cap = (uint64_t)c->cfg.max_pairs;
-    blend_backward(L, sl.cam, sl.ranges, sl.vals[sl.cur], sl.rec, d_image, sl.T_final, sl.last, ga, c->accum);
+    blend_backward(L, sl.cam, sl.ranges, sl.vals[sl.cur], sl.rec, d_image, sl.T_final, sl.last, ga, c->accum,
+                   out->d_opacity != nullptr || out->d_opacity_logits != nullptr);
     GradsDev gd;
     gd.d_means = out->d_means; gd.d_quats = out->d_quats; gd.d_log_scales = out->d_log_scales;
     gd.d_opac = out->d_opacity_logits; gd.d_sh = out->d_sh; gd.d_dmu = sl.g.dmu ? out->d_dmu : nullptr;

@@ -32,7 +32,7 @@ struct GaussDev {
 };
 
 // Blend record of one Gaussian, three 16-byte words:
-//   w0 = (u, v, A, B), w1 = (C, opacity, r, g), w2 = (b, box x0|y0<<16, box x1|y1<<16, 0)
+//   w0 = (u, v, A, B), w1 = (C, opacity, r, g), w2 = (b, box x0|y0<<16, box x1|y1<<16, ln(1/(255 opacity)))
 // with the conic stored so that power = -(A dx^2 + C dy^2)/2 - B dx dy.
 
 // exp used for the scale activation.  It is part of the single-precision
@@ -300,17 +300,25 @@ __device__ __forceinline__ void colour_forward(const GaussDev& g, const CamDev& 
 // alpha of a Gaussian record at pixel (px, py); false when the candidate is
 // skipped (power > 0 or alpha < 1/255).  Used identically by the forward and
 // backward blend so that both walk the same contributors.
-__device__ __forceinline__ bool blend_alpha(float px, float py, const float4& w0, const float4& w1,
+// pthr = ln(1 / (255 opacity)) (record word w2.w): a candidate with power
+// below it has alpha < 1/255 and is rejected without the exp; the exact
+// alpha test below stays the deciding one for the rest.
+__device__ __forceinline__ bool blend_alpha(float px, float py, const float4& w0, const float4& w1, float pthr,
                                             float& dx, float& dy, float& G, float& raw, float& alpha) {
 #pragma clang fp contract(off)
     dx = px - w0.x;
     dy = py - w0.y;
     float power = -0.5f * (w0.z * dx * dx + w1.x * dy * dy) - w0.w * dx * dy;
-    if (power > 0.0f) return false;
+    if (power > 0.0f || power < pthr) return false;
     G = __expf(power);
     raw = w1.y * G;
     alpha = fminf(0.99f, raw);
     return alpha >= (1.0f / 255.0f);
+}
+
+// does the pixel box cover the whole tile [x0, x1] x [y0, y1]?
+__device__ __forceinline__ bool box_covers(uint32_t b0, uint32_t b1, int x0, int y0, int x1, int y1) {
+    return (int)(b0 & 0xFFFFu) <= x0 && (int)(b0 >> 16) <= y0 && (int)(b1 & 0xFFFFu) >= x1 && (int)(b1 >> 16) >= y1;
 }
 
 __device__ __forceinline__ bool box_contains(uint32_t b0, uint32_t b1, int px, int py) {
@@ -328,6 +336,38 @@ template <int kCtrl, int kRowMask>
 __device__ __forceinline__ float dpp_add(float x) {
     const int moved = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kCtrl, kRowMask, 0xF, false);
     return x + __builtin_bit_cast(float, moved);
+}
+
+// Eight per-lane values -> their eight wave sums, spread over lane groups:
+// after the call, every lane of the 8-lane group g (lanes 8g..8g+7) holds
+// the total of term g.  Two exchanges halve the set (lanes ^32 swap four
+// terms, lanes ^16 swap two), a third (^8, DPP row_ror:8) leaves one term per
+// lane, then DPP sums the 8-lane group: 10 moves instead of 8 x 6.
+__device__ __forceinline__ float wave_reduce_scatter8(const float v[8], int lane) {
+    float a[4], b[2], c;
+    const bool hi32 = lane & 32, hi16 = lane & 16, hi8 = lane & 8;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const float send = hi32 ? v[k] : v[4 + k];
+        const float keep = hi32 ? v[4 + k] : v[k];
+        a[k] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const float send = hi16 ? a[k] : a[2 + k];
+        const float keep = hi16 ? a[2 + k] : a[k];
+        b[k] = keep + __shfl_xor(send, 16, 64);
+    }
+    {
+        const float send = hi8 ? b[0] : b[1];
+        const float keep = hi8 ? b[1] : b[0];
+        const int moved = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, send), 0x128, 0xF, 0xF, false);
+        c = keep + __builtin_bit_cast(float, moved);   // row_ror:8 pairs lane i with lane i ^ 8
+    }
+    c = dpp_add<0xB1, 0xF>(c);    // quad_perm [1,0,3,2]
+    c = dpp_add<0x4E, 0xF>(c);    // quad_perm [2,3,0,1]
+    c = dpp_add<0x141, 0xF>(c);   // row_half_mirror: the 8-lane group total in every lane
+    return c;                     // term index: (lane >> 5) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1)
 }
 
 // Sum over the 64 lanes with DPP moves (no LDS traffic); the result is

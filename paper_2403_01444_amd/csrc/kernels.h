@@ -36,6 +36,10 @@ int radix_sort_u32(const Launch& L, uint32_t* keys[2], uint32_t* vals[2], int64_
 int radix_sort_u64(const Launch& L, uint64_t* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist,
                    uint64_t* tmp);
 
+void morton_codes(const Launch& L, const float* means, int64_t n, const float lo[3], const float inv[3],
+                  uint32_t* code, uint32_t* idx);
+void gather_rows(const Launch& L, const float* src, const uint32_t* perm, int64_t n, int rf, float* dst);
+
 void fill_u32(const Launch& L, uint32_t* p, uint32_t v, int64_t n);
 void fill_f32(const Launch& L, float* p, float v, int64_t n);
 void iota_u32(const Launch& L, uint32_t* p, int64_t n);
@@ -83,7 +87,7 @@ void blend_forward(const Launch& L, const CamDev& cam, const uint2* ranges, cons
                    float* image, float* T_final, uint32_t* last, uint32_t* tile_walk);
 void blend_backward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals,
                     const float4* rec, const float* d_image, const float* T_final, const uint32_t* last,
-                    const GatherDev& ga, float* accum);
+                    const GatherDev& ga, float* accum, bool want_opacity);
 
 struct GradsDev {
     float *d_means, *d_quats, *d_log_scales, *d_opac, *d_sh, *d_dmu, *d_dq;

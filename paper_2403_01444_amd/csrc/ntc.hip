@@ -561,33 +561,48 @@ __global__ __launch_bounds__(256) void k_csr_weights(NtcDev nd, const float* __r
     w[k] = wt[corner];
 }
 
+// 8 lanes per table entry: the entry's contributions are read 8 at a time
+// (coalesced), each lane gathers its point's encoding gradient, and the group
+// sums with DPP (pairs, quads, half-row mirror): fixed order.
 __global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ rows, const uint32_t* __restrict__ pid,
                                                     const float* __restrict__ w, const float* __restrict__ denc,
                                                     int64_t entries, float* __restrict__ g_table) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= entries) return;
-    const uint2 r = rows[e];
+    const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 3;
+    const int sub = threadIdx.x & 7;
+    uint2 r = make_uint2(0u, 0u);
+    if (e < entries) r = rows[e];
     float a0 = 0.f, a1 = 0.f;
-    for (uint32_t k = r.x; k < r.y; k++) {
+    for (uint32_t k = r.x + sub; k < r.y; k += 8) {
         const uint32_t c = pid[k];
         const float2 d = *reinterpret_cast<const float2*>(denc + 32 * (int64_t)(c >> 7) + 2 * ((c >> 3) & 15));
         const float wk = w[k];
         a0 += wk * d.x;
         a1 += wk * d.y;
     }
-    if (r.y > r.x) {
+    a0 = dpp_add<0xB1, 0xF>(a0);
+    a0 = dpp_add<0x4E, 0xF>(a0);
+    a0 = dpp_add<0x141, 0xF>(a0);
+    a1 = dpp_add<0xB1, 0xF>(a1);
+    a1 = dpp_add<0x4E, 0xF>(a1);
+    a1 = dpp_add<0x141, 0xF>(a1);
+    if (sub == 0 && e < entries && r.y > r.x) {
         g_table[2 * e] += a0;
         g_table[2 * e + 1] += a1;
     }
 }
 
+// Sum the per-workgroup weight-gradient rows: blockIdx.y takes a slice of
+// the rows, blockIdx.x a range of columns; one atomic per (slice, column).
+constexpr int kPartSlice = 32;
 __global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ part, int nparts, int len,
                                                       float* __restrict__ dst) {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= len) return;
+    const int b0 = blockIdx.y * kPartSlice;
+    const int b1 = min(b0 + kPartSlice, nparts);
     float s = 0.f;
-    for (int b = 0; b < nparts; b++) s += part[(int64_t)b * len + k];
-    dst[k] += s;
+    for (int b = b0; b < b1; b++) s += part[(int64_t)b * len + k];
+    atomicAdd(dst + k, s);
 }
 
 template <class P>
@@ -696,14 +711,14 @@ void bwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* 
                            (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, csr->denc);
         if (L.prof) L.prof->end(L.st);
         if (L.prof) L.prof->begin("ntc_scatter", L.st);
-        hipLaunchKernelGGL(k_csr_gather, dim3(nblk(csr->entries, 256)), dim3(256), 0, L.st, csr->rows, csr->pid,
+        hipLaunchKernelGGL(k_csr_gather, dim3(nblk(csr->entries * 8, 256)), dim3(256), 0, L.st, csr->rows, csr->pid,
                            csr->w, csr->denc, csr->entries, g_table);
     } else {
         hipLaunchKernelGGL((k_ntc_bwd<P, false>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
                            (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, (float*)nullptr);
     }
-    hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(kMlpParams, 256)), dim3(256), 0, L.st, g_part, (int)grid, kMlpParams,
-                       g_mlp);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(kMlpParams, 256), (grid + kPartSlice - 1) / kPartSlice), dim3(256), 0,
+                       L.st, g_part, (int)grid, kMlpParams, g_mlp);
 }
 
 }  // namespace

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussDev g, CamDev cam, floa
     rec[3 * i + 0] = make_float4(o.u, o.v, A, B);
     rec[3 * i + 1] = make_float4(C, op, fmaxf(cc.raw[0], 0.f), fmaxf(cc.raw[1], 0.f));
     rec[3 * i + 2] = make_float4(fmaxf(cc.raw[2], 0.f), __uint_as_float(pack16(o.x0, o.y0)),
-                                 __uint_as_float(pack16(o.x1, o.y1)), 0.f);
+                                 __uint_as_float(pack16(o.x1, o.y1)), -logf(255.0f * op));
     const int tx0 = o.x0 / kTile, ty0 = o.y0 / kTile, tx1 = o.x1 / kTile, ty1 = o.y1 / kTile;
     rect[i] = make_uint2(pack16(tx0, ty0), pack16(tx1, ty1));
     count[i] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_bin_rows(const uint32_t* __restrict__ o
         s_id[e] = id;
         s_rect[e] = count[id] ? rect[id] : make_uint2(0xFFFF0000u, 0u);   // empty: no row spans
         if (kScatter) {
-            const uint64_t go = goff[id];
+            const uint64_t go = gpos ? goff[id] : 0u;
             s_goff[e] = go < (uint64_t)cap ? (uint32_t)go : cap;
         }
     }
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_bin_rows(const uint32_t* __restrict__ o
                 if (kScatter && pos < cap) {
                     vals[pos] = idj;
                     const uint32_t k = k0 + (uint32_t)(tx - tx0);
-                    if (k < cap) gpos[k] = pos;
+                    if (gpos && k < cap) gpos[k] = pos;
                 }
             }
         }
@@ -228,10 +228,13 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_fwd(CamDev cam, int nti
     __shared__ float4 s_w0[kBlendThreads];
     __shared__ float4 s_w1[kBlendThreads];
     __shared__ float4 s_w2[kBlendThreads];
+    __shared__ uint8_t s_full[kBlendThreads];
     const int tile = tile_of_block(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+    const int tx0p = tx * kTile, ty0p = ty * kTile;
+    const int tx1p = min(tx0p + kTile - 1, cam.W - 1), ty1p = min(ty0p + kTile - 1, cam.H - 1);
     const bool inside = px < cam.W && py < cam.H;
     const uint2 rg = ranges[tile];
     const uint32_t start = rg.x, end = rg.y;
@@ -246,17 +249,19 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_fwd(CamDev cam, int nti
             const uint32_t id = vals[e];
             s_w0[threadIdx.x] = rec[3 * (int64_t)id + 0];
             s_w1[threadIdx.x] = rec[3 * (int64_t)id + 1];
-            s_w2[threadIdx.x] = rec[3 * (int64_t)id + 2];
+            const float4 w2 = rec[3 * (int64_t)id + 2];
+            s_w2[threadIdx.x] = w2;
+            s_full[threadIdx.x] = box_covers(__float_as_uint(w2.y), __float_as_uint(w2.z), tx0p, ty0p, tx1p, ty1p);
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)kBlendThreads, end - b);
         if (!done) {
             for (int j = 0; j < cnt; j++) {
                 const float4 w2 = s_w2[j];
-                if (!box_contains(__float_as_uint(w2.y), __float_as_uint(w2.z), px, py)) continue;
+                if (!s_full[j] && !box_contains(__float_as_uint(w2.y), __float_as_uint(w2.z), px, py)) continue;
                 const float4 w0 = s_w0[j], w1 = s_w1[j];
                 float dx, dy, G, raw, alpha;
-                if (!blend_alpha(fpx, fpy, w0, w1, dx, dy, G, raw, alpha)) continue;
+                if (!blend_alpha(fpx, fpy, w0, w1, w2.w, dx, dy, G, raw, alpha)) continue;
                 const float Tn = T * (1.0f - alpha);
                 if (Tn < 1e-4f) {
                     done = true;
@@ -293,6 +298,11 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_fwd(CamDev cam, int nti
 // gradient terms across the wave (then the four waves in LDS) before one
 // global atomic per term and tile.
 // ---------------------------------------------------------------------------
+// kRecords: write each walked entry's nine sums to the compact record buffer
+// (fixed summation order; gathered per Gaussian by the preprocess backward),
+// atomics only past its capacity; otherwise one global atomic per term and
+// (tile, Gaussian).  kOpacity: also reduce the opacity term.
+template <bool kRecords, bool kOpacity>
 __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(CamDev cam, int ntiles, const uint2* __restrict__ ranges,
                                                               const uint32_t* __restrict__ vals,
                                                               const float4* __restrict__ rec,
@@ -307,6 +317,7 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(CamDev cam, int nti
     __shared__ float4 s_w1[kBlendThreads];
     __shared__ float4 s_w2[kBlendThreads];
     __shared__ uint32_t s_id[kBlendThreads];
+    __shared__ uint8_t s_full[kBlendThreads];
     __shared__ float s_g[4][9][kBlendThreads];   // per-wave sums, [wave][term][entry]
     const int tile = tile_of_block(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
@@ -314,10 +325,12 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(CamDev cam, int nti
     if (maxlast == 0) return;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+    const int tx0p = tx * kTile, ty0p = ty * kTile;
+    const int tx1p = min(tx0p + kTile - 1, cam.W - 1), ty1p = min(ty0p + kTile - 1, cam.H - 1);
     const bool inside = px < cam.W && py < cam.H;
     const uint2 rg = ranges[tile];
     const uint32_t start = rg.x;
-    const uint32_t woff = walk_off[tile];
+    const uint32_t woff = kRecords ? walk_off[tile] : 0u;
     const int64_t p = (int64_t)py * cam.W + px, P = (int64_t)cam.W * cam.H;
     float T = 1.0f;
     uint32_t last = 0;
@@ -332,6 +345,9 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(CamDev cam, int nti
     const float fpx = (float)px, fpy = (float)py;
     float b0 = cam.bg[0], b1 = cam.bg[1], b2 = cam.bg[2];   // colour behind the current contributor
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // reduce-scatter terms: u, v, A, B, C, r, g, b; lane group (lane >> 3) holds term (lane >> 3)
+    const int my_term = lane >> 3;
+    const int my_slot = my_term < 5 ? my_term : my_term + 1;   // index in the nine-term layout
     for (int64_t jb = ((int64_t)(maxlast - 1) / kBlendThreads) * kBlendThreads; jb >= 0; jb -= kBlendThreads) {
         const uint32_t e = (uint32_t)jb + threadIdx.x;
         if (e < maxlast) {
@@ -339,33 +355,36 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(CamDev cam, int nti
             s_id[threadIdx.x] = id;
             s_w0[threadIdx.x] = rec[3 * (int64_t)id + 0];
             s_w1[threadIdx.x] = rec[3 * (int64_t)id + 1];
-            s_w2[threadIdx.x] = rec[3 * (int64_t)id + 2];
+            const float4 w2 = rec[3 * (int64_t)id + 2];
+            s_w2[threadIdx.x] = w2;
+            s_full[threadIdx.x] = box_covers(__float_as_uint(w2.y), __float_as_uint(w2.z), tx0p, ty0p, tx1p, ty1p);
         }
         __syncthreads();
         const int cnt = (int)min((int64_t)kBlendThreads, (int64_t)maxlast - jb);
         for (int j = cnt - 1; j >= 0; j--) {
             const uint32_t ej = (uint32_t)jb + (uint32_t)j;
-            float gr[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float gr[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float gop = 0.f;
             bool act = false;
             if (ej < last) {
                 const float4 w2 = s_w2[j];
-                if (box_contains(__float_as_uint(w2.y), __float_as_uint(w2.z), px, py)) {
+                if (s_full[j] || box_contains(__float_as_uint(w2.y), __float_as_uint(w2.z), px, py)) {
                     const float4 w0 = s_w0[j], w1 = s_w1[j];
                     float dx, dy, G, raw, alpha;
-                    if (blend_alpha(fpx, fpy, w0, w1, dx, dy, G, raw, alpha)) {
+                    if (blend_alpha(fpx, fpy, w0, w1, w2.w, dx, dy, G, raw, alpha)) {
                         act = true;
                         T = T / (1.0f - alpha);
                         const float wgt = alpha * T;
                         const float cr = w1.z, cg = w1.w, cb = w2.x;
-                        gr[6] = g0 * wgt;
-                        gr[7] = g1 * wgt;
-                        gr[8] = g2 * wgt;
+                        gr[5] = g0 * wgt;
+                        gr[6] = g1 * wgt;
+                        gr[7] = g2 * wgt;
                         const float dal = T * (g0 * (cr - b0) + g1 * (cg - b1) + g2 * (cb - b2));
                         b0 = alpha * cr + (1.0f - alpha) * b0;
                         b1 = alpha * cg + (1.0f - alpha) * b1;
                         b2 = alpha * cb + (1.0f - alpha) * b2;
                         if (raw < 0.99f) {
-                            gr[5] = dal * G;
+                            gop = dal * G;
                             const float dp = dal * raw;
                             gr[0] = dp * (w0.z * dx + w0.w * dy);
                             gr[1] = dp * (w0.w * dx + w1.x * dy);
@@ -376,21 +395,25 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(CamDev cam, int nti
                     }
                 }
             }
-            if (__any(act)) {
-#pragma unroll
-                for (int k = 0; k < 9; k++) gr[k] = wave_sum_dpp(gr[k]);
+            const bool any = __any(act);
+            float red = 0.f, redop = 0.f;
+            if (any) {
+                red = wave_reduce_scatter8(gr, lane);
+                if (kOpacity) redop = wave_sum_dpp(gop);
             }
-            if (lane == 0) {
-#pragma unroll
-                for (int k = 0; k < 9; k++) s_g[wv][k][j] = gr[k];
-            }
+            if ((lane & 7) == 0) s_g[wv][my_slot][j] = red;
+            if (kOpacity && lane == 8) s_g[wv][5][j] = redop;
         }
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
             const uint32_t widx = woff + (uint32_t)jb + threadIdx.x;   // compact index of this walked entry
-            const bool fits = widx < grec_cap;
+            const bool fits = kRecords && widx < grec_cap;
 #pragma unroll
             for (int k = 0; k < 9; k++) {
+                if (!kOpacity && k == 5) {
+                    if (fits) grec[(int64_t)k * grec_cap + widx] = 0.f;
+                    continue;
+                }
                 const float v = ((s_g[0][k][threadIdx.x] + s_g[1][k][threadIdx.x]) + s_g[2][k][threadIdx.x]) +
                                 s_g[3][k][threadIdx.x];
                 if (fits)
@@ -428,7 +451,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussDev g, CamDev cam, 
     // entries, visited in its tile-rectangle order
     float a9[9];
     for (int k = 0; k < 9; k++) a9[k] = accum[9 * i + k];
-    {
+    if (ga.grec_cap > 0) {
         const uint2 r = ga.rect[i];
         const int tx0 = r.x & 0xFFFF, ty0 = r.x >> 16, tx1 = r.y & 0xFFFF, ty1 = r.y >> 16;
         uint64_t k = ga.goff[i];
@@ -697,11 +720,14 @@ void blend_forward(const Launch& L, const CamDev& cam, const uint2* ranges, cons
 
 void blend_backward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals, const float4* rec,
                     const float* d_image, const float* T_final, const uint32_t* last, const GatherDev& ga,
-                    float* accum) {
+                    float* accum, bool want_opacity) {
     const int ntiles = cam.tiles_x * cam.tiles_y;
     if (L.prof) L.prof->begin("blend_bwd", L.st);
-    hipLaunchKernelGGL(k_blend_bwd, dim3(blend_grid(ntiles)), dim3(kBlendThreads), 0, L.st, cam, ntiles, ranges, vals,
-                       rec, d_image, T_final, last, ga.tile_walk, ga.walk_off, ga.grec, (uint32_t)ga.grec_cap, accum);
+    const bool records = ga.grec_cap > 0;
+    auto kern = records ? (want_opacity ? k_blend_bwd<true, true> : k_blend_bwd<true, false>)
+                        : (want_opacity ? k_blend_bwd<false, true> : k_blend_bwd<false, false>);
+    hipLaunchKernelGGL(kern, dim3(blend_grid(ntiles)), dim3(kBlendThreads), 0, L.st, cam, ntiles, ranges, vals, rec,
+                       d_image, T_final, last, ga.tile_walk, ga.walk_off, ga.grec, (uint32_t)ga.grec_cap, accum);
     if (L.prof) L.prof->end(L.st);
 }
 

@@ -223,7 +223,51 @@ __global__ void k_iota_u32(uint32_t* p, int64_t n) {
     if (i < n) p[i] = (uint32_t)i;
 }
 
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_morton(const float* __restrict__ means, int64_t n, float3 lo, float3 inv,
+                                                uint32_t* __restrict__ code, uint32_t* __restrict__ idx) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float x = fminf(fmaxf((means[3 * i] - lo.x) * inv.x, 0.f), 1.f);
+    const float y = fminf(fmaxf((means[3 * i + 1] - lo.y) * inv.y, 0.f), 1.f);
+    const float z = fminf(fmaxf((means[3 * i + 2] - lo.z) * inv.z, 0.f), 1.f);
+    const uint32_t qx = min((uint32_t)(x * 1024.f), 1023u), qy = min((uint32_t)(y * 1024.f), 1023u),
+                   qz = min((uint32_t)(z * 1024.f), 1023u);
+    code[i] = spread10(qx) | (spread10(qy) << 1) | (spread10(qz) << 2);
+    idx[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_gather_rows(const float* __restrict__ src, const uint32_t* __restrict__ perm,
+                                                     int64_t n, int rf, float* __restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n * rf) return;
+    const int64_t i = t / rf;
+    const int c = (int)(t - i * rf);
+    dst[t] = src[(int64_t)perm[i] * rf + c];
+}
+
 }  // namespace
+
+void morton_codes(const Launch& L, const float* means, int64_t n, const float lo[3], const float inv[3],
+                  uint32_t* code, uint32_t* idx) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_morton, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.st, means, n,
+                       make_float3(lo[0], lo[1], lo[2]), make_float3(inv[0], inv[1], inv[2]), code, idx);
+}
+
+void gather_rows(const Launch& L, const float* src, const uint32_t* perm, int64_t n, int rf, float* dst) {
+    if (n <= 0 || rf <= 0) return;
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((n * rf + 255) / 256)), dim3(256), 0, L.st, src, perm, n, rf,
+                       dst);
+}
 
 int64_t scan_tmp_words(int64_t n) { return (n + kTileItems - 1) / kTileItems + 2; }
 

@@ -64,7 +64,8 @@ class GradsC(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in GRAD_FIELDS]
 
 
-EXPORTED = ("gs3_create", "gs3_destroy", "gs3_last_error", "gs3_set_stream", "gs3_ntc_num_params",
+EXPORTED = ("gs3_create", "gs3_destroy", "gs3_last_error", "gs3_set_stream", "gs3_morton_order",
+            "gs3_gather_rows", "gs3_ntc_num_params",
             "gs3_ntc_load", "gs3_ntc_save", "gs3_ntc_forward", "gs3_ntc_backward", "gs3_ntc_prepare", "gs3_ntc_step",
             "gs3_ntc_grads", "gs3_ntc_zero_grads", "gs3_warmup_loss", "gs3_render", "gs3_render_backward",
             "gs3_loss", "gs3_adam", "gs3_zero", "gs3_debug_counts", "gs3_debug_pairs", "gs3_debug_ranges",
@@ -88,6 +89,8 @@ def lib():
         "gs3_destroy": [vp],
         "gs3_last_error": [vp],
         "gs3_set_stream": [vp, vp],
+        "gs3_morton_order": [vp, vp, i64, C.POINTER(f32), C.POINTER(f32), vp],
+        "gs3_gather_rows": [vp, vp, vp, i64, i32, vp],
         "gs3_ntc_num_params": [vp, C.POINTER(i64)],
         "gs3_ntc_load": [vp, vp, i64],
         "gs3_ntc_save": [vp, vp, i64],
@@ -214,6 +217,18 @@ def gs3_last_error(h) -> str:
 
 def gs3_set_stream(h, stream_ptr: int):
     _check(h, lib().gs3_set_stream(h, C.c_void_p(stream_ptr)))
+
+
+def gs3_morton_order(h, means, aabb_min, inv_extent, perm):
+    n = means.shape[0]
+    lo = (C.c_float * 3)(*[float(v) for v in aabb_min])
+    inv = (C.c_float * 3)(*[float(v) for v in inv_extent])
+    _check(h, lib().gs3_morton_order(h, _ptr(means, numel=3 * n), n, lo, inv, _ptr(perm, numel=n)))
+
+
+def gs3_gather_rows(h, src, perm, n, row_floats, dst):
+    _check(h, lib().gs3_gather_rows(h, _ptr(src, numel=n * row_floats), _ptr(perm, numel=n), n, row_floats,
+                                    _ptr(dst, numel=n * row_floats)))
 
 
 def gs3_ntc_num_params(h) -> int:
@@ -343,6 +358,11 @@ def gs3_profile_query(h, kernel: str):
 # convenience wrapper
 # ---------------------------------------------------------------------------
 
+def torch_empty_like(t):
+    import torch
+    return torch.empty_like(t)
+
+
 def make_config(max_gaussians: int, max_pairs: int, max_width: int, max_height: int, num_slots: int = 1,
                 sort_mode: str = "depth_first", ntc=None, precision: str = "f32", grad_record_log2: int = 0) -> ConfigC:
     cfg = ConfigC()
@@ -405,6 +425,26 @@ class Context:
     def zeros(self, *shape, dtype=None):
         import torch
         return torch.zeros(*shape, dtype=dtype or torch.float32, device=self.device)
+
+    # -- per-frame setup
+    def morton_order(self, means, aabb_min, inv_extent):
+        import torch
+        perm = torch.empty(means.shape[0], dtype=torch.int32, device=self.device)
+        gs3_morton_order(self.h, means, aabb_min, inv_extent, perm)
+        return perm
+
+    def gather_rows(self, src, perm):
+        n = perm.shape[0]
+        dst = torch_empty_like(src)
+        gs3_gather_rows(self.h, src, perm, n, src.numel() // max(n, 1), dst)
+        return dst
+
+    def reorder(self, gs: "GaussiansGPU", aabb_min, inv_extent):
+        """Morton-ordered copy of a Gaussian set and the permutation used."""
+        perm = self.morton_order(gs.means, aabb_min, inv_extent)
+        return GaussiansGPU(self.gather_rows(gs.means, perm), self.gather_rows(gs.quats, perm),
+                            self.gather_rows(gs.log_scales, perm), self.gather_rows(gs.opacity_logits, perm),
+                            self.gather_rows(gs.sh, perm), gs.sh_degree), perm
 
     # -- NTC
     def ntc_load(self, params):

@@ -112,7 +112,9 @@ def _grads_gpu(ctx, g, dmu, dq, full):
 @pytest.mark.parametrize("name,seed,full,sort_mode,rec_log2", [
     ("small-2k-64px", 4, False, "depth_first", 0), ("grad-200-32px", 5, True, "depth_first", 0),
     ("ring-50k-256px", 6, False, "depth_first", 0), ("small-2k-64px", 4, False, "radix64", 0),
-    # per-pair record buffer of 16 entries: nearly every pair takes the atomic fallback
+    # deterministic per-pair records, and a 16-entry record buffer where
+    # nearly every pair takes the atomic fallback
+    ("ring-50k-256px", 6, True, "depth_first", 23), ("small-2k-64px", 4, True, "radix64", 23),
     ("small-2k-64px", 4, True, "depth_first", 4)])
 def test_gradients_match_oracle(name, seed, full, sort_mode, rec_log2):
     g, cam, dmu, dq = _scene(name, seed, True)
@@ -197,9 +199,9 @@ def test_invalid_arguments_return_errors():
 
 
 def test_backward_is_deterministic():
-    """Without the atomic fallback the backward has a fixed summation order."""
+    """In record mode (no atomic fallback) the backward has a fixed summation order."""
     g, cam, dmu, dq = _scene("ring-50k-256px", 11, True)
-    ctx = make_ctx(g.n, cam, max_pairs=1 << 24)
+    ctx = make_ctx(g.n, cam, max_pairs=1 << 24, grad_record_log2=23)
     gg = _gs3().GaussiansGPU.from_host(g)
     tdmu, tdq = cuda(dmu), cuda(dq)
     ctx.render(gg, cam, tdmu, tdq)
@@ -211,4 +213,31 @@ def test_backward_is_deterministic():
         outs.append({k: v.cpu().numpy() for k, v in grads.items()})
     for k in outs[0]:
         assert np.array_equal(outs[0][k], outs[1][k]), k
+    ctx.close()
+
+
+def test_morton_reorder_is_a_sorted_permutation_and_keeps_the_image():
+    gs3 = _gs3()
+    g, cam, _, _ = _scene("small-2k-64px", 12, False)
+    ctx = make_ctx(g.n, cam)
+    cfg = synth.NTCConfig()
+    gg = gs3.GaussiansGPU.from_host(g)
+    ro, perm = ctx.reorder(gg, cfg.aabb_min, cfg.inv_extent())
+    p = perm.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(p), np.arange(g.n))
+    # Morton codes of the reordered means are non-decreasing
+    x = np.clip((g.means[p] - np.float32(-1.2)) * cfg.inv_extent(), 0, 1)
+    q = np.minimum((x * 1024).astype(np.int64), 1023)
+    code = np.zeros(g.n, np.int64)
+    for b in range(10):
+        for a in range(3):
+            code |= ((q[:, a] >> b) & 1) << (3 * b + a)
+    assert np.all(np.diff(code) >= 0)
+    assert np.array_equal(ro.means.cpu().numpy(), g.means[p])
+    a = ctx.render(gg, cam).clone()
+    b = ctx.render(ro, cam)
+    pre = orc.preprocess(g, cam)
+    keys = pre["key"][pre["visible"] == 1]
+    if len(np.unique(keys)) == len(keys):      # distinct depths: same compositing order
+        assert torch.equal(a, b)
     ctx.close()
