@@ -228,6 +228,18 @@ gs3_status gs3_render(gs3_ctx* ctx, int32_t slot, const gs3_gaussians* g, const 
  * final transmittance, not stored. */
 gs3_status gs3_render_backward(gs3_ctx* ctx, int32_t slot, const float* d_image, const gs3_grads* out);
 
+/* Frame carry-over (Sec. 4.1: the transformed Gaussians are carried into the
+ * next frame): means_out = mu + dmu (n x 3), quats_out = norm(q) x norm(dq)
+ * (n x 4), sh_out = the SH coefficients turned with the Gaussian
+ * (n x (deg+1)^2 x 3): band l >= 1 multiplied by M_l(dR), dR = R(q')
+ * R(norm q)^T, M_l = [P_l(dR N_k)] A_l^{-1} over 2l+1 fixed directions N_k
+ * (Suppl. Sec. B; the paper uses band 1 with N = e_x, e_y, e_z).  Rendering
+ * the outputs without a transform gives the image gs3_render gives for the
+ * inputs with (dmu, dq).  dmu / dq may be NULL.  Outputs must not alias the
+ * inputs. */
+gs3_status gs3_transform_bake(gs3_ctx* ctx, const gs3_gaussians* g, const float* dmu, const float* dq,
+                              float* means_out, float* quats_out, float* sh_out);
+
 /* ---- Loss (Eq. 6) and optimiser ------------------------------------------ */
 
 /* L = (1 - lambda) L1 + lambda (1 - SSIM) over 3 x H x W images (11x11

@@ -557,6 +557,23 @@ gs3_status gs3_render_backward(gs3_ctx* c, int32_t slot, const float* d_image, c
     return c->check_launch("render_backward");
 }
 
+gs3_status gs3_transform_bake(gs3_ctx* c, const gs3_gaussians* g, const float* dmu, const float* dq,
+                              float* means_out, float* quats_out, float* sh_out) {
+    if (!c) return GS3_EINVAL;
+    if (!g || g->n < 0 || g->sh_degree < 0 || g->sh_degree > 3)
+        return c->fail(GS3_EINVAL, "transform_bake: bad Gaussians");
+    if (g->n > 0 && (!g->means || !g->quats || !g->sh || !means_out || !quats_out || !sh_out))
+        return c->fail(GS3_EINVAL, "transform_bake: null array");
+    if (g->n > 0 && (means_out == g->means || quats_out == g->quats || sh_out == g->sh))
+        return c->fail(GS3_EINVAL, "transform_bake: outputs alias inputs");
+    GaussDev gd{};
+    gd.means = g->means; gd.quats = g->quats; gd.log_scales = g->log_scales; gd.opac = g->opacity_logits;
+    gd.sh = g->sh; gd.dmu = dmu; gd.dq = dq; gd.n = g->n; gd.sh_degree = g->sh_degree;
+    static const ShRotConst rc = make_shrot_const();
+    transform_bake(c->L(), gd, rc, means_out, quats_out, sh_out);
+    return c->check_launch("transform_bake");
+}
+
 /* ---- loss / optimiser ----------------------------------------------------- */
 
 gs3_status gs3_loss(gs3_ctx* c, const float* image, const float* target, int32_t height, int32_t width,

@@ -197,6 +197,29 @@ constexpr float c3d = 0.3731763325901154f;   // sqrt(7 / pi) / 4
 constexpr float c3e = 1.445305721320277f;    // sqrt(105 / pi) / 4
 }  // namespace shc
 
+template <typename F>
+__host__ __device__ __forceinline__ void sh_basis_t(int deg, F x, F y, F z, F Y[16]) {
+    using namespace shc;
+    Y[0] = (F)c0;
+    if (deg < 1) return;
+    Y[1] = -(F)c1 * y; Y[2] = (F)c1 * z; Y[3] = -(F)c1 * x;
+    if (deg < 2) return;
+    const F xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = (F)c2a * x * y;
+    Y[5] = -(F)c2a * y * z;
+    Y[6] = (F)c2b * (2 * zz - xx - yy);
+    Y[7] = -(F)c2a * x * z;
+    Y[8] = (F)c2c * (xx - yy);
+    if (deg < 3) return;
+    Y[9] = -(F)c3a * y * (3 * xx - yy);
+    Y[10] = (F)c3b * x * y * z;
+    Y[11] = -(F)c3c * y * (4 * zz - xx - yy);
+    Y[12] = (F)c3d * z * (2 * zz - 3 * xx - 3 * yy);
+    Y[13] = -(F)c3c * x * (4 * zz - xx - yy);
+    Y[14] = (F)c3e * z * (xx - yy);
+    Y[15] = -(F)c3a * x * (xx - 3 * yy);
+}
+
 __device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float Y[16]) {
     using namespace shc;
     Y[0] = c0;

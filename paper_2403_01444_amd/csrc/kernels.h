@@ -99,6 +99,15 @@ void debug_keys(const Launch& L, const uint2* ranges, const uint32_t* vals, cons
                 uint64_t* keys_out);
 void debug_records(const Launch& L, int64_t n, const float4* rec, int32_t* box, float* rec9);
 
+// ---- transform bake (bake.hip) -------------------------------------------------
+struct ShRotConst {
+    float dirs[3 * 15];       // bands 1..3: 3 + 5 + 7 directions
+    float ainv[9 + 25 + 49];  // A_l^{-1}, row-major, bands 1..3
+};
+ShRotConst make_shrot_const();
+void transform_bake(const Launch& L, const GaussDev& g, const ShRotConst& rc, float* mu_out, float* q_out,
+                    float* sh_out);
+
 // ---- loss (loss.hip) ---------------------------------------------------------
 struct LossWork {
     float* partial_maps;   // 3 x (3 H W) SSIM partial derivatives

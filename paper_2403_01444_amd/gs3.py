@@ -67,7 +67,7 @@ class GradsC(C.Structure):
 EXPORTED = ("gs3_create", "gs3_destroy", "gs3_last_error", "gs3_set_stream", "gs3_morton_order",
             "gs3_gather_rows", "gs3_ntc_num_params",
             "gs3_ntc_load", "gs3_ntc_save", "gs3_ntc_forward", "gs3_ntc_backward", "gs3_ntc_prepare", "gs3_ntc_step",
-            "gs3_ntc_grads", "gs3_ntc_zero_grads", "gs3_warmup_loss", "gs3_render", "gs3_render_backward",
+            "gs3_ntc_grads", "gs3_ntc_zero_grads", "gs3_warmup_loss", "gs3_render", "gs3_render_backward", "gs3_transform_bake",
             "gs3_loss", "gs3_adam", "gs3_zero", "gs3_debug_counts", "gs3_debug_pairs", "gs3_debug_ranges",
             "gs3_debug_gaussians", "gs3_debug_pixels", "gs3_check_flags", "gs3_profile_enable",
             "gs3_profile_reset", "gs3_profile_query")
@@ -103,6 +103,7 @@ def lib():
         "gs3_warmup_loss": [vp, vp, vp, i64, vp, vp, vp],
         "gs3_render": [vp, i32, C.POINTER(GaussiansC), vp, vp, C.POINTER(CameraC), vp],
         "gs3_render_backward": [vp, i32, vp, C.POINTER(GradsC)],
+        "gs3_transform_bake": [vp, C.POINTER(GaussiansC), vp, vp, vp, vp, vp],
         "gs3_loss": [vp, vp, vp, i32, i32, f32, vp, vp],
         "gs3_adam": [vp, vp, vp, vp, vp, i64, i32, f32, f32, f32, f32],
         "gs3_zero": [vp, vp, i64],
@@ -294,6 +295,14 @@ def gs3_render(h, slot, gs: GaussiansGPU, dmu, dq, cam, image):
 def gs3_render_backward(h, slot, d_image, grads: dict):
     gr = GradsC(*[_ptr(grads.get(k), name=k) for k in GRAD_FIELDS])
     _check(h, lib().gs3_render_backward(h, slot, _ptr(d_image, name="d_image"), C.byref(gr)))
+
+
+def gs3_transform_bake(h, gs: GaussiansGPU, dmu, dq, means_out, quats_out, sh_out):
+    n = gs.n
+    gsc = gs.struct()
+    _check(h, lib().gs3_transform_bake(h, C.byref(gsc), _ptr(dmu, numel=3 * n, name="dmu"),
+                                       _ptr(dq, numel=4 * n, name="dq"), _ptr(means_out, numel=3 * n),
+                                       _ptr(quats_out, numel=4 * n), _ptr(sh_out, numel=gs.sh.numel())))
 
 
 def gs3_loss(h, image, target, height, width, lam, loss, d_image):
@@ -493,6 +502,14 @@ class Context:
     def render_backward(self, d_image, grads: dict, slot=0):
         gs3_render_backward(self.h, slot, d_image, grads)
         return grads
+
+    def transform_bake(self, gs: GaussiansGPU, dmu=None, dq=None) -> GaussiansGPU:
+        """The transformed Gaussians (frame carry-over)."""
+        import torch
+        out = GaussiansGPU(torch.empty_like(gs.means), torch.empty_like(gs.quats), gs.log_scales,
+                           gs.opacity_logits, torch.empty_like(gs.sh), gs.sh_degree)
+        gs3_transform_bake(self.h, gs, dmu, dq, out.means, out.quats, out.sh)
+        return out
 
     def loss(self, image, target, lam=0.2, loss=None, d_image=None):
         _, H, W = image.shape
