@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--protocol", action="store_true",
                     help="equal-PSNR comparison of NTC and FP32 direct optimisation instead of the timing run")
     ap.add_argument("--protocol-iters", type=int, default=1000)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB, a kernel of known traffic "
+                         "for calibrating the HBM byte counters")
     return ap.parse_args()
 
 
@@ -109,25 +112,43 @@ def protocol(args):
     print(json.dumps(res))
 
 
-def algorithmic_bytes(name, st):
-    """Bytes the method itself must move per launch of `name`."""
-    n, P, walked, S = st["n"], st["pixels"], st["walked"], st["sh_floats"]
-    if name == "preprocess_fwd":
-        return n * (12 + 16 + 12 + 4 + 4 * S + 12 + 16 + 48 + 4 + 8 + 4)
+# Per-unit algorithmic work of each kernel.  The blend kernels are bound by
+# vector ALU work per (pixel, tile-list entry up to that pixel's last
+# contributor): operations counted from the forward and adjoint formulas of
+# Eq. 4 (add, mul, compare, min and the hardware exp each 1; a fused
+# multiply-add 2); the backward includes the 9 adds that sum each pixel's
+# contribution into the Gaussian's gradient terms.
+BLEND_FWD_FLOP = 29
+BLEND_BWD_FLOP = 71
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def algorithmic_work(name, st):
+    """(bound, amount per launch, unit) of the work the method itself needs."""
+    n, P, S = st["n"], st["pixels"], st["sh_floats"]
     if name == "blend_fwd":
-        return P * 20 + walked * (4 + 48)
+        return "alu", st["evals"] * BLEND_FWD_FLOP, "flop"
     if name == "blend_bwd":
-        return P * 20 + walked * (4 + 48) + st["contrib_pairs"] * 36
+        return "alu", st["evals"] * BLEND_BWD_FLOP, "flop"
+    if name == "preprocess_fwd":
+        # read mean, quat, log-scale, opacity, SH, dmu, dq; write 48-byte record, key, rect, count
+        return "hbm", n * (12 + 16 + 12 + 4 + 4 * S + 12 + 16 + 48 + 4 + 8 + 4), "byte"
     if name == "preprocess_bwd":
-        return n * (36 + 12 + 16 + 12 + 4 + 4 * S + 12 + 16 + 12 + 16)
+        # read the 36-byte gradient terms and the inputs again; write d_dmu, d_dq
+        return "hbm", n * (36 + 12 + 16 + 12 + 4 + 4 * S + 12 + 16 + 12 + 16), "byte"
     if name == "ntc_fwd":
-        return n * (12 + 28) + st["table_bytes"]
+        return "hbm", n * (12 + 28) + st["table_bytes"], "byte"
     if name == "ntc_bwd":
-        return n * (12 + 28) + st["table_bytes"] + 4 * st["table_entries"] * 2
+        return "hbm", n * (12 + 28) + st["table_bytes"], "byte"
+    if name == "ntc_scatter":
+        # each contribution read once (entry weight and feature gradient), each table gradient written once
+        return "hbm", st["contribs"] * (4 + 8) + 4 * st["table_entries"] * 2, "byte"
     if name == "loss":
-        return P * (12 + 12 + 12) + P * 36 * 2
-    if name in ("bin_count", "bin_scatter"):
-        return n * 16 + (st["K"] * 4 if name == "bin_scatter" else 0)
+        return "hbm", P * (12 + 12 + 12) + P * 36 * 2, "byte"
+    if name == "bin_scatter":
+        return "hbm", n * 16 + st["K"] * 4, "byte"
+    if name == "bin_count":
+        return "hbm", n * 16, "byte"
     return None
 
 
@@ -174,6 +195,12 @@ def main():
     if args.protocol:
         protocol(args)
         return
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     g, cams, held, nxt = synth.workload(args.workload, seed=0)
     cfg = synth.NTCConfig()
     W = max(c.width for c in cams + held)
@@ -232,17 +259,21 @@ def main():
             kernels[name] = {"ms_per_launch": ms / cnt, "launches_per_step": cnt / args.steps}
     iters_per_s = args.steps / elapsed
 
-    # pair count and walked list entries for the last rendered view
-    K, ov = ctx.debug_counts()
-    T, last = ctx.debug_pixels(cams[0])
-    ctx.render(gg, cams[0], *st1.transform())
-    T, last = ctx.debug_pixels(cams[0])
-    lastn = last.cpu().numpy()
-    th, tw = (cams[0].height + 15) // 16, (cams[0].width + 15) // 16
-    pad = np.zeros((th * 16, tw * 16), np.int64)
-    pad[:lastn.shape[0], :lastn.shape[1]] = lastn
-    walked = int(pad.reshape(th, 16, tw, 16).max(axis=(1, 3)).sum())
-    K0, _ = ctx.debug_counts()
+    # pairs, walked list entries and per-pixel evaluations, averaged over the
+    # training views with the final transform
+    dmu_f, dq_f = st1.transform()
+    Ks, walks, evals = [], [], []
+    for cam in cams:
+        ctx.render(gg, cam, dmu_f, dq_f)
+        T, last = ctx.debug_pixels(cam)
+        lastn = last.cpu().numpy().astype(np.int64)
+        th, tw = (cam.height + 15) // 16, (cam.width + 15) // 16
+        pad = np.zeros((th * 16, tw * 16), np.int64)
+        pad[:lastn.shape[0], :lastn.shape[1]] = lastn
+        walks.append(int(pad.reshape(th, 16, tw, 16).max(axis=(1, 3)).sum()))
+        evals.append(int(lastn.sum()))
+        Ks.append(ctx.debug_counts()[0])
+    K0, walked, n_evals = int(np.mean(Ks)), int(np.mean(walks)), int(np.mean(evals))
 
     # render FPS on the held-out view: NTC query + transform + raster (and raster alone)
     hc = held[0]
@@ -280,18 +311,33 @@ def main():
 
     # roofline of the dominant kernel (by device time per step)
     n_table_entries = cfg.num_table_params() // 2
-    st = dict(n=g.n, pixels=cams[0].width * cams[0].height, walked=walked, sh_floats=3 * (g.sh_degree + 1) ** 2,
-              K=K0, contrib_pairs=walked, table_bytes=n_table_entries * 2 * (4 if args.precision == "f32" else 2),
+    st = dict(n=g.n, pixels=cams[0].width * cams[0].height, walked=walked, evals=n_evals,
+              sh_floats=3 * (g.sh_degree + 1) ** 2, K=K0, contribs=8 * cfg.levels * g.n,
+              table_bytes=n_table_entries * 2 * (4 if args.precision == "f32" else 2),
               table_entries=n_table_entries)
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"] * kernels[k]["launches_per_step"]) if kernels else None
     roof = None
     if dom is not None:
-        b = algorithmic_bytes(dom, st)
-        if b is not None:
-            gbs = b / (kernels[dom]["ms_per_launch"] * 1e-3) / 1e9
-            roof = {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                    "algorithmic_bytes_per_launch": int(b)}
+        w = algorithmic_work(dom, st)
+        if w is not None:
+            bound, amount, unit = w
+            sec = kernels[dom]["ms_per_launch"] * 1e-3
+            if bound == "alu":
+                ach, peak, u = amount / sec / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+            else:
+                ach, peak, u = amount / sec / 1e9, HBM_PEAK_GBS, "GB/s"
+            roof = {"kernel": dom, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": u,
+                    "frac": round(ach / peak, 4), "traffic": None, "algorithmic_per_launch": int(amount),
+                    "algorithmic_unit": unit, "ms_per_launch": round(kernels[dom]["ms_per_launch"], 5)}
+    all_roof = {}
+    for k, v in kernels.items():
+        w = algorithmic_work(k, st)
+        if w is None:
+            continue
+        bound, amount, unit = w
+        sec = v["ms_per_launch"] * 1e-3
+        all_roof[k] = (round(amount / sec / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4) if bound == "alu"
+                       else round(amount / sec / 1e9 / HBM_PEAK_GBS, 4))
 
     base = None
     if not args.no_cpu_baseline:
@@ -309,10 +355,11 @@ def main():
         "s_per_frame_150_iters": round(150.0 / iters_per_s, 4),
         "render_fps_with_ntc": round(fps, 2), "render_fps_without_ntc": round(fps_plain, 2),
         "direct_f32_iters_per_s": None if direct is None else round(direct, 3),
-        "pairs_per_view": int(K0), "walked_entries": walked, "heldout_psnr_after_steps": round(psnr_ntc, 3),
+        "pairs_per_view": int(K0), "walked_entries": walked, "pixel_evals": n_evals,
+        "heldout_psnr_after_steps": round(psnr_ntc, 3),
         "warmup_s": round(t_warm, 3), "warmup_iters": args.warmup_iters, "frame_setup_s": round(t_prepare + t_reorder, 4),
         "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in kernels.items()},
-        "roofline": roof, "cpu_baseline": base,
+        "roofline": roof, "roofline_frac_by_kernel": all_roof, "cpu_baseline": base,
     }
     print(json.dumps(res))
 
