@@ -93,6 +93,8 @@ typedef struct {
     int32_t rect[4];   /* tile rectangle, inclusive */
     int64_t ntiles;
     float u, v, radius;
+    float A, B, C;     /* conic: inverse of the dilated 2D covariance */
+    float opacity;     /* sigmoid of the logit */
 } spec_t;
 
 static void spec_preprocess(const orc_gaussians* g, const orc_camera* c, int64_t i,
@@ -182,7 +184,24 @@ static void spec_preprocess(const orc_gaussians* g, const orc_camera* c, int64_t
     memcpy(&bits, &tz, 4);
     o->key = bits;
     o->u = u; o->v = v; o->radius = r;
+    o->A = cc / det;
+    o->B = -b / det;
+    o->C = a / det;
+    o->opacity = 1.0f / (1.0f + orc_spec_exp(-g->opacity_logits[i]));
     o->visible = 1;
+}
+
+/* Contributor decision of the blend (Eq. 4 with the 1/255 cut-off), taken in
+ * single precision: dx, dy and the exponent from the single-precision image
+ * position and conic with a fixed operation order, alpha from the
+ * decision-procedure exponential.  Returns 1 when the Gaussian contributes
+ * and stores the single-precision exponent. */
+static int spec_contributes(const spec_t* p, int x, int y, float* power_out) {
+    float dx = (float)x - p->u, dy = (float)y - p->v;
+    float power = -0.5f * (p->A * dx * dx + p->C * dy * dy) - p->B * dx * dy;
+    *power_out = power;
+    if (power > 0.0f) return 0;
+    return p->opacity * orc_spec_exp(power) >= 1.0f / 255.0f;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -612,11 +631,18 @@ static int scene_build(const orc_gaussians* g, const orc_camera* c, scene_t* s) 
 typedef struct { int64_t id; double alpha, raw, G, T, dx, dy; } contrib_t;
 
 /* Walk the candidates of pixel (x, y) (Eq. 4).  Returns the number of
- * contributors; fills list[] when list != NULL (capacity cap).  Sets
- * *ambig when a threshold decision is within FP32 reach of flipping. */
+ * contributors; fills list[] when list != NULL (capacity cap).  Which
+ * Gaussians contribute is decided in single precision (spec_contributes);
+ * their weights are double.  Sets *ambig when one of the two decisions that
+ * still depend on single-precision values could go the other way: the 0.99
+ * clamp of alpha, and the transmittance cut-off.  The margins follow from the
+ * difference between the single- and double-precision exponents (which moves
+ * alpha by the same relative amount), the error of a hardware exponential
+ * (taken as 2e-6 relative) and rounding of the transmittance product. */
 static int64_t walk_pixel(const scene_t* s, int x, int y, double* T_out, double col[3],
                           contrib_t* list, int64_t cap, int* ambig) {
     double T = 1.0;
+    double relT = 0.0;   /* bound on the relative error of a single-precision T */
     col[0] = col[1] = col[2] = 0;
     int64_t n = 0;
     *ambig = 0;
@@ -624,21 +650,19 @@ static int64_t walk_pixel(const scene_t* s, int x, int y, double* T_out, double 
         int64_t id = s->row_ids[k];
         const spec_t* p = &s->sp[id];
         if (x < p->box[0] || x > p->box[2]) continue;
+        float power32;
+        if (!spec_contributes(p, x, y, &power32)) continue;
         const g64_t* q = &s->gp[id];
         double dx = (double)x - q->u, dy = (double)y - q->v;
         double power = -0.5 * (q->A * dx * dx + q->C * dy * dy) - q->B * dx * dy;
-        if (power > 0) continue;
         double G = exp(power);
         double raw = q->opacity * G;
         double alpha = raw < 0.99 ? raw : 0.99;
-        /* single precision reaches alpha to ~1e-6 relative (power from
-         * float32 mean, conic and exp) and the transmittance product to
-         * ~1e-4 relative after a few hundred factors: decisions within those
-         * margins may go the other way on the GPU */
-        if (fabs(alpha - 1.0 / 255.0) < 2e-6 / 255.0 || fabs(raw - 0.99) < 2e-6 || power > -1e-6) *ambig = 1;
-        if (alpha < 1.0 / 255.0) continue;
+        double e = fabs((double)power32 - power) + fabs((double)p->opacity - q->opacity) / q->opacity + 2e-6;
+        if (fabs(raw - 0.99) < 2.0 * e * 0.99) *ambig = 1;
         double Tn = T * (1.0 - alpha);
-        if (fabs(Tn - 1e-4) < 1e-8) *ambig = 1;
+        relT += (raw < 0.99 ? alpha / (1.0 - alpha) : 0.0) * e + 3.0e-7;
+        if (fabs(Tn - 1e-4) < 2.0 * relT * 1e-4 + 1e-9) *ambig = 1;
         if (Tn < 1e-4) break;
         for (int ch = 0; ch < 3; ch++) col[ch] += alpha * T * q->rgb[ch];
         if (list && n < cap) {

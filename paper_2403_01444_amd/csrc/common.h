@@ -326,17 +326,33 @@ __device__ __forceinline__ void colour_forward(const GaussDev& g, const CamDev& 
 // pthr = ln(1 / (255 opacity)) (record word w2.w): a candidate with power
 // below it has alpha < 1/255 and is rejected without the exp; the exact
 // alpha test below stays the deciding one for the rest.
+// Opacity activation, in the decision procedure's arithmetic (the opacity
+// takes part in the contributor decision below).
+__device__ __forceinline__ float opacity_of(float logit) {
+#pragma clang fp contract(off)
+    return 1.0f / (1.0f + spec_exp(-logit));
+}
+
+// Contributor test and alpha of one (pixel, Gaussian) evaluation (Eq. 4).
+// A Gaussian contributes when its exponent is <= 0 and
+// opacity * exp(power) >= 1/255, both evaluated in single precision with a
+// fixed operation order and the decision-procedure exponential.  The
+// per-Gaussian threshold pthr = ln(1 / (255 opacity)) settles every case
+// more than 1e-4 away from it (the exponential and logf errors are below
+// 2e-6 there); only the rest evaluate the exact test.  alpha itself uses the
+// hardware exponential.
 __device__ __forceinline__ bool blend_alpha(float px, float py, const float4& w0, const float4& w1, float pthr,
                                             float& dx, float& dy, float& G, float& raw, float& alpha) {
 #pragma clang fp contract(off)
     dx = px - w0.x;
     dy = py - w0.y;
-    float power = -0.5f * (w0.z * dx * dx + w1.x * dy * dy) - w0.w * dx * dy;
-    if (power > 0.0f || power < pthr) return false;
+    const float power = -0.5f * (w0.z * dx * dx + w1.x * dy * dy) - w0.w * dx * dy;
+    if (power > 0.0f || power < pthr - 1e-4f) return false;
+    if (power < pthr + 1e-4f && !(w1.y * spec_exp(power) >= 1.0f / 255.0f)) return false;
     G = __expf(power);
     raw = w1.y * G;
     alpha = fminf(0.99f, raw);
-    return alpha >= (1.0f / 255.0f);
+    return true;
 }
 
 // does the pixel box cover the whole tile [x0, x1] x [y0, y1]?

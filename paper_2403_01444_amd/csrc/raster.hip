@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussDev g, CamDev cam, floa
     ColourCtx cc;
     colour_forward(g, cam, i, o, cc);
     const float A = o.c / o.det, B = -o.b / o.det, C = o.a / o.det;
-    const float op = 1.0f / (1.0f + __expf(-g.opac[i]));
+    const float op = opacity_of(g.opac[i]);
     rec[3 * i + 0] = make_float4(o.u, o.v, A, B);
     rec[3 * i + 1] = make_float4(C, op, fmaxf(cc.raw[0], 0.f), fmaxf(cc.raw[1], 0.f));
     rec[3 * i + 2] = make_float4(fmaxf(cc.raw[2], 0.f), __uint_as_float(pack16(o.x0, o.y0)),
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussDev g, CamDev cam, 
     if (out.d_opacity) out.d_opacity[i] += dop;
     if (out.d_rgb) for (int k = 0; k < 3; k++) out.d_rgb[3 * i + k] += drgb[k];
     if (out.d_opac) {
-        const float op = 1.0f / (1.0f + __expf(-g.opac[i]));
+        const float op = opacity_of(g.opac[i]);
         out.d_opac[i] += dop * op * (1.0f - op);
     }
     float dm[3] = {0.f, 0.f, 0.f};
