@@ -43,37 +43,44 @@ def parse():
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--render-reps", type=int, default=50)
     ap.add_argument("--protocol", action="store_true",
-                    help="equal-PSNR comparison of NTC and FP32 direct optimisation instead of the timing run")
-    ap.add_argument("--protocol-iters", type=int, default=1000)
+                    help="only the equal-PSNR comparison, with full logs")
+    ap.add_argument("--protocol-iters", type=int, default=300, help="direct-optimisation iterations in the protocol")
+    ap.add_argument("--quality-workload", default="surfaces-300k-1352px",
+                    help="capture-like scene for the equal-PSNR comparison")
+    ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB, a kernel of known traffic "
                          "for calibrating the HBM byte counters")
     return ap.parse_args()
 
 
-def protocol(args):
-    """Equal-PSNR protocol: both methods up to --protocol-iters iterations,
-    held-out PSNR logged every 10; NTC's PSNR at 150 iterations is P*; the
-    direct optimiser's time to P* - 0.1 dB is compared with NTC's time for
-    150 iterations (training time only; the once-per-scene warm-up is
-    reported apart)."""
+def quality(args, workload, iters=150, direct_iters=300):
+    """Equal-PSNR protocol on one workload: the FP16/BF16 NTC (warm-started
+    by Eq. 7) and FP32 direct optimisation of per-Gaussian (dmu, dq), same
+    renderer, loss and view order, held-out PSNR logged every 10 iterations.
+    NTC's PSNR at `iters` iterations is P*; the direct optimiser's training
+    time to reach P* - 0.1 dB is compared with NTC's time for `iters`
+    iterations (training time only; the once-per-scene warm-up is reported
+    apart).  Also the NTC from its random initialisation ('w/o warm-up')."""
     import torch
     from paper_2403_01444_amd import gs3, synth, train
-    g, cams, held, nxt = synth.workload(args.workload, seed=0)
+    g, cams, held, nxt = synth.workload(workload, seed=0)
     cfg = synth.NTCConfig()
     W = max(c.width for c in cams + held)
     H = max(c.height for c in cams + held)
     ctx = gs3.Context(g.n, 120_000_000, W, H, num_slots=1, sort_mode=args.sort_mode, ntc=cfg,
                       precision=args.precision)
-    gg, gn = gs3.GaussiansGPU.from_host(g), gs3.GaussiansGPU.from_host(nxt)
+    gg = gs3.GaussiansGPU.from_host(g)
+    gg, perm = ctx.reorder(gg, cfg.aabb_min, cfg.inv_extent())
+    gn = gs3.GaussiansGPU.from_host(nxt.subset(perm.cpu().numpy().astype(np.int64)))
     targets = [ctx.render(gn, c).clone() for c in cams]
     ht = ctx.render(gn, held[0]).clone()
-    gg, perm = ctx.reorder(gg, cfg.aabb_min, cfg.inv_extent())
-    g = g.subset(perm.cpu().numpy().astype(np.int64))
+    K, _ = ctx.debug_counts()
     ctx.ntc_load(synth.ntc_init_params(cfg, 0))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    train.warmup(ctx, torch.from_numpy(synth.warmup_points(g.means, cfg, 1)).cuda(), args.warmup_iters)
+    train.warmup(ctx, torch.from_numpy(synth.warmup_points(gg.means.cpu().numpy(), cfg, 1)).cuda(),
+                 args.warmup_iters)
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
     warm = ctx.ntc_save()
@@ -82,34 +89,32 @@ def protocol(args):
 
     ctx.ntc_load(warm)
     st = train.Stage1NTC(ctx, gg, cams, targets, lam=0.2)
-
-    def ev_ntc():
-        dmu, dq = st.transform()
-        return train.psnr(ctx.render(gg, held[0], dmu, dq, image=img), ht)
-    ntc_log = train.logged_run(st.step, ev_ntc, args.protocol_iters)
-
+    ntc_log = train.logged_run(st.step, lambda: train.psnr(ctx.render(gg, held[0], *st.transform(), image=img), ht),
+                               iters)
     d = train.Stage1Direct(ctx, gg, cams, targets, lam=0.2)
-
-    def ev_direct():
-        return train.psnr(ctx.render(gg, held[0], d.dmu, d.dq, image=img), ht)
-    direct_log = train.logged_run(d.step, ev_direct, args.protocol_iters)
-
-    ctx.ntc_load(synth.ntc_init_params(cfg, 0))          # "w/o warm-up" ablation
+    direct_log = train.logged_run(d.step, lambda: train.psnr(ctx.render(gg, held[0], d.dmu, d.dq, image=img), ht),
+                                  direct_iters)
+    ctx.ntc_load(synth.ntc_init_params(cfg, 0))
     st_cold = train.Stage1NTC(ctx, gg, cams, targets, lam=0.2)
-
-    def ev_cold():
-        dmu, dq = st_cold.transform()
-        return train.psnr(ctx.render(gg, held[0], dmu, dq, image=img), ht)
-    cold_log = train.logged_run(st_cold.step, ev_cold, 150)
-
-    cmp = train.equal_psnr(ntc_log, direct_log, 150)
-    res = {"protocol": "equal-PSNR (held-out view, every 10 iterations)", "workload": args.workload,
-           "ntc_precision": args.precision, "psnr_static_previous_frame": psnr_static,
-           "warmup_seconds": t_warm, "warmup_iters": args.warmup_iters, **cmp,
-           "ntc_without_warmup_psnr_at_150": cold_log[-1][2],
-           "ntc_log": [(i, round(t, 5), round(p, 4)) for i, t, p in ntc_log],
-           "direct_log": [(i, round(t, 5), round(p, 4)) for i, t, p in direct_log]}
-    print(json.dumps(res))
+    cold_log = train.logged_run(st_cold.step,
+                                lambda: train.psnr(ctx.render(gg, held[0], *st_cold.transform(), image=img), ht),
+                                iters)
+    ctx.close()
+    cmp = train.equal_psnr(ntc_log, direct_log, iters)
+    res = {"workload": workload, "pairs_per_view": int(K), "ntc_precision": args.precision,
+           "psnr_untransformed": round(psnr_static, 3), "warmup_s": round(t_warm, 3),
+           "warmup_iters": args.warmup_iters,
+           **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in cmp.items()},
+           "ntc_iters_per_s": round(iters / ntc_log[-1][1], 2),
+           "direct_iters_per_s": round(direct_iters / direct_log[-1][1], 2),
+           "ntc_without_warmup_psnr": {str(i): round(p, 3) for i, _, p in cold_log if i in (20, 50, iters)},
+           "ntc_psnr": {str(i): round(p, 3) for i, _, p in ntc_log if i in (10, 20, 50, 100, iters)},
+           "direct_psnr": {str(i): round(p, 3) for i, _, p in direct_log if i in (10, 20, 50, 100, 150, direct_iters)}}
+    if args.protocol:
+        res["ntc_log"] = [(i, round(t, 5), round(p, 4)) for i, t, p in ntc_log]
+        res["direct_log"] = [(i, round(t, 5), round(p, 4)) for i, t, p in direct_log]
+        res["ntc_without_warmup_log"] = [(i, round(t, 5), round(p, 4)) for i, t, p in cold_log]
+    return res
 
 
 # Per-unit algorithmic work of each kernel.  The blend kernels are bound by
@@ -193,7 +198,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.protocol:
-        protocol(args)
+        print(json.dumps(quality(args, args.quality_workload, direct_iters=args.protocol_iters)))
         return
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib << 18, device="cuda")
@@ -339,6 +344,12 @@ def main():
         all_roof[k] = (round(amount / sec / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4) if bound == "alu"
                        else round(amount / sec / 1e9 / HBM_PEAK_GBS, 4))
 
+    qual = None
+    if not args.no_quality:
+        del st1
+        ctx.close()
+        qual = quality(args, args.quality_workload)
+
     base = None
     if not args.no_cpu_baseline:
         g_ordered = g.subset(order.cpu().numpy().astype(np.int64))
@@ -360,6 +371,7 @@ def main():
         "warmup_s": round(t_warm, 3), "warmup_iters": args.warmup_iters, "frame_setup_s": round(t_prepare + t_reorder, 4),
         "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in kernels.items()},
         "roofline": roof, "roofline_frac_by_kernel": all_roof, "cpu_baseline": base,
+        "equal_psnr": qual,
     }
     print(json.dumps(res))
 

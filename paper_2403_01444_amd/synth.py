@@ -177,6 +177,148 @@ def rigid_sinusoid_motion(g: Gaussians, seed: int, angle_deg: float = 1.0,
     return out
 
 
+# --- a capture-like scene: textured surfaces, moving objects -------------------
+
+def _quat_from_frame(t1: np.ndarray, t2: np.ndarray, nrm: np.ndarray) -> np.ndarray:
+    """Unit quaternions (w, x, y, z) of rotations with columns (t1, t2, nrm)."""
+    R = np.stack([t1, t2, nrm], axis=2)            # (n, 3, 3), columns
+    tr = R[:, 0, 0] + R[:, 1, 1] + R[:, 2, 2]
+    q = np.zeros((R.shape[0], 4))
+    # Shepperd's method, branch on the largest of (tr, R00, R11, R22)
+    cand = np.stack([tr, R[:, 0, 0], R[:, 1, 1], R[:, 2, 2]], axis=1)
+    k = np.argmax(cand, axis=1)
+    for b in range(4):
+        m = k == b
+        if not m.any():
+            continue
+        r = R[m]
+        if b == 0:
+            s = np.sqrt(1.0 + tr[m]) * 2
+            q[m] = np.stack([0.25 * s, (r[:, 2, 1] - r[:, 1, 2]) / s, (r[:, 0, 2] - r[:, 2, 0]) / s,
+                             (r[:, 1, 0] - r[:, 0, 1]) / s], 1)
+        elif b == 1:
+            s = np.sqrt(1.0 + r[:, 0, 0] - r[:, 1, 1] - r[:, 2, 2]) * 2
+            q[m] = np.stack([(r[:, 2, 1] - r[:, 1, 2]) / s, 0.25 * s, (r[:, 0, 1] + r[:, 1, 0]) / s,
+                             (r[:, 0, 2] + r[:, 2, 0]) / s], 1)
+        elif b == 2:
+            s = np.sqrt(1.0 + r[:, 1, 1] - r[:, 0, 0] - r[:, 2, 2]) * 2
+            q[m] = np.stack([(r[:, 0, 2] - r[:, 2, 0]) / s, (r[:, 0, 1] + r[:, 1, 0]) / s, 0.25 * s,
+                             (r[:, 1, 2] + r[:, 2, 1]) / s], 1)
+        else:
+            s = np.sqrt(1.0 + r[:, 2, 2] - r[:, 0, 0] - r[:, 1, 1]) * 2
+            q[m] = np.stack([(r[:, 1, 0] - r[:, 0, 1]) / s, (r[:, 0, 2] + r[:, 2, 0]) / s,
+                             (r[:, 1, 2] + r[:, 2, 1]) / s, 0.25 * s], 1)
+    return q / np.linalg.norm(q, axis=1, keepdims=True)
+
+
+@dataclass
+class SurfaceScene:
+    gaussians: Gaussians
+    labels: np.ndarray          # 0 = static background, k >= 1 = object k
+    centres: np.ndarray         # (objects + 1, 3); row 0 unused
+
+
+def surface_scene(n: int, sh_degree: int, seed: int, objects: int = 6) -> SurfaceScene:
+    """Gaussians on textured surfaces, the structure of a reconstructed
+    capture: a back wall (z = 0.9) and a floor (y = -0.9) of the [-1, 1]^3 box,
+    and `objects` spheres in front of them.  Each Gaussian is a flat disk in
+    its surface (tangent scales ~1.2x the sample spacing, normal scale 0.2x),
+    nearly opaque, coloured by a smooth multi-frequency texture."""
+    rng = np.random.default_rng(seed)
+    radii = rng.uniform(0.15, 0.3, size=objects)
+    centres = np.stack([rng.uniform(-0.6, 0.6, objects),
+                        rng.uniform(-0.9 + radii, 0.4),
+                        rng.uniform(-0.5, 0.5, objects)], axis=1)
+    areas = np.concatenate([[4.0, 3.8], 4 * math.pi * radii ** 2])
+    counts = np.floor(n * areas / areas.sum()).astype(np.int64)
+    counts[0] += n - counts.sum()
+    P, N, T1, L = [], [], [], []
+    # back wall: x, y in [-1, 1], z = 0.9, normal towards the cameras (-z)
+    c = counts[0]
+    P.append(np.stack([rng.uniform(-1, 1, c), rng.uniform(-1, 1, c), np.full(c, 0.9)], 1))
+    N.append(np.tile([0.0, 0.0, -1.0], (c, 1)))
+    L.append(np.zeros(c, np.int64))
+    # floor: x in [-1, 1], z in [-1, 0.9], y = -0.9, normal +y
+    c = counts[1]
+    P.append(np.stack([rng.uniform(-1, 1, c), np.full(c, -0.9), rng.uniform(-1, 0.9, c)], 1))
+    N.append(np.tile([0.0, 1.0, 0.0], (c, 1)))
+    L.append(np.zeros(c, np.int64))
+    for k in range(objects):
+        c = counts[2 + k]
+        d = rng.normal(size=(c, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        P.append(centres[k] + radii[k] * d)
+        N.append(d)
+        L.append(np.full(c, k + 1, np.int64))
+    P, N, L = np.concatenate(P), np.concatenate(N), np.concatenate(L)
+    # random tangent frame about each normal
+    a = rng.normal(size=(n, 3))
+    t1 = a - (a * N).sum(1, keepdims=True) * N
+    t1 /= np.linalg.norm(t1, axis=1, keepdims=True)
+    t2 = np.cross(N, t1)
+    q = _quat_from_frame(t1, t2, N)
+    spacing = math.sqrt(areas.sum() / n)
+    log_scales = np.stack([np.log(1.2 * spacing) + rng.normal(0, 0.15, n),
+                           np.log(1.2 * spacing) + rng.normal(0, 0.15, n),
+                           np.log(0.2 * spacing) + rng.normal(0, 0.15, n)], 1)
+    logits = rng.normal(2.5, 0.5, n)
+    # texture: three octaves of random plane waves per channel, plus an object tint
+    col = np.full((n, 3), 0.5)
+    for amp, freq in ((0.2, 1.0), (0.12, 3.0), (0.08, 8.0)):
+        for ch in range(3):
+            f = rng.normal(size=3)
+            f *= freq / np.linalg.norm(f)
+            col[:, ch] += amp * np.sin(2 * math.pi * (P @ f) + rng.uniform(0, 2 * math.pi))
+    tint = rng.uniform(-0.15, 0.15, size=(objects + 1, 3))
+    tint[0] = 0
+    col = np.clip(col + tint[L], 0.02, 0.98)
+    k = (sh_degree + 1) ** 2
+    sh = np.zeros((n, k, 3))
+    sh[:, 0, :] = (col - 0.5) / _Y00
+    if k > 1:
+        sh[:, 1:, :] = rng.normal(0.0, 0.02, size=(n, k - 1, 3))
+    f32 = np.float32
+    g = Gaussians(P.astype(f32), q.astype(f32), log_scales.astype(f32), logits.astype(f32),
+                  sh.astype(f32), sh_degree)
+    return SurfaceScene(g, L, np.concatenate([np.zeros((1, 3)), centres]))
+
+
+def object_motion(scene: SurfaceScene, seed: int, angle_deg: float = 1.5, translation: float = 0.006,
+                  wave: float = 0.002) -> Gaussians:
+    """Next frame of a surface scene: the background stays, each object turns
+    by `angle_deg` about a random axis through its centre, moves by
+    `translation` in a random direction and bends by a sinusoid of amplitude
+    `wave`; its Gaussians turn with it (q_next = q_rot (x) q)."""
+    rng = np.random.default_rng(seed)
+    g = scene.gaussians
+    out = g.subset(slice(None))
+    x = g.means.astype(np.float64)
+    moved = x.copy()
+    qn = g.quats.astype(np.float64).copy()
+    for k in range(1, scene.centres.shape[0]):
+        m = scene.labels == k
+        axis = rng.normal(size=3)
+        axis /= np.linalg.norm(axis)
+        half = math.radians(angle_deg) / 2.0
+        q_rot = np.concatenate([[math.cos(half)], math.sin(half) * axis])
+        w, (ax, ay, az) = q_rot[0], q_rot[1:]
+        rot = np.array([[1 - 2 * (ay * ay + az * az), 2 * (ax * ay - w * az), 2 * (ax * az + w * ay)],
+                        [2 * (ax * ay + w * az), 1 - 2 * (ax * ax + az * az), 2 * (ay * az - w * ax)],
+                        [2 * (ax * az - w * ay), 2 * (ay * az + w * ax), 1 - 2 * (ax * ax + ay * ay)]])
+        tdir = rng.normal(size=3)
+        tdir /= np.linalg.norm(tdir)
+        kv = rng.normal(size=3)
+        kv *= 3.0 / np.linalg.norm(kv)
+        ph = rng.uniform(0, 2 * math.pi, size=3)
+        c = scene.centres[k]
+        s = np.sin(2 * math.pi * (x[m] @ kv)[:, None] + ph[None, :]) * (wave / math.sqrt(3.0))
+        moved[m] = (x[m] - c) @ rot.T + c + translation * tdir + s
+        qn[m] = _hamilton(np.broadcast_to(q_rot, (int(m.sum()), 4)), qn[m])
+    out.means = moved.astype(np.float32)
+    out.quats = qn.astype(np.float32)
+    return out
+
+
 # --- NTC configuration and initial parameters --------------------------------
 
 @dataclass
@@ -255,6 +397,12 @@ def workload(name: str, seed: int = 0):
                       forward arc (azimuth in [-30, 30] deg) + one held-out
                       camera at azimuth 1.5 deg.
     grad-200-32px   : 200 Gaussians, SH3, one 32x32 camera.
+    surfaces-50k-256px : 50K Gaussians (SH1) of the same kind of scene, 12 arc
+                      cameras at 256x256, held-out camera at azimuth 0 (midway
+                      between two training views).
+    surfaces-300k-1352px : the arc cameras of arc-300k-1352px on a capture-like
+                      scene of 300K Gaussians (SH3): textured wall, floor and six
+                      spheres; the spheres move, the background stays.
     """
     if name == "small-2k-64px":
         g = make_gaussians(2000, 0, seed)
@@ -271,6 +419,16 @@ def workload(name: str, seed: int = 0):
         cams = arc_cameras(20, 1352, 1014)
         nxt = rigid_sinusoid_motion(g, seed + 1000)
         return g, cams, [look_at_camera(1352, 1014, azimuth_deg=1.5)], nxt
+    if name == "surfaces-50k-256px":
+        sc = surface_scene(50_000, 1, seed)
+        cams = arc_cameras(12, 256, 256)
+        nxt = object_motion(sc, seed + 1000)
+        return sc.gaussians, cams, [look_at_camera(256, 256, azimuth_deg=0.0)], nxt
+    if name == "surfaces-300k-1352px":
+        sc = surface_scene(300_000, 3, seed)
+        cams = arc_cameras(20, 1352, 1014)
+        nxt = object_motion(sc, seed + 1000)
+        return sc.gaussians, cams, [look_at_camera(1352, 1014, azimuth_deg=1.5)], nxt
     if name == "grad-200-32px":
         g = make_gaussians(200, 3, seed)
         return g, [look_at_camera(32, 32)], [], smooth_displacement(g, seed + 1000)

@@ -153,20 +153,29 @@ def logged_run(step, evaluate, iters: int, every: int = 10):
 
 
 def equal_psnr(ntc_log, direct_log, ntc_iters: int = 150, slack_db: float = 0.1):
-    """NTC at `ntc_iters` iterations reaches P*; the direct optimiser's time to
-    reach P* - slack is the wall time of its first logged point at or above
-    it (None if never).  Returns a dict of the comparison."""
+    """Two equal-PSNR comparisons of logs of (iterations, training seconds,
+    held-out PSNR).  (a) NTC at `ntc_iters` iterations reaches P*; the direct
+    optimiser's time to reach P* - slack (None if it never does).  (b) The
+    level both reach, min(best NTC, best direct) - slack, and each method's
+    time to its first logged point at or above it."""
     at = [r for r in ntc_log if r[0] == ntc_iters]
     if not at:
         raise ValueError("the NTC log has no point at the requested iteration")
     _, t_ntc, p_star = at[0]
     hit = [r for r in direct_log if r[2] >= p_star - slack_db]
-    d150 = [r for r in direct_log if r[0] == ntc_iters]
+    d_same = [r for r in direct_log if r[0] == ntc_iters]
+    common = min(max(r[2] for r in ntc_log), max(r[2] for r in direct_log)) - slack_db
+    first = lambda log: next(r for r in log if r[2] >= common)
+    fn, fd = first(ntc_log), first(direct_log)
     return {
-        "ntc_iters": ntc_iters, "ntc_psnr": p_star, "ntc_seconds": t_ntc,
+        "ntc_iters": ntc_iters, "ntc_psnr_at_iters": p_star, "ntc_seconds": t_ntc,
         "direct_iters_to_match": hit[0][0] if hit else None,
         "direct_seconds_to_match": hit[0][1] if hit else None,
-        "direct_psnr_at_same_iters": d150[0][2] if d150 else None,
-        "direct_seconds_at_same_iters": d150[0][1] if d150 else None,
+        "direct_psnr_at_same_iters": d_same[0][2] if d_same else None,
+        "direct_seconds_at_same_iters": d_same[0][1] if d_same else None,
+        "ntc_best_psnr": max(r[2] for r in ntc_log),
         "direct_best_psnr": max(r[2] for r in direct_log),
+        "common_psnr": common,
+        "ntc_iters_to_common": fn[0], "ntc_seconds_to_common": fn[1],
+        "direct_iters_to_common": fd[0], "direct_seconds_to_common": fd[1],
     }

@@ -93,15 +93,17 @@ def test_identity_ntc_on_unmoved_scene_gives_zero_loss():
     ctx.close()
 
 
-def test_warmup_drives_ntc_to_identity_and_helps_stage1():
-    """Eq. 7 warm-up brings the NTC close to the identity transform; Stage 1
-    from the warmed-up NTC reaches a higher held-out PSNR in the same number
-    of iterations than from the random initialisation (the paper's 'w/o
-    Warm-up' ablation)."""
+def test_warmup_and_stage1_ntc_on_capture_like_scene():
+    """300K Gaussians on textured surfaces at 1352x1014 (moving spheres in
+    front of a static wall and floor), FP16 NTC.  The Eq. 7 warm-up brings the
+    NTC to the identity transform; 150 Stage-1 iterations from it raise the
+    held-out PSNR well above the untransformed scene's, and the warm start is
+    ahead of the random initialisation early on (the paper's 'w/o Warm-up'
+    ablation: more iterations to converge)."""
     from paper_2403_01444_amd import gs3, train
-    g, cams, held, nxt = synth.workload("ring-50k-256px", seed=2)
+    g, cams, held, nxt = synth.workload("surfaces-300k-1352px", seed=4)
     cfg = synth.NTCConfig()
-    ctx = gs3.Context(g.n, 1 << 25, 256, 256, ntc=cfg, precision="f16")
+    ctx = gs3.Context(g.n, 1 << 26, 1352, 1014, ntc=cfg, precision="f16")
     gg = gs3.GaussiansGPU.from_host(g)
     gn = gs3.GaussiansGPU.from_host(nxt)
     targets = [ctx.render(gn, c).clone() for c in cams]
@@ -113,17 +115,19 @@ def test_warmup_drives_ntc_to_identity_and_helps_stage1():
     assert loss.item() < -0.99          # mean ||dmu||_1 - mean cos^2 -> -1 at the identity
     warm = ctx.ntc_save()
 
-    def run(params, iters=150):
+    def run(params, iters):
         ctx.ntc_load(params)
         st = train.Stage1NTC(ctx, gg, cams, targets, lam=0.2)
-        for _ in range(iters):
+        out = {}
+        for it in range(1, iters + 1):
             st.step()
-        dmu, dq = st.transform()
-        return train.psnr(ctx.render(gg, held[0], dmu, dq), ht)
+            if it in (20, iters):
+                out[it] = train.psnr(ctx.render(gg, held[0], *st.transform()), ht)
+        return out
 
-    psnr_warm = run(warm)
-    psnr_cold = run(p0)
     psnr_static = train.psnr(ctx.render(gg, held[0]), ht)
-    assert psnr_warm > psnr_static + 0.1, (psnr_warm, psnr_static)
-    assert psnr_warm > psnr_cold, (psnr_warm, psnr_cold)
+    warm_log = run(warm, 150)
+    cold_log = run(p0, 20)
+    assert warm_log[150] > psnr_static + 1.5, (warm_log, psnr_static)
+    assert warm_log[20] > cold_log[20] + 1.0, (warm_log, cold_log)
     ctx.close()
