@@ -334,19 +334,25 @@ __device__ __forceinline__ float opacity_of(float logit) {
 }
 
 // Contributor test and alpha of one (pixel, Gaussian) evaluation (Eq. 4).
-// A Gaussian contributes when its exponent is <= 0 and
-// opacity * exp(power) >= 1/255, both evaluated in single precision with a
-// fixed operation order and the decision-procedure exponential.  The
-// per-Gaussian threshold pthr = ln(1 / (255 opacity)) settles every case
-// more than 1e-4 away from it (the exponential and logf errors are below
-// 2e-6 there); only the rest evaluate the exact test.  alpha itself uses the
-// hardware exponential.
-__device__ __forceinline__ bool blend_alpha(float px, float py, const float4& w0, const float4& w1, float pthr,
-                                            float& dx, float& dy, float& G, float& raw, float& alpha) {
+// A Gaussian contributes when its exponent
+//     power = -0.5 ((A dx) dx + (C dy) dy) - (B dx) dy
+// is <= 0 and opacity * exp(power) >= 1/255, both evaluated in single
+// precision in exactly this order and with the decision-procedure
+// exponential.  The per-Gaussian threshold pthr = ln(1 / (255 opacity))
+// settles every case more than 1e-4 away from it (the exponential and logf
+// errors are below 2e-6 there); only the rest evaluate the exact test.  alpha
+// itself uses the hardware exponential.  The pixel-column products (A dx) dx
+// and B dx are shared by the rows a thread walks (blend_dx_terms).
+__device__ __forceinline__ void blend_dx_terms(float dx, const float4& w0, float& adx2, float& bdx) {
 #pragma clang fp contract(off)
-    dx = px - w0.x;
-    dy = py - w0.y;
-    const float power = -0.5f * (w0.z * dx * dx + w1.x * dy * dy) - w0.w * dx * dy;
+    adx2 = w0.z * dx * dx;
+    bdx = w0.w * dx;
+}
+
+__device__ __forceinline__ bool blend_alpha_dy(float adx2, float bdx, float dy, const float4& w1, float pthr,
+                                               float& G, float& raw, float& alpha) {
+#pragma clang fp contract(off)
+    const float power = -0.5f * (adx2 + w1.x * dy * dy) - bdx * dy;
     if (power > 0.0f || power < pthr - 1e-4f) return false;
     if (power < pthr + 1e-4f && !(w1.y * spec_exp(power) >= 1.0f / 255.0f)) return false;
     G = __expf(power);

@@ -20,7 +20,7 @@ struct NtcCsr {
     uint2* rows = nullptr;    // [entries]: [start, end) into pid / w
     uint32_t* pid = nullptr;  // point << 7 | level << 3 | corner, sorted by entry
     float* w = nullptr;       // trilinear weight of each contribution
-    float* denc = nullptr;    // n x 32 encoding gradient of the current backward
+    float* denc = nullptr;    // [16 levels][n][2] encoding gradient of the current backward
 };
 
 int ntc_mlp_params();

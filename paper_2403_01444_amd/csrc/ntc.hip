@@ -457,9 +457,14 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
             for (int mt = 0; mt < 2; mt++) {
                 const f4v e = layer_tile<P, 64>(sW1t, LD64, mt * 16, H1, LD64, lane);
                 if (kCSR) {
-                    if (valid)
-                        *reinterpret_cast<float4*>(denc + 32 * pt + mt * 16 + 4 * g) =
-                            make_float4(e[0] * inv, e[1] * inv, e[2] * inv, e[3] * inv);
+                    // level-major [level][point][2]: one level's slice (8 n bytes)
+                    // stays cache-resident while the gather walks that level
+                    if (valid) {
+                        const int lv = mt * 8 + 2 * g;
+                        *reinterpret_cast<float2*>(denc + 2 * ((int64_t)lv * n + pt)) = make_float2(e[0] * inv, e[1] * inv);
+                        *reinterpret_cast<float2*>(denc + 2 * ((int64_t)(lv + 1) * n + pt)) =
+                            make_float2(e[2] * inv, e[3] * inv);
+                    }
                 } else {
                     for (int r = 0; r < 4; r++) E[p * 33 + mt * 16 + 4 * g + r] = e[r] * inv;
                 }
@@ -566,7 +571,7 @@ __global__ __launch_bounds__(256) void k_csr_weights(NtcDev nd, const float* __r
 // sums with DPP (pairs, quads, half-row mirror): fixed order.
 __global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ rows, const uint32_t* __restrict__ pid,
                                                     const float* __restrict__ w, const float* __restrict__ denc,
-                                                    int64_t entries, float* __restrict__ g_table) {
+                                                    int64_t n, int64_t entries, float* __restrict__ g_table) {
     const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 3;
     const int sub = threadIdx.x & 7;
     uint2 r = make_uint2(0u, 0u);
@@ -574,7 +579,7 @@ __global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ ro
     float a0 = 0.f, a1 = 0.f;
     for (uint32_t k = r.x + sub; k < r.y; k += 8) {
         const uint32_t c = pid[k];
-        const float2 d = *reinterpret_cast<const float2*>(denc + 32 * (int64_t)(c >> 7) + 2 * ((c >> 3) & 15));
+        const float2 d = *reinterpret_cast<const float2*>(denc + 2 * ((int64_t)((c >> 3) & 15) * n + (c >> 7)));
         const float wk = w[k];
         a0 += wk * d.x;
         a1 += wk * d.y;
@@ -712,7 +717,7 @@ void bwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* 
         if (L.prof) L.prof->end(L.st);
         if (L.prof) L.prof->begin("ntc_scatter", L.st);
         hipLaunchKernelGGL(k_csr_gather, dim3(nblk(csr->entries * 8, 256)), dim3(256), 0, L.st, csr->rows, csr->pid,
-                           csr->w, csr->denc, csr->entries, g_table);
+                           csr->w, csr->denc, n, csr->entries, g_table);
     } else {
         hipLaunchKernelGGL((k_ntc_bwd<P, false>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
                            (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, (float*)nullptr);

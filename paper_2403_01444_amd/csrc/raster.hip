@@ -3,6 +3,10 @@
 // per-Gaussian kernels.
 #include "kernels.h"
 
+#ifndef GS3_BLEND_ROWS
+#define GS3_BLEND_ROWS 2
+#endif
+
 namespace gs3 {
 
 namespace {
@@ -216,34 +220,50 @@ __device__ __forceinline__ int tile_of_block(int b, int ntiles) {
 }
 
 // ---------------------------------------------------------------------------
-// blend forward (Eq. 4): one workgroup per 16x16 tile, one thread per pixel;
-// the tile's Gaussian records are staged through LDS 256 at a time.
+// blend forward (Eq. 4): one workgroup per 16x16 tile; each thread owns R
+// vertically adjacent pixels of one column, so a staged record is read from
+// LDS once per R evaluations and the column terms of the exponent are shared.
+// The tile's Gaussian records are staged through LDS 256/R at a time.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlendThreads) void k_blend_fwd(CamDev cam, int ntiles, const uint2* __restrict__ ranges,
-                                                              const uint32_t* __restrict__ vals,
-                                                              const float4* __restrict__ rec, float* __restrict__ image,
-                                                              float* __restrict__ T_final, uint32_t* __restrict__ last_out,
-                                                              uint32_t* __restrict__ tile_walk) {
+template <int R>
+__global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int ntiles,
+                                                                 const uint2* __restrict__ ranges,
+                                                                 const uint32_t* __restrict__ vals,
+                                                                 const float4* __restrict__ rec,
+                                                                 float* __restrict__ image, float* __restrict__ T_final,
+                                                                 uint32_t* __restrict__ last_out,
+                                                                 uint32_t* __restrict__ tile_walk) {
+    constexpr int NT = kTile * kTile / R;
     __shared__ uint32_t s_walk;
-    __shared__ float4 s_w0[kBlendThreads];
-    __shared__ float4 s_w1[kBlendThreads];
-    __shared__ float4 s_w2[kBlendThreads];
-    __shared__ uint8_t s_full[kBlendThreads];
+    __shared__ float4 s_w0[NT];
+    __shared__ float4 s_w1[NT];
+    __shared__ float4 s_w2[NT];
+    __shared__ uint8_t s_full[NT];
     const int tile = tile_of_block(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-    const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
     const int tx0p = tx * kTile, ty0p = ty * kTile;
     const int tx1p = min(tx0p + kTile - 1, cam.W - 1), ty1p = min(ty0p + kTile - 1, cam.H - 1);
-    const bool inside = px < cam.W && py < cam.H;
+    const int px = tx0p + (threadIdx.x & 15), py0 = ty0p + (threadIdx.x >> 4) * R;
+    const float fpx = (float)px;
     const uint2 rg = ranges[tile];
     const uint32_t start = rg.x, end = rg.y;
-    const float fpx = (float)px, fpy = (float)py;
-    float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-    uint32_t last = 0;
-    bool done = !inside;
-    for (uint32_t b = start; b < end; b += kBlendThreads) {
-        if (__syncthreads_count(done) == kBlendThreads) break;
+    float T[R], c0[R], c1[R], c2[R];
+    uint32_t last[R];
+    bool done[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        T[k] = 1.0f;
+        c0[k] = c1[k] = c2[k] = 0.f;
+        last[k] = 0u;
+        done[k] = !(px < cam.W && py0 + k < cam.H);
+    }
+    if (threadIdx.x == 0) s_walk = 0u;
+    for (uint32_t b = start; b < end; b += NT) {
+        bool all = true;
+#pragma unroll
+        for (int k = 0; k < R; k++) all = all && done[k];
+        if (__syncthreads_count(all) == NT) break;
         const uint32_t e = b + threadIdx.x;
         if (e < end) {
             const uint32_t id = vals[e];
@@ -254,39 +274,54 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_fwd(CamDev cam, int nti
             s_full[threadIdx.x] = box_covers(__float_as_uint(w2.y), __float_as_uint(w2.z), tx0p, ty0p, tx1p, ty1p);
         }
         __syncthreads();
-        const int cnt = (int)min((uint32_t)kBlendThreads, end - b);
-        if (!done) {
+        const int cnt = (int)min((uint32_t)NT, end - b);
+        if (!all) {
             for (int j = 0; j < cnt; j++) {
                 const float4 w2 = s_w2[j];
-                if (!s_full[j] && !box_contains(__float_as_uint(w2.y), __float_as_uint(w2.z), px, py)) continue;
+                const bool full = s_full[j];
+                const uint32_t bx0 = __float_as_uint(w2.y), bx1 = __float_as_uint(w2.z);
+                if (!full && (px < (int)(bx0 & 0xFFFFu) || px > (int)(bx1 & 0xFFFFu))) continue;
+                const int y0 = (int)(bx0 >> 16), y1 = (int)(bx1 >> 16);
                 const float4 w0 = s_w0[j], w1 = s_w1[j];
-                float dx, dy, G, raw, alpha;
-                if (!blend_alpha(fpx, fpy, w0, w1, w2.w, dx, dy, G, raw, alpha)) continue;
-                const float Tn = T * (1.0f - alpha);
-                if (Tn < 1e-4f) {
-                    done = true;
-                    break;
+                float adx2, bdx;
+                blend_dx_terms(fpx - w0.x, w0, adx2, bdx);
+#pragma unroll
+                for (int k = 0; k < R; k++) {
+                    const int py = py0 + k;
+                    if (done[k] || (!full && (py < y0 || py > y1))) continue;
+                    float G, raw, alpha;
+                    if (!blend_alpha_dy(adx2, bdx, (float)py - w0.y, w1, w2.w, G, raw, alpha)) continue;
+                    const float Tn = T[k] * (1.0f - alpha);
+                    if (Tn < 1e-4f) {
+                        done[k] = true;
+                        continue;
+                    }
+                    const float wgt = alpha * T[k];
+                    c0[k] += wgt * w1.z;
+                    c1[k] += wgt * w1.w;
+                    c2[k] += wgt * w2.x;
+                    T[k] = Tn;
+                    last[k] = b - start + (uint32_t)j + 1u;
                 }
-                const float wgt = alpha * T;
-                c0 += wgt * w1.z;
-                c1 += wgt * w1.w;
-                c2 += wgt * w2.x;
-                T = Tn;
-                last = b - start + (uint32_t)j + 1u;
             }
         }
+        __syncthreads();
     }
-    if (inside) {
-        const int64_t p = (int64_t)py * cam.W + px, P = (int64_t)cam.W * cam.H;
-        image[p] = c0 + T * cam.bg[0];
-        image[P + p] = c1 + T * cam.bg[1];
-        image[2 * P + p] = c2 + T * cam.bg[2];
-        T_final[p] = T;
-        last_out[p] = last;
+    const int64_t P = (int64_t)cam.W * cam.H;
+    uint32_t mx = 0u;
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        if (px < cam.W && py0 + k < cam.H) {
+            const int64_t p = (int64_t)(py0 + k) * cam.W + px;
+            image[p] = c0[k] + T[k] * cam.bg[0];
+            image[P + p] = c1[k] + T[k] * cam.bg[1];
+            image[2 * P + p] = c2[k] + T[k] * cam.bg[2];
+            T_final[p] = T[k];
+            last_out[p] = last[k];
+        }
+        mx = max(mx, last[k]);
     }
-    if (threadIdx.x == 0) s_walk = 0u;
-    __syncthreads();
-    if (last) atomicMax(&s_walk, last);
+    if (mx) atomicMax(&s_walk, mx);
     __syncthreads();
     if (threadIdx.x == 0) tile_walk[tile] = s_walk;
 }
@@ -294,61 +329,69 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_fwd(CamDev cam, int nti
 // ---------------------------------------------------------------------------
 // blend backward: walk the tile list from the last contributor of any pixel
 // down to the first, recover T_i = T_{i+1} / (1 - alpha_i), keep the colour
-// accumulated behind each contributor, and reduce each Gaussian's nine
-// gradient terms across the wave (then the four waves in LDS) before one
-// global atomic per term and tile.
+// accumulated behind each contributor, sum each Gaussian's nine gradient
+// terms over a thread's R pixels, then across the wave (reduce-scatter) and
+// the tile's waves in LDS, before one global atomic per term and tile.
 // ---------------------------------------------------------------------------
 // kRecords: write each walked entry's nine sums to the compact record buffer
 // (fixed summation order; gathered per Gaussian by the preprocess backward),
 // atomics only past its capacity; otherwise one global atomic per term and
 // (tile, Gaussian).  kOpacity: also reduce the opacity term.
-template <bool kRecords, bool kOpacity>
-__global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(CamDev cam, int ntiles, const uint2* __restrict__ ranges,
-                                                              const uint32_t* __restrict__ vals,
-                                                              const float4* __restrict__ rec,
-                                                              const float* __restrict__ d_image,
-                                                              const float* __restrict__ T_final,
-                                                              const uint32_t* __restrict__ last_in,
-                                                              const uint32_t* __restrict__ tile_walk,
-                                                              const uint32_t* __restrict__ walk_off,
-                                                              float* __restrict__ grec, uint32_t grec_cap,
-                                                              float* __restrict__ accum) {
-    __shared__ float4 s_w0[kBlendThreads];
-    __shared__ float4 s_w1[kBlendThreads];
-    __shared__ float4 s_w2[kBlendThreads];
-    __shared__ uint32_t s_id[kBlendThreads];
-    __shared__ uint8_t s_full[kBlendThreads];
-    __shared__ float s_g[4][9][kBlendThreads];   // per-wave sums, [wave][term][entry]
+template <int R, bool kRecords, bool kOpacity>
+__global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int ntiles,
+                                                                 const uint2* __restrict__ ranges,
+                                                                 const uint32_t* __restrict__ vals,
+                                                                 const float4* __restrict__ rec,
+                                                                 const float* __restrict__ d_image,
+                                                                 const float* __restrict__ T_final,
+                                                                 const uint32_t* __restrict__ last_in,
+                                                                 const uint32_t* __restrict__ tile_walk,
+                                                                 const uint32_t* __restrict__ walk_off,
+                                                                 float* __restrict__ grec, uint32_t grec_cap,
+                                                                 float* __restrict__ accum) {
+    constexpr int NT = kTile * kTile / R, NW = NT / 64;
+    __shared__ float4 s_w0[NT];
+    __shared__ float4 s_w1[NT];
+    __shared__ float4 s_w2[NT];
+    __shared__ uint32_t s_id[NT];
+    __shared__ uint8_t s_full[NT];
+    __shared__ float s_g[NW][9][NT];   // per-wave sums, [wave][term][entry]
     const int tile = tile_of_block(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const uint32_t maxlast = tile_walk[tile];
     if (maxlast == 0) return;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-    const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
     const int tx0p = tx * kTile, ty0p = ty * kTile;
     const int tx1p = min(tx0p + kTile - 1, cam.W - 1), ty1p = min(ty0p + kTile - 1, cam.H - 1);
-    const bool inside = px < cam.W && py < cam.H;
-    const uint2 rg = ranges[tile];
-    const uint32_t start = rg.x;
+    const int px = tx0p + (threadIdx.x & 15), py0 = ty0p + (threadIdx.x >> 4) * R;
+    const float fpx = (float)px;
+    const uint32_t start = ranges[tile].x;
     const uint32_t woff = kRecords ? walk_off[tile] : 0u;
-    const int64_t p = (int64_t)py * cam.W + px, P = (int64_t)cam.W * cam.H;
-    float T = 1.0f;
-    uint32_t last = 0;
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-    if (inside) {
-        T = T_final[p];
-        last = last_in[p];
-        g0 = d_image[p];
-        g1 = d_image[P + p];
-        g2 = d_image[2 * P + p];
+    const int64_t P = (int64_t)cam.W * cam.H;
+    float T[R], g0[R], g1[R], g2[R], b0[R], b1[R], b2[R];   // b: colour behind the current contributor
+    uint32_t last[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        T[k] = 1.0f;
+        last[k] = 0u;
+        g0[k] = g1[k] = g2[k] = 0.f;
+        b0[k] = cam.bg[0];
+        b1[k] = cam.bg[1];
+        b2[k] = cam.bg[2];
+        if (px < cam.W && py0 + k < cam.H) {
+            const int64_t p = (int64_t)(py0 + k) * cam.W + px;
+            T[k] = T_final[p];
+            last[k] = last_in[p];
+            g0[k] = d_image[p];
+            g1[k] = d_image[P + p];
+            g2[k] = d_image[2 * P + p];
+        }
     }
-    const float fpx = (float)px, fpy = (float)py;
-    float b0 = cam.bg[0], b1 = cam.bg[1], b2 = cam.bg[2];   // colour behind the current contributor
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // reduce-scatter terms: u, v, A, B, C, r, g, b; lane group (lane >> 3) holds term (lane >> 3)
     const int my_term = lane >> 3;
     const int my_slot = my_term < 5 ? my_term : my_term + 1;   // index in the nine-term layout
-    for (int64_t jb = ((int64_t)(maxlast - 1) / kBlendThreads) * kBlendThreads; jb >= 0; jb -= kBlendThreads) {
+    for (int64_t jb = ((int64_t)(maxlast - 1) / NT) * NT; jb >= 0; jb -= NT) {
         const uint32_t e = (uint32_t)jb + threadIdx.x;
         if (e < maxlast) {
             const uint32_t id = vals[start + e];
@@ -360,38 +403,47 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(CamDev cam, int nti
             s_full[threadIdx.x] = box_covers(__float_as_uint(w2.y), __float_as_uint(w2.z), tx0p, ty0p, tx1p, ty1p);
         }
         __syncthreads();
-        const int cnt = (int)min((int64_t)kBlendThreads, (int64_t)maxlast - jb);
+        const int cnt = (int)min((int64_t)NT, (int64_t)maxlast - jb);
         for (int j = cnt - 1; j >= 0; j--) {
             const uint32_t ej = (uint32_t)jb + (uint32_t)j;
             float gr[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             float gop = 0.f;
             bool act = false;
-            if (ej < last) {
-                const float4 w2 = s_w2[j];
-                if (s_full[j] || box_contains(__float_as_uint(w2.y), __float_as_uint(w2.z), px, py)) {
-                    const float4 w0 = s_w0[j], w1 = s_w1[j];
-                    float dx, dy, G, raw, alpha;
-                    if (blend_alpha(fpx, fpy, w0, w1, w2.w, dx, dy, G, raw, alpha)) {
-                        act = true;
-                        T = T / (1.0f - alpha);
-                        const float wgt = alpha * T;
-                        const float cr = w1.z, cg = w1.w, cb = w2.x;
-                        gr[5] = g0 * wgt;
-                        gr[6] = g1 * wgt;
-                        gr[7] = g2 * wgt;
-                        const float dal = T * (g0 * (cr - b0) + g1 * (cg - b1) + g2 * (cb - b2));
-                        b0 = alpha * cr + (1.0f - alpha) * b0;
-                        b1 = alpha * cg + (1.0f - alpha) * b1;
-                        b2 = alpha * cb + (1.0f - alpha) * b2;
-                        if (raw < 0.99f) {
-                            gop = dal * G;
-                            const float dp = dal * raw;
-                            gr[0] = dp * (w0.z * dx + w0.w * dy);
-                            gr[1] = dp * (w0.w * dx + w1.x * dy);
-                            gr[2] = dp * (-0.5f * dx * dx);
-                            gr[3] = dp * (-dx * dy);
-                            gr[4] = dp * (-0.5f * dy * dy);
-                        }
+            const float4 w2 = s_w2[j];
+            const bool full = s_full[j];
+            const uint32_t bx0 = __float_as_uint(w2.y), bx1 = __float_as_uint(w2.z);
+            if (full || (px >= (int)(bx0 & 0xFFFFu) && px <= (int)(bx1 & 0xFFFFu))) {
+                const int y0 = (int)(bx0 >> 16), y1 = (int)(bx1 >> 16);
+                const float4 w0 = s_w0[j], w1 = s_w1[j];
+                const float cr = w1.z, cg = w1.w, cb = w2.x;
+                const float dx = fpx - w0.x;
+                float adx2, bdx;
+                blend_dx_terms(dx, w0, adx2, bdx);
+#pragma unroll
+                for (int k = 0; k < R; k++) {
+                    const int py = py0 + k;
+                    if (ej >= last[k] || (!full && (py < y0 || py > y1))) continue;
+                    const float dy = (float)py - w0.y;
+                    float G, raw, alpha;
+                    if (!blend_alpha_dy(adx2, bdx, dy, w1, w2.w, G, raw, alpha)) continue;
+                    act = true;
+                    T[k] = T[k] / (1.0f - alpha);
+                    const float wgt = alpha * T[k];
+                    gr[5] += g0[k] * wgt;
+                    gr[6] += g1[k] * wgt;
+                    gr[7] += g2[k] * wgt;
+                    const float dal = T[k] * (g0[k] * (cr - b0[k]) + g1[k] * (cg - b1[k]) + g2[k] * (cb - b2[k]));
+                    b0[k] = alpha * cr + (1.0f - alpha) * b0[k];
+                    b1[k] = alpha * cg + (1.0f - alpha) * b1[k];
+                    b2[k] = alpha * cb + (1.0f - alpha) * b2[k];
+                    if (raw < 0.99f) {
+                        gop += dal * G;
+                        const float dp = dal * raw;
+                        gr[0] += dp * (w0.z * dx + w0.w * dy);
+                        gr[1] += dp * (w0.w * dx + w1.x * dy);
+                        gr[2] += dp * (-0.5f * dx * dx);
+                        gr[3] += dp * (-dx * dy);
+                        gr[4] += dp * (-0.5f * dy * dy);
                     }
                 }
             }
@@ -414,8 +466,9 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(CamDev cam, int nti
                     if (fits) grec[(int64_t)k * grec_cap + widx] = 0.f;
                     continue;
                 }
-                const float v = ((s_g[0][k][threadIdx.x] + s_g[1][k][threadIdx.x]) + s_g[2][k][threadIdx.x]) +
-                                s_g[3][k][threadIdx.x];
+                float v = s_g[0][k][threadIdx.x];
+#pragma unroll
+                for (int w = 1; w < NW; w++) v += s_g[w][k][threadIdx.x];
                 if (fits)
                     grec[(int64_t)k * grec_cap + widx] = v;
                 else if (v != 0.f)
@@ -709,12 +762,15 @@ void pairs_total_check(const Launch& L, const uint64_t* total, uint64_t cap, int
 
 static unsigned blend_grid(int ntiles) { return (unsigned)(((ntiles + 7) / 8) * 8); }
 
+// pixels per thread of the blend kernels
+constexpr int kBlendRows = GS3_BLEND_ROWS;
+
 void blend_forward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals, const float4* rec,
                    float* image, float* T_final, uint32_t* last, uint32_t* tile_walk) {
     const int ntiles = cam.tiles_x * cam.tiles_y;
     if (L.prof) L.prof->begin("blend_fwd", L.st);
-    hipLaunchKernelGGL(k_blend_fwd, dim3(blend_grid(ntiles)), dim3(kBlendThreads), 0, L.st, cam, ntiles, ranges, vals,
-                       rec, image, T_final, last, tile_walk);
+    hipLaunchKernelGGL(k_blend_fwd<kBlendRows>, dim3(blend_grid(ntiles)), dim3(kTile * kTile / kBlendRows), 0, L.st,
+                       cam, ntiles, ranges, vals, rec, image, T_final, last, tile_walk);
     if (L.prof) L.prof->end(L.st);
 }
 
@@ -724,10 +780,11 @@ void blend_backward(const Launch& L, const CamDev& cam, const uint2* ranges, con
     const int ntiles = cam.tiles_x * cam.tiles_y;
     if (L.prof) L.prof->begin("blend_bwd", L.st);
     const bool records = ga.grec_cap > 0;
-    auto kern = records ? (want_opacity ? k_blend_bwd<true, true> : k_blend_bwd<true, false>)
-                        : (want_opacity ? k_blend_bwd<false, true> : k_blend_bwd<false, false>);
-    hipLaunchKernelGGL(kern, dim3(blend_grid(ntiles)), dim3(kBlendThreads), 0, L.st, cam, ntiles, ranges, vals, rec,
-                       d_image, T_final, last, ga.tile_walk, ga.walk_off, ga.grec, (uint32_t)ga.grec_cap, accum);
+    constexpr int R = kBlendRows;
+    auto kern = records ? (want_opacity ? k_blend_bwd<R, true, true> : k_blend_bwd<R, true, false>)
+                        : (want_opacity ? k_blend_bwd<R, false, true> : k_blend_bwd<R, false, false>);
+    hipLaunchKernelGGL(kern, dim3(blend_grid(ntiles)), dim3(kTile * kTile / R), 0, L.st, cam, ntiles, ranges, vals,
+                       rec, d_image, T_final, last, ga.tile_walk, ga.walk_off, ga.grec, (uint32_t)ga.grec_cap, accum);
     if (L.prof) L.prof->end(L.st);
 }
 
