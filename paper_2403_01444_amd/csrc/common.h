@@ -349,6 +349,19 @@ __device__ __forceinline__ void blend_dx_terms(float dx, const float4& w0, float
     bdx = w0.w * dx;
 }
 
+// Branch-free form for the blend loops: the exponent and whether it passes
+// the cheap part of the test (0 = reject, 1 = accept, 2 = needs the exact
+// test near the threshold).
+__device__ __forceinline__ float blend_power(float adx2, float bdx, float dy, float C) {
+#pragma clang fp contract(off)
+    return -0.5f * (adx2 + C * dy * dy) - bdx * dy;
+}
+
+__device__ __forceinline__ bool blend_exact_test(float power, float opacity) {
+#pragma clang fp contract(off)
+    return opacity * spec_exp(power) >= 1.0f / 255.0f;
+}
+
 __device__ __forceinline__ bool blend_alpha_dy(float adx2, float bdx, float dy, const float4& w1, float pthr,
                                                float& G, float& raw, float& alpha) {
 #pragma clang fp contract(off)

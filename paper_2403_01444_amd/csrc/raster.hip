@@ -4,7 +4,7 @@
 #include "kernels.h"
 
 #ifndef GS3_BLEND_ROWS
-#define GS3_BLEND_ROWS 2
+#define GS3_BLEND_ROWS 1
 #endif
 
 namespace gs3 {
@@ -276,33 +276,51 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, end - b);
         if (!all) {
+            // branch-free per-pixel body: every lane evaluates, selects keep
+            // the state of pixels that do not take the contribution
             for (int j = 0; j < cnt; j++) {
-                const float4 w2 = s_w2[j];
+                const float4 w0 = s_w0[j], w1 = s_w1[j], w2 = s_w2[j];
                 const bool full = s_full[j];
                 const uint32_t bx0 = __float_as_uint(w2.y), bx1 = __float_as_uint(w2.z);
-                if (!full && (px < (int)(bx0 & 0xFFFFu) || px > (int)(bx1 & 0xFFFFu))) continue;
+                const bool inx = full || (px >= (int)(bx0 & 0xFFFFu) && px <= (int)(bx1 & 0xFFFFu));
                 const int y0 = (int)(bx0 >> 16), y1 = (int)(bx1 >> 16);
-                const float4 w0 = s_w0[j], w1 = s_w1[j];
+                const float pthr = w2.w;
                 float adx2, bdx;
                 blend_dx_terms(fpx - w0.x, w0, adx2, bdx);
+                float power[R];
+                bool ok[R], band[R];
+                bool any_band = false;
 #pragma unroll
                 for (int k = 0; k < R; k++) {
                     const int py = py0 + k;
-                    if (done[k] || (!full && (py < y0 || py > y1))) continue;
-                    float G, raw, alpha;
-                    if (!blend_alpha_dy(adx2, bdx, (float)py - w0.y, w1, w2.w, G, raw, alpha)) continue;
-                    const float Tn = T[k] * (1.0f - alpha);
-                    if (Tn < 1e-4f) {
-                        done[k] = true;
-                        continue;
-                    }
-                    const float wgt = alpha * T[k];
-                    c0[k] += wgt * w1.z;
-                    c1[k] += wgt * w1.w;
-                    c2[k] += wgt * w2.x;
-                    T[k] = Tn;
-                    last[k] = b - start + (uint32_t)j + 1u;
+                    power[k] = blend_power(adx2, bdx, (float)py - w0.y, w1.x);
+                    ok[k] = !done[k] && inx && (full || (py >= y0 && py <= y1)) && power[k] <= 0.0f &&
+                            power[k] >= pthr - 1e-4f;
+                    band[k] = ok[k] && power[k] < pthr + 1e-4f;
+                    any_band = any_band || band[k];
                 }
+                if (__any(any_band)) {
+#pragma unroll
+                    for (int k = 0; k < R; k++)
+                        if (band[k]) ok[k] = blend_exact_test(power[k], w1.y);
+                }
+                bool active = false;
+#pragma unroll
+                for (int k = 0; k < R; k++) {
+                    const float alpha = fminf(0.99f, w1.y * __expf(power[k]));
+                    const float Tn = T[k] * (1.0f - alpha);
+                    const bool stop = ok[k] && Tn < 1e-4f;
+                    const bool take = ok[k] && !stop;
+                    const float wgt = alpha * T[k];
+                    c0[k] = take ? c0[k] + wgt * w1.z : c0[k];
+                    c1[k] = take ? c1[k] + wgt * w1.w : c1[k];
+                    c2[k] = take ? c2[k] + wgt * w2.x : c2[k];
+                    T[k] = take ? Tn : T[k];
+                    last[k] = take ? b - start + (uint32_t)j + 1u : last[k];
+                    done[k] = done[k] || stop;
+                    active = active || !done[k];
+                }
+                if (!__any(active)) break;
             }
         }
         __syncthreads();
@@ -409,43 +427,60 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
             float gr[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             float gop = 0.f;
             bool act = false;
-            const float4 w2 = s_w2[j];
+            const float4 w0 = s_w0[j], w1 = s_w1[j], w2 = s_w2[j];
             const bool full = s_full[j];
             const uint32_t bx0 = __float_as_uint(w2.y), bx1 = __float_as_uint(w2.z);
-            if (full || (px >= (int)(bx0 & 0xFFFFu) && px <= (int)(bx1 & 0xFFFFu))) {
-                const int y0 = (int)(bx0 >> 16), y1 = (int)(bx1 >> 16);
-                const float4 w0 = s_w0[j], w1 = s_w1[j];
-                const float cr = w1.z, cg = w1.w, cb = w2.x;
-                const float dx = fpx - w0.x;
-                float adx2, bdx;
-                blend_dx_terms(dx, w0, adx2, bdx);
+            const bool inx = full || (px >= (int)(bx0 & 0xFFFFu) && px <= (int)(bx1 & 0xFFFFu));
+            const int y0 = (int)(bx0 >> 16), y1 = (int)(bx1 >> 16);
+            const float pthr = w2.w;
+            const float cr = w1.z, cg = w1.w, cb = w2.x;
+            const float dx = fpx - w0.x;
+            float adx2, bdx;
+            blend_dx_terms(dx, w0, adx2, bdx);
+            float power[R], dy[R];
+            bool ok[R], band[R];
+            bool any_band = false;
 #pragma unroll
-                for (int k = 0; k < R; k++) {
-                    const int py = py0 + k;
-                    if (ej >= last[k] || (!full && (py < y0 || py > y1))) continue;
-                    const float dy = (float)py - w0.y;
-                    float G, raw, alpha;
-                    if (!blend_alpha_dy(adx2, bdx, dy, w1, w2.w, G, raw, alpha)) continue;
-                    act = true;
-                    T[k] = T[k] / (1.0f - alpha);
-                    const float wgt = alpha * T[k];
-                    gr[5] += g0[k] * wgt;
-                    gr[6] += g1[k] * wgt;
-                    gr[7] += g2[k] * wgt;
-                    const float dal = T[k] * (g0[k] * (cr - b0[k]) + g1[k] * (cg - b1[k]) + g2[k] * (cb - b2[k]));
-                    b0[k] = alpha * cr + (1.0f - alpha) * b0[k];
-                    b1[k] = alpha * cg + (1.0f - alpha) * b1[k];
-                    b2[k] = alpha * cb + (1.0f - alpha) * b2[k];
-                    if (raw < 0.99f) {
-                        gop += dal * G;
-                        const float dp = dal * raw;
-                        gr[0] += dp * (w0.z * dx + w0.w * dy);
-                        gr[1] += dp * (w0.w * dx + w1.x * dy);
-                        gr[2] += dp * (-0.5f * dx * dx);
-                        gr[3] += dp * (-dx * dy);
-                        gr[4] += dp * (-0.5f * dy * dy);
-                    }
-                }
+            for (int k = 0; k < R; k++) {
+                const int py = py0 + k;
+                dy[k] = (float)py - w0.y;
+                power[k] = blend_power(adx2, bdx, dy[k], w1.x);
+                ok[k] = ej < last[k] && inx && (full || (py >= y0 && py <= y1)) && power[k] <= 0.0f &&
+                        power[k] >= pthr - 1e-4f;
+                band[k] = ok[k] && power[k] < pthr + 1e-4f;
+                any_band = any_band || band[k];
+            }
+            if (__any(any_band)) {
+#pragma unroll
+                for (int k = 0; k < R; k++)
+                    if (band[k]) ok[k] = blend_exact_test(power[k], w1.y);
+            }
+            // branch-free per-pixel body: selects keep the state of pixels
+            // that this Gaussian does not reach
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                const float G = __expf(power[k]);
+                const float raw = w1.y * G;
+                const float alpha = fminf(0.99f, raw);
+                act = act || ok[k];
+                const float Tk = ok[k] ? T[k] / (1.0f - alpha) : T[k];
+                T[k] = Tk;
+                const float wgt = ok[k] ? alpha * Tk : 0.0f;
+                gr[5] += g0[k] * wgt;
+                gr[6] += g1[k] * wgt;
+                gr[7] += g2[k] * wgt;
+                const float dal = Tk * (g0[k] * (cr - b0[k]) + g1[k] * (cg - b1[k]) + g2[k] * (cb - b2[k]));
+                b0[k] = ok[k] ? alpha * cr + (1.0f - alpha) * b0[k] : b0[k];
+                b1[k] = ok[k] ? alpha * cg + (1.0f - alpha) * b1[k] : b1[k];
+                b2[k] = ok[k] ? alpha * cb + (1.0f - alpha) * b2[k] : b2[k];
+                const bool unclamped = ok[k] && raw < 0.99f;
+                const float dp = unclamped ? dal * raw : 0.0f;
+                gop += unclamped ? dal * G : 0.0f;
+                gr[0] += dp * (w0.z * dx + w0.w * dy[k]);
+                gr[1] += dp * (w0.w * dx + w1.x * dy[k]);
+                gr[2] += dp * (-0.5f * dx * dx);
+                gr[3] += dp * (-dx * dy[k]);
+                gr[4] += dp * (-0.5f * dy[k] * dy[k]);
             }
             const bool any = __any(act);
             float red = 0.f, redop = 0.f;
