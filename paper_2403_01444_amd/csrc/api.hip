@@ -72,6 +72,8 @@ struct Slot {
     uint64_t* goff = nullptr;        // exclusive scan of the tile counts
     uint32_t* gpos = nullptr;        // per Gaussian and rectangle tile: slot of that pair
     uint32_t* tile_walk = nullptr;   // list entries walked per tile by the forward blend
+    int* order_fwd = nullptr;        // longest-first tile order of the forward blend
+    int* order_bwd = nullptr;        // and of the backward blend
     bool valid = false;
     GaussDev g{};
     CamDev cam{};
@@ -177,7 +179,8 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
         ok = ok && c->alloc(&s.rec, 3 * N) && c->alloc(&s.key, N) && c->alloc(&s.rect, N) && c->alloc(&s.count, N) &&
              c->alloc(&s.vals[0], PK) && c->alloc(&s.ranges, c->max_tiles) && c->alloc(&s.T_final, PX) &&
              c->alloc(&s.last, PX) && c->alloc(&s.total, 1) && c->alloc(&s.goff, N) &&
-             c->alloc(&s.gpos, cfg->grad_record_log2 > 0 ? PK : 1) && c->alloc(&s.tile_walk, c->max_tiles);
+             c->alloc(&s.gpos, cfg->grad_record_log2 > 0 ? PK : 1) && c->alloc(&s.tile_walk, c->max_tiles) &&
+             c->alloc(&s.order_fwd, c->max_tiles) && c->alloc(&s.order_bwd, c->max_tiles);
         if (ok && cfg->sort_mode == GS3_SORT_RADIX64)
             ok = c->alloc(&s.vals[1], PK) && c->alloc(&s.pkeys[0], PK) && c->alloc(&s.pkeys[1], PK);
     }
@@ -522,7 +525,8 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
             gpos_from_pairs(L, sl.pkeys[sl.cur], sl.vals[sl.cur], (int64_t)K, sl.rect, sl.goff, cd.tiles_x, cap,
                             sl.gpos);
     }
-    blend_forward(L, cd, sl.ranges, sl.vals[sl.cur], sl.rec, image, sl.T_final, sl.last, sl.tile_walk);
+    tile_order(L, sl.ranges, nullptr, ntiles, sl.order_fwd);
+    blend_forward(L, cd, sl.ranges, sl.vals[sl.cur], sl.rec, image, sl.T_final, sl.last, sl.tile_walk, sl.order_fwd);
     gs3_status st = c->check_launch("render");
     if (st != GS3_OK) return st;
     sl.g = gd;
@@ -546,8 +550,9 @@ gs3_status gs3_render_backward(gs3_ctx* c, int32_t slot, const float* d_image, c
     ga.rect = sl.rect; ga.goff = sl.goff; ga.gpos = sl.gpos; ga.ranges = sl.ranges; ga.tile_walk = sl.tile_walk;
     ga.walk_off = c->walk_off; ga.grec = c->grec; ga.grec_cap = (uint64_t)c->grec_cap;
     ga.cap = (uint64_t)c->cfg.max_pairs;
+    tile_order(L, sl.ranges, sl.tile_walk, ntiles, sl.order_bwd);
     blend_backward(L, sl.cam, sl.ranges, sl.vals[sl.cur], sl.rec, d_image, sl.T_final, sl.last, ga, c->accum,
-                   out->d_opacity != nullptr || out->d_opacity_logits != nullptr);
+                   out->d_opacity != nullptr || out->d_opacity_logits != nullptr, sl.order_bwd);
     GradsDev gd;
     gd.d_means = out->d_means; gd.d_quats = out->d_quats; gd.d_log_scales = out->d_log_scales;
     gd.d_opac = out->d_opacity_logits; gd.d_sh = out->d_sh; gd.d_dmu = sl.g.dmu ? out->d_dmu : nullptr;

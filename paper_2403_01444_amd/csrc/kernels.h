@@ -83,11 +83,15 @@ struct GatherDev {
     uint64_t cap;   // pair capacity (gpos length)
 };
 
+// Longest-first launch order of the tiles: by list length (walk == nullptr)
+// or by walked entries.  `order` holds ntiles ints.
+void tile_order(const Launch& L, const uint2* ranges, const uint32_t* walk, int ntiles, int* order);
+// `order` (optional) maps workgroups to tiles
 void blend_forward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals, const float4* rec,
-                   float* image, float* T_final, uint32_t* last, uint32_t* tile_walk);
+                   float* image, float* T_final, uint32_t* last, uint32_t* tile_walk, const int* order);
 void blend_backward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals,
                     const float4* rec, const float* d_image, const float* T_final, const uint32_t* last,
-                    const GatherDev& ga, float* accum, bool want_opacity);
+                    const GatherDev& ga, float* accum, bool want_opacity, const int* order);
 
 struct GradsDev {
     float *d_means, *d_quats, *d_log_scales, *d_opac, *d_sh, *d_dmu, *d_dq;

@@ -219,6 +219,44 @@ __device__ __forceinline__ int tile_of_block(int b, int ntiles) {
     return t;
 }
 
+// Longest-first tile schedule: tiles bucketed by the work they carry (list
+// length for the forward, walked entries for the backward) on a half-octave
+// scale, heaviest bucket first, so the long tiles start in the first wave of
+// workgroups instead of trailing the launch.  One workgroup; the order inside
+// a bucket is whatever the atomics give (it only affects scheduling).
+constexpr int kOrderBuckets = 66;
+__device__ __forceinline__ int work_bucket(uint32_t w) {
+    if (w == 0u) return 0;
+    const int lz = 31 - __clz(w);
+    const int half = lz >= 1 ? (int)((w >> (lz - 1)) & 1u) : 0;
+    return 1 + 2 * lz + half;
+}
+
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges,
+                                                     const uint32_t* __restrict__ walk, int ntiles,
+                                                     int* __restrict__ order) {
+    __shared__ uint32_t cnt[kOrderBuckets], off[kOrderBuckets];
+    for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) cnt[b] = 0u;
+    __syncthreads();
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+        const uint32_t w = walk ? walk[t] : ranges[t].y - ranges[t].x;
+        atomicAdd(&cnt[work_bucket(w)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0u;
+        for (int b = kOrderBuckets - 1; b >= 0; b--) {
+            off[b] = acc;
+            acc += cnt[b];
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+        const uint32_t w = walk ? walk[t] : ranges[t].y - ranges[t].x;
+        order[atomicAdd(&off[work_bucket(w)], 1u)] = t;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // blend forward (Eq. 4): one workgroup per 16x16 tile; each thread owns R
 // vertically adjacent pixels of one column, so a staged record is read from
@@ -232,14 +270,15 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                                                                  const float4* __restrict__ rec,
                                                                  float* __restrict__ image, float* __restrict__ T_final,
                                                                  uint32_t* __restrict__ last_out,
-                                                                 uint32_t* __restrict__ tile_walk) {
+                                                                 uint32_t* __restrict__ tile_walk,
+                                                                 const int* __restrict__ order) {
     constexpr int NT = kTile * kTile / R;
     __shared__ uint32_t s_walk;
+    const int tile = order ? order[blockIdx.x] : tile_of_block(blockIdx.x, ntiles);
     __shared__ float4 s_w0[NT];
     __shared__ float4 s_w1[NT];
     __shared__ float4 s_w2[NT];
     __shared__ uint8_t s_full[NT];
-    const int tile = tile_of_block(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int tx0p = tx * kTile, ty0p = ty * kTile;
@@ -366,7 +405,8 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
                                                                  const uint32_t* __restrict__ tile_walk,
                                                                  const uint32_t* __restrict__ walk_off,
                                                                  float* __restrict__ grec, uint32_t grec_cap,
-                                                                 float* __restrict__ accum) {
+                                                                 float* __restrict__ accum,
+                                                                 const int* __restrict__ order) {
     constexpr int NT = kTile * kTile / R, NW = NT / 64;
     __shared__ float4 s_w0[NT];
     __shared__ float4 s_w1[NT];
@@ -374,7 +414,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
     __shared__ uint32_t s_id[NT];
     __shared__ uint8_t s_full[NT];
     __shared__ float s_g[NW][9][NT];   // per-wave sums, [wave][term][entry]
-    const int tile = tile_of_block(blockIdx.x, ntiles);
+    const int tile = order ? order[blockIdx.x] : tile_of_block(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const uint32_t maxlast = tile_walk[tile];
     if (maxlast == 0) return;
@@ -800,26 +840,34 @@ static unsigned blend_grid(int ntiles) { return (unsigned)(((ntiles + 7) / 8) * 
 // pixels per thread of the blend kernels
 constexpr int kBlendRows = GS3_BLEND_ROWS;
 
+void tile_order(const Launch& L, const uint2* ranges, const uint32_t* walk, int ntiles, int* order) {
+    if (L.prof) L.prof->begin("tile_order", L.st);
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, L.st, ranges, walk, ntiles, order);
+    if (L.prof) L.prof->end(L.st);
+}
+
 void blend_forward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals, const float4* rec,
-                   float* image, float* T_final, uint32_t* last, uint32_t* tile_walk) {
+                   float* image, float* T_final, uint32_t* last, uint32_t* tile_walk, const int* order) {
     const int ntiles = cam.tiles_x * cam.tiles_y;
     if (L.prof) L.prof->begin("blend_fwd", L.st);
-    hipLaunchKernelGGL(k_blend_fwd<kBlendRows>, dim3(blend_grid(ntiles)), dim3(kTile * kTile / kBlendRows), 0, L.st,
-                       cam, ntiles, ranges, vals, rec, image, T_final, last, tile_walk);
+    hipLaunchKernelGGL(k_blend_fwd<kBlendRows>, dim3(order ? (unsigned)ntiles : blend_grid(ntiles)),
+                       dim3(kTile * kTile / kBlendRows), 0, L.st, cam, ntiles, ranges, vals, rec, image, T_final, last,
+                       tile_walk, order);
     if (L.prof) L.prof->end(L.st);
 }
 
 void blend_backward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals, const float4* rec,
                     const float* d_image, const float* T_final, const uint32_t* last, const GatherDev& ga,
-                    float* accum, bool want_opacity) {
+                    float* accum, bool want_opacity, const int* order) {
     const int ntiles = cam.tiles_x * cam.tiles_y;
     if (L.prof) L.prof->begin("blend_bwd", L.st);
     const bool records = ga.grec_cap > 0;
     constexpr int R = kBlendRows;
     auto kern = records ? (want_opacity ? k_blend_bwd<R, true, true> : k_blend_bwd<R, true, false>)
                         : (want_opacity ? k_blend_bwd<R, false, true> : k_blend_bwd<R, false, false>);
-    hipLaunchKernelGGL(kern, dim3(blend_grid(ntiles)), dim3(kTile * kTile / R), 0, L.st, cam, ntiles, ranges, vals,
-                       rec, d_image, T_final, last, ga.tile_walk, ga.walk_off, ga.grec, (uint32_t)ga.grec_cap, accum);
+    hipLaunchKernelGGL(kern, dim3(order ? (unsigned)ntiles : blend_grid(ntiles)), dim3(kTile * kTile / R), 0, L.st,
+                       cam, ntiles, ranges, vals, rec, d_image, T_final, last, ga.tile_walk, ga.walk_off, ga.grec,
+                       (uint32_t)ga.grec_cap, accum, order);
     if (L.prof) L.prof->end(L.st);
 }
 
