@@ -257,7 +257,7 @@ def main():
     ctx.profile(False)
     ctx.check_flags()
     kernels = {}
-    for name in ("ntc_fwd", "preprocess_fwd", "radix_pass", "bin_count", "scan", "bin_scatter", "tile_ranges", "tile_order",
+    for name in ("ntc_fwd", "preprocess_fwd", "radix_pass", "bin_count", "scan", "bin_gather", "bin_scatter", "tile_ranges", "tile_order",
                  "blend_fwd", "loss", "blend_bwd", "preprocess_bwd", "ntc_bwd", "ntc_scatter", "ntc_adam"):
         ms, cnt = ctx.profile_query(name)
         if cnt:

@@ -49,6 +49,7 @@ enum { GS3_SORT_DEPTH_FIRST = 0, GS3_SORT_RADIX64 = 1 };    /* pair-ordering met
 #define GS3_MAX_LEVELS 16
 #define GS3_TILE 16          /* tiles are 16 x 16 pixels */
 #define GS3_MAX_TILES 16384  /* ceil(W/16) * ceil(H/16) must not exceed this */
+#define GS3_MAX_WIDTH 4096   /* widest image (256 tile columns) */
 
 /* NTC shape (Sec. 4.1, Suppl. Sec. A): L levels of a multi-resolution hash
  * grid with F = 2 features per entry and 2^log2_T entries per hashed level,
@@ -67,7 +68,7 @@ typedef struct {
 typedef struct {
     int64_t max_gaussians;           /* capacity in Gaussians, >= 1 */
     int64_t max_pairs;               /* capacity in (Gaussian, tile) pairs per slot */
-    int32_t max_width, max_height;   /* largest image */
+    int32_t max_width, max_height;   /* largest image; max_width <= GS3_MAX_WIDTH */
     int32_t num_slots;               /* renders whose state is kept for backward, 1..8 */
     int32_t sort_mode;               /* GS3_SORT_DEPTH_FIRST (default) | GS3_SORT_RADIX64 */
     int32_t enable_ntc;              /* 0: rasterizer only */

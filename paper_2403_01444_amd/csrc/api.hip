@@ -96,6 +96,8 @@ struct gs3_ctx {
     uint64_t* scan_tmp = nullptr;
     uint32_t* bin_hist = nullptr;
     uint64_t* bin_base = nullptr;
+    uint2* bin_rect = nullptr;       // tile rectangles in depth order
+    uint32_t* bin_goff = nullptr;    // first pair slots in depth order (record mode)
     float* accum = nullptr;
     uint32_t* walk_off = nullptr;
     uint64_t* walk_total = nullptr;
@@ -167,6 +169,7 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
         (cfg->sort_mode != GS3_SORT_DEPTH_FIRST && cfg->sort_mode != GS3_SORT_RADIX64))
         return GS3_EINVAL;
     if (tiles_of(cfg->max_width, cfg->max_height) > GS3_MAX_TILES) return GS3_EINVAL;
+    if ((cfg->max_width + 15) / 16 > kMaxTilesX) return GS3_EINVAL;
     if ((cfg->max_width + kTile - 1) / kTile > 2048) return GS3_EINVAL;
     gs3_ctx* c = new gs3_ctx();
     c->cfg = *cfg;
@@ -199,7 +202,8 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
         ok = ok && c->alloc(&c->grec, 9 * c->grec_cap);
     }
     if (ok && cfg->sort_mode == GS3_SORT_DEPTH_FIRST)
-        ok = c->alloc(&c->bin_hist, bin_words) && c->alloc(&c->bin_base, bin_words);
+        ok = c->alloc(&c->bin_hist, bin_words) && c->alloc(&c->bin_base, bin_words) && c->alloc(&c->bin_rect, N) &&
+             c->alloc(&c->bin_goff, cfg->grad_record_log2 > 0 ? N : 1);
     if (ok && cfg->enable_ntc) {
         const gs3_ntc_config& nc = cfg->ntc;
         if (nc.levels != 16 || nc.feats != 2 || nc.hidden != 64 || nc.log2_T < 10 || nc.log2_T > 22 ||
@@ -495,10 +499,12 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
             const uint32_t* order = c->dvals[r];
             const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
             scan_u32_to_u64(L, sl.count, n, sl.goff, c->goff_total, c->scan_tmp);
-            bin_count(L, order, n, sl.rect, sl.count, cd.tiles_x, cd.tiles_y, c->bin_hist);
+            const bool rec_mode = c->grec_cap > 0;
+            bin_gather(L, order, n, sl.rect, sl.count, sl.goff, cap, c->bin_rect, rec_mode ? c->bin_goff : nullptr);
+            bin_count(L, order, n, c->bin_rect, cd.tiles_x, cd.tiles_y, c->bin_hist);
             scan_u32_to_u64(L, c->bin_hist, (int64_t)ntiles * nchunks, c->bin_base, sl.total, c->scan_tmp);
-            bin_scatter(L, order, n, sl.rect, sl.count, cd.tiles_x, cd.tiles_y, c->bin_base, cap, sl.vals[0],
-                        sl.goff, c->grec_cap > 0 ? sl.gpos : nullptr);
+            bin_scatter(L, order, n, c->bin_rect, c->bin_goff, cd.tiles_x, cd.tiles_y, c->bin_base, cap, sl.vals[0],
+                        rec_mode ? sl.gpos : nullptr);
             ranges_from_hist(L, c->bin_base, sl.total, ntiles, (int)nchunks, cap, sl.ranges, c->flags);
         } else {
             fill_u32(L, (uint32_t*)sl.ranges, 0u, 2 * (int64_t)ntiles);

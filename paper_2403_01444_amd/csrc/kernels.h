@@ -54,13 +54,17 @@ void ranges_from_keys(const Launch& L, const uint64_t* keys, int64_t K, int ntil
 // depth-first path: per-chunk tile histograms of depth-ordered Gaussians,
 // then an order-preserving scatter of Gaussian indices.
 constexpr int kBinChunk = 2048;
-void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
-               int tiles_x, int tiles_y, uint32_t* hist);
+constexpr int kMaxTilesX = 256;   // widest image: 4096 pixels
+// tile rectangles (empty for culled Gaussians) and, when sgoff is set, the
+// first pair slots goff, gathered into depth order
+void bin_gather(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
+                const uint64_t* goff, uint64_t cap, uint2* srect, uint32_t* sgoff);
+void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, int tiles_x, int tiles_y,
+               uint32_t* hist);
 // also records, for each Gaussian's k-th rectangle tile, the slot of that
 // pair: gpos[goff[id] + k] (goff = exclusive scan of the tile counts)
-void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
-                 int tiles_x, int tiles_y, const uint64_t* base, uint64_t cap, uint32_t* vals, const uint64_t* goff,
-                 uint32_t* gpos);
+void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, const uint32_t* sgoff,
+                 int tiles_x, int tiles_y, const uint64_t* base, uint64_t cap, uint32_t* vals, uint32_t* gpos);
 void gpos_from_pairs(const Launch& L, const uint64_t* keys, const uint32_t* vals, int64_t K, const uint2* rect,
                      const uint64_t* goff, int tiles_x, uint64_t cap, uint32_t* gpos);
 void ranges_from_hist(const Launch& L, const uint64_t* base, const uint64_t* total, int ntiles, int nchunks,

@@ -103,57 +103,67 @@ __global__ __launch_bounds__(256) void k_ranges_from_keys(const uint64_t* __rest
 
 // ---------------------------------------------------------------------------
 // depth-first ordering.  The Gaussians are first sorted by (depth bits,
-// index).  The sorted sequence is cut into chunks of kBinChunk.  A workgroup
-// stages one chunk's tile rectangles in LDS; each of its four waves owns one
-// tile row and walks the chunk in order, taking 64 Gaussians per step and
-// visiting (ballot, lowest set bit first) those whose rectangle spans its
-// row; the lanes cover the rectangle's columns, so one wave updates each
-// tile's cursor and the tiles of one Gaussian never collide.  Pass 1 counts
-// pairs per (tile, chunk); an exclusive scan in tile-major order gives each
+// index) and their tile rectangles gathered into that order.  The sorted
+// sequence is cut into chunks of kBinChunk.  A workgroup stages one chunk's
+// rectangles in LDS; each of its four waves owns one tile row and walks the
+// chunk in order, taking 64 Gaussians per step and visiting (ballot, lowest
+// set bit first) those whose rectangle spans its row.  Lane l keeps the
+// cursors of columns l, l + 64, ... in registers, so a Gaussian's tiles are
+// updated in parallel and no two lanes share a cursor.  Pass 1 counts pairs
+// per (tile, chunk); an exclusive scan in tile-major order gives each
 // (tile, chunk) its first slot; pass 2 repeats the walk and writes Gaussian
 // indices at consecutive slots.  Inside a tile the result is ordered by
 // (chunk, position in chunk), i.e. by (depth bits, index): the order a stable
 // (tile, depth) sort gives.
 // ---------------------------------------------------------------------------
 constexpr int kBinRowsPerBlock = 4;
+constexpr int kBinColSlots = kMaxTilesX / 64;   // register cursors per lane
+
+__global__ __launch_bounds__(256) void k_bin_gather(const uint32_t* __restrict__ order, int64_t n,
+                                                    const uint2* __restrict__ rect, const uint32_t* __restrict__ count,
+                                                    const uint64_t* __restrict__ goff, uint32_t cap,
+                                                    uint2* __restrict__ srect, uint32_t* __restrict__ sgoff) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const uint32_t id = order[e];
+    srect[e] = count[id] ? rect[id] : make_uint2(0xFFFF0000u, 0u);   // empty: no row spans
+    if (sgoff) {
+        const uint64_t go = goff[id];
+        sgoff[e] = go < (uint64_t)cap ? (uint32_t)go : cap;
+    }
+}
 
 template <bool kScatter>
 __global__ __launch_bounds__(256) void k_bin_rows(const uint32_t* __restrict__ order, int64_t n,
-                                                  const uint2* __restrict__ rect, const uint32_t* __restrict__ count,
+                                                  const uint2* __restrict__ srect, const uint32_t* __restrict__ sgoff,
                                                   int tiles_x, int tiles_y, int64_t nchunks,
                                                   uint32_t* __restrict__ hist, const uint64_t* __restrict__ base,
                                                   uint32_t cap, uint32_t* __restrict__ vals,
-                                                  const uint64_t* __restrict__ goff, uint32_t* __restrict__ gpos) {
+                                                  uint32_t* __restrict__ gpos) {
     // A cursor starts at min(first slot, cap) and moves at most kBinChunk
     // past it, so with cap < 2^31 it never wraps; slots at or past cap are
     // not written.
     __shared__ uint2 s_rect[kBinChunk];
     __shared__ uint32_t s_id[kBinChunk];
     __shared__ uint32_t s_goff[kScatter ? kBinChunk : 1];
-    extern __shared__ uint32_t s_cur_all[];   // kBinRowsPerBlock x tiles_x cursors
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t chunk = blockIdx.x;
     const int row = blockIdx.y * kBinRowsPerBlock + w;
-    uint32_t* s_cur = s_cur_all + w * tiles_x;
     const int64_t e0 = chunk * kBinChunk;
     const int m = (int)min((int64_t)kBinChunk, n - e0);
     for (int e = threadIdx.x; e < m; e += 256) {
-        const uint32_t id = order[e0 + e];
-        s_id[e] = id;
-        s_rect[e] = count[id] ? rect[id] : make_uint2(0xFFFF0000u, 0u);   // empty: no row spans
-        if (kScatter) {
-            const uint64_t go = gpos ? goff[id] : 0u;
-            s_goff[e] = go < (uint64_t)cap ? (uint32_t)go : cap;
-        }
+        s_id[e] = order[e0 + e];
+        s_rect[e] = srect[e0 + e];
+        if (kScatter) s_goff[e] = gpos ? sgoff[e0 + e] : 0u;
     }
-    if (row < tiles_y) {
-        for (int tx = lane; tx < tiles_x; tx += 64) {
-            if (kScatter) {
-                const uint64_t b = base[((int64_t)row * tiles_x + tx) * nchunks + chunk];
-                s_cur[tx] = b < (uint64_t)cap ? (uint32_t)b : cap;
-            } else {
-                s_cur[tx] = 0u;
-            }
+    uint32_t cur[kBinColSlots];
+#pragma unroll
+    for (int k = 0; k < kBinColSlots; k++) {
+        const int tx = k * 64 + lane;
+        cur[k] = 0u;
+        if (kScatter && row < tiles_y && tx < tiles_x) {
+            const uint64_t b = base[((int64_t)row * tiles_x + tx) * nchunks + chunk];
+            cur[k] = b < (uint64_t)cap ? (uint32_t)b : cap;
         }
     }
     __syncthreads();
@@ -170,24 +180,33 @@ __global__ __launch_bounds__(256) void k_bin_rows(const uint32_t* __restrict__ o
             const int j = __ffsll((unsigned long long)mask) - 1;
             mask &= mask - 1;
             const uint2 r = s_rect[eb + j];
-            const uint32_t idj = s_id[eb + j];
             const int tx0 = (int)(r.x & 0xFFFF), tx1 = (int)(r.y & 0xFFFF);
-            // slot of this Gaussian's k-th rectangle tile in its own pair range
-            const uint32_t k0 = kScatter ? s_goff[eb + j] + (uint32_t)((row - (int)(r.x >> 16)) * (tx1 - tx0 + 1)) : 0u;
-            for (int tx = tx0 + lane; tx <= tx1; tx += 64) {
-                const uint32_t pos = s_cur[tx];
-                s_cur[tx] = pos + 1u;
+            uint32_t idj = 0u, k0 = 0u;
+            if (kScatter) {
+                idj = s_id[eb + j];
+                // slot of this Gaussian's first tile of this row in its own pair range
+                k0 = s_goff[eb + j] + (uint32_t)((row - (int)(r.x >> 16)) * (tx1 - tx0 + 1));
+            }
+#pragma unroll
+            for (int k = 0; k < kBinColSlots; k++) {
+                const int tx = k * 64 + lane;
+                if (tx < tx0 || tx > tx1) continue;
+                const uint32_t pos = cur[k]++;
                 if (kScatter && pos < cap) {
                     vals[pos] = idj;
-                    const uint32_t k = k0 + (uint32_t)(tx - tx0);
-                    if (gpos && k < cap) gpos[k] = pos;
+                    const uint32_t kk = k0 + (uint32_t)(tx - tx0);
+                    if (gpos && kk < cap) gpos[kk] = pos;
                 }
             }
         }
     }
-    if (!kScatter)
-        for (int tx = lane; tx < tiles_x; tx += 64)
-            hist[((int64_t)row * tiles_x + tx) * nchunks + chunk] = s_cur[tx];
+    if (!kScatter) {
+#pragma unroll
+        for (int k = 0; k < kBinColSlots; k++) {
+            const int tx = k * 64 + lane;
+            if (tx < tiles_x) hist[((int64_t)row * tiles_x + tx) * nchunks + chunk] = cur[k];
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_ranges_from_hist(const uint64_t* __restrict__ base,
@@ -791,28 +810,35 @@ void ranges_from_keys(const Launch& L, const uint64_t* keys, int64_t K, int ntil
     if (L.prof) L.prof->end(L.st);
 }
 
-void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
-               int tiles_x, int tiles_y, uint32_t* hist) {
+void bin_gather(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
+                const uint64_t* goff, uint64_t cap, uint2* srect, uint32_t* sgoff) {
+    if (n <= 0) return;
+    if (L.prof) L.prof->begin("bin_gather", L.st);
+    hipLaunchKernelGGL(k_bin_gather, dim3(blocks_for(n, 256)), dim3(256), 0, L.st, order, n, rect, count, goff,
+                       (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull), srect, sgoff);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, int tiles_x, int tiles_y,
+               uint32_t* hist) {
     const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_count", L.st);
     dim3 grid((unsigned)nchunks, (unsigned)((tiles_y + kBinRowsPerBlock - 1) / kBinRowsPerBlock));
-    hipLaunchKernelGGL((k_bin_rows<false>), grid, dim3(256), kBinRowsPerBlock * tiles_x * sizeof(uint32_t), L.st, order, n, rect, count, tiles_x, tiles_y, nchunks,
-                       hist, (const uint64_t*)nullptr, 0u, (uint32_t*)nullptr, (const uint64_t*)nullptr,
+    hipLaunchKernelGGL((k_bin_rows<false>), grid, dim3(256), 0, L.st, order, n, srect, (const uint32_t*)nullptr,
+                       tiles_x, tiles_y, nchunks, hist, (const uint64_t*)nullptr, 0u, (uint32_t*)nullptr,
                        (uint32_t*)nullptr);
     if (L.prof) L.prof->end(L.st);
 }
 
-void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
-                 int tiles_x, int tiles_y, const uint64_t* base, uint64_t cap, uint32_t* vals, const uint64_t* goff,
-                 uint32_t* gpos) {
+void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, const uint32_t* sgoff,
+                 int tiles_x, int tiles_y, const uint64_t* base, uint64_t cap, uint32_t* vals, uint32_t* gpos) {
     const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_scatter", L.st);
     dim3 grid((unsigned)nchunks, (unsigned)((tiles_y + kBinRowsPerBlock - 1) / kBinRowsPerBlock));
-    hipLaunchKernelGGL((k_bin_rows<true>), grid, dim3(256), kBinRowsPerBlock * tiles_x * sizeof(uint32_t), L.st,
-                       order, n, rect, count, tiles_x, tiles_y, nchunks, (uint32_t*)nullptr, base, (uint32_t)cap, vals,
-                       goff, gpos);
+    hipLaunchKernelGGL((k_bin_rows<true>), grid, dim3(256), 0, L.st, order, n, srect, sgoff, tiles_x, tiles_y,
+                       nchunks, (uint32_t*)nullptr, base, (uint32_t)cap, vals, gpos);
     if (L.prof) L.prof->end(L.st);
 }
 
