@@ -26,6 +26,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+HERE = os.path.dirname(os.path.abspath(__file__))
 METRIC = "Stage-1 train iters/s + render FPS, 300K Gaussians @1352x1014, vs FP32 direct"
 HBM_PEAK_GBS = 8000.0
 
@@ -155,6 +156,31 @@ def algorithmic_work(name, st):
     if name == "bin_count":
         return "hbm", n * 16, "byte"
     return None
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by what the counters read for
+    a copy of known size), or None when there is no summary for this
+    workload or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", f"stage1_step_{workload}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ": " in line and not line.startswith(" "):
+            k, v = line.strip().split(": ", 1)
+            kv[k] = v
+    if kv.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for f in ("paper_2403_01444_amd/csrc/raster.hip", "paper_2403_01444_amd/csrc/common.h"):
+        h.update(open(os.path.join(HERE, f), "rb").read())
+    if h.hexdigest() != kv.get("source_sha256"):
+        return None
+    return int((float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_factor"]) +
+                float(kv["write_kib_per_dispatch"]) * float(kv["write_factor"])) * 1024)
 
 
 def cpu_baseline(g, cam, target_np, params, cfg):
@@ -332,7 +358,9 @@ def main():
             else:
                 ach, peak, u = amount / sec / 1e9, HBM_PEAK_GBS, "GB/s"
             roof = {"kernel": dom, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": u,
-                    "frac": round(ach / peak, 4), "traffic": None, "algorithmic_per_launch": int(amount),
+                    "frac": round(ach / peak, 4), "traffic": measured_traffic(dom, args.workload),
+                    "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    "algorithmic_per_launch": int(amount),
                     "algorithmic_unit": unit, "ms_per_launch": round(kernels[dom]["ms_per_launch"], 5)}
     all_roof = {}
     for k, v in kernels.items():

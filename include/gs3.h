@@ -125,6 +125,12 @@ typedef struct {
     float* d_conic;          /* n x 3 */
     float* d_opacity;        /* n */
     float* d_rgb;            /* n x 3 */
+    /* Stage 2 bookkeeping (Sec. 4.2), both accumulated, both or neither:
+     * vspace_grad[i] += |(dL/du W/2, dL/dv H/2)|, the norm of the gradient
+     * with respect to the Gaussian's mean in normalised device coordinates;
+     * vspace_count[i] += 1 when the Gaussian is visible in the view. */
+    float* vspace_grad;      /* n */
+    float* vspace_count;     /* n */
 } gs3_grads;
 
 typedef struct gs3_ctx gs3_ctx;
@@ -157,7 +163,8 @@ gs3_status gs3_morton_order(gs3_ctx* ctx, const float* means, int64_t n, const f
                             const float inv_extent[3], uint32_t* perm);
 
 /* dst[i, :] = src[perm[i], :] for n rows of row_floats floats (DEVICE;
- * dst must not alias src). */
+ * dst must not alias src; every perm[i] must index a row of src, which may
+ * hold more rows than dst). */
 gs3_status gs3_gather_rows(gs3_ctx* ctx, const float* src, const uint32_t* perm, int64_t n, int32_t row_floats,
                            float* dst);
 
@@ -240,6 +247,27 @@ gs3_status gs3_render_backward(gs3_ctx* ctx, int32_t slot, const float* d_image,
  * inputs. */
 gs3_status gs3_transform_bake(gs3_ctx* ctx, const gs3_gaussians* g, const float* dmu, const float* dq,
                               float* means_out, float* quats_out, float* sh_out);
+
+/* ---- Stage 2: adaptive 3DG addition (Sec. 4.2) ---------------------------- */
+
+/* Indices (ascending, written to idx, capacity n) of the elements that pass a
+ * threshold; their number goes to *count (host memory; the call waits for
+ * the stream).  With den != NULL: den[i] > 0 and num[i] / den[i] > threshold
+ * (the average view-space gradient above tau_grad); with den == NULL:
+ * num[i] >= threshold (pruning: opacity logits at or above logit(tau_alpha)).
+ * n may not exceed max_gaussians. */
+gs3_status gs3_select(gs3_ctx* ctx, const float* num, const float* den, int64_t n, float threshold,
+                      uint32_t* idx, int64_t* count);
+
+#define GS3_SPAWN 0   /* new Gaussian: identity rotation, opacity 0.1, source scale and SH */
+#define GS3_SPLIT 1   /* quantity control: source rotation, opacity and SH, 80% of the scale */
+/* Additional Gaussians around the sources src[idx[k]], k < m: mean
+ * mu + sqrt(2) R S z_k, a draw of N(mu, 2 Sigma) for z_k ~ N(0, I) given in
+ * z (m x 3, device); the other attributes by mode.  Outputs (device, m rows
+ * each) follow the gs3_gaussians layout and must not alias the sources. */
+gs3_status gs3_spawn(gs3_ctx* ctx, const gs3_gaussians* src, const uint32_t* idx, int64_t m, const float* z,
+                     int32_t mode, float* means, float* quats, float* log_scales, float* opacity_logits,
+                     float* sh);
 
 /* ---- Loss (Eq. 6) and optimiser ------------------------------------------ */
 

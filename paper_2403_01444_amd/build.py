@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgs3.so")
-SOURCES = ["api.hip", "sort.hip", "raster.hip", "loss.hip", "ntc.hip", "bake.hip"]
+SOURCES = ["api.hip", "sort.hip", "raster.hip", "loss.hip", "ntc.hip", "bake.hip", "stage2.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
 

@@ -96,6 +96,9 @@ struct gs3_ctx {
     uint64_t* scan_tmp = nullptr;
     uint32_t* bin_hist = nullptr;
     uint64_t* bin_base = nullptr;
+    uint32_t* sel_flag = nullptr;    // selection scratch (max_gaussians each)
+    uint32_t* sel_pos = nullptr;
+    uint64_t* sel_total = nullptr;
     uint2* bin_rect = nullptr;       // tile rectangles in depth order
     uint32_t* bin_goff = nullptr;    // first pair slots in depth order (record mode)
     float* accum = nullptr;
@@ -196,6 +199,7 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
          c->alloc(&c->scan_tmp, scan_tmp_words(scan_items) + 4) && c->alloc(&c->accum, 9 * N) &&
          c->alloc(&c->flags, 4) && c->alloc(&c->loss_maps, loss_map_floats(cfg->max_height, cfg->max_width)) &&
          c->alloc(&c->walk_off, c->max_tiles) && c->alloc(&c->walk_total, 1) && c->alloc(&c->goff_total, 1) &&
+         c->alloc(&c->sel_flag, N) && c->alloc(&c->sel_pos, N) && c->alloc(&c->sel_total, 1) &&
          c->alloc(&c->loss_bsum, 2 * (int64_t)loss_blocks(cfg->max_height, cfg->max_width));
     if (cfg->grad_record_log2 > 0) {
         c->grec_cap = std::min<int64_t>(PK, (int64_t)1 << std::min(cfg->grad_record_log2, 30));
@@ -564,6 +568,9 @@ gs3_status gs3_render_backward(gs3_ctx* c, int32_t slot, const float* d_image, c
     gd.d_opac = out->d_opacity_logits; gd.d_sh = out->d_sh; gd.d_dmu = sl.g.dmu ? out->d_dmu : nullptr;
     gd.d_dq = sl.g.dq ? out->d_dq : nullptr; gd.d_uv = out->d_uv; gd.d_conic = out->d_conic;
     gd.d_opacity = out->d_opacity; gd.d_rgb = out->d_rgb;
+    if ((out->vspace_grad == nullptr) != (out->vspace_count == nullptr))
+        return c->fail(GS3_EINVAL, "render_backward: vspace_grad and vspace_count go together");
+    gd.vgrad = out->vspace_grad; gd.vcount = out->vspace_count;
     preprocess_backward(L, sl.g, sl.cam, c->accum, ga, gd);
     return c->check_launch("render_backward");
 }
@@ -583,6 +590,44 @@ gs3_status gs3_transform_bake(gs3_ctx* c, const gs3_gaussians* g, const float* d
     static const ShRotConst rc = make_shrot_const();
     transform_bake(c->L(), gd, rc, means_out, quats_out, sh_out);
     return c->check_launch("transform_bake");
+}
+
+gs3_status gs3_select(gs3_ctx* c, const float* num, const float* den, int64_t n, float threshold, uint32_t* idx,
+                      int64_t* count) {
+    if (!c) return GS3_EINVAL;
+    if (!count || n < 0) return c->fail(GS3_EINVAL, "select: bad arguments");
+    if (n > c->cfg.max_gaussians) return c->fail(GS3_ECAPACITY, "select: n exceeds max_gaussians");
+    if (n > 0 && (!num || !idx)) return c->fail(GS3_EINVAL, "select: null array");
+    *count = 0;
+    if (n == 0) return GS3_OK;
+    select_indices(c->L(), num, den, n, threshold, c->sel_flag, c->sel_pos, c->sel_total, c->scan_tmp, idx);
+    uint64_t total = 0;
+    if (hipMemcpyAsync(&total, c->sel_total, sizeof(total), hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "select: copy of the count failed");
+    *count = (int64_t)total;
+    return c->check_launch("select");
+}
+
+gs3_status gs3_spawn(gs3_ctx* c, const gs3_gaussians* src, const uint32_t* idx, int64_t m, const float* z,
+                     int32_t mode, float* means, float* quats, float* log_scales, float* opacity_logits, float* sh) {
+    if (!c) return GS3_EINVAL;
+    if (!src || src->n < 0 || src->sh_degree < 0 || src->sh_degree > 3 || m < 0)
+        return c->fail(GS3_EINVAL, "spawn: bad arguments");
+    if (mode != GS3_SPAWN && mode != GS3_SPLIT) return c->fail(GS3_EINVAL, "spawn: unknown mode");
+    if (m == 0) return GS3_OK;
+    if (!idx || !z || !means || !quats || !log_scales || !opacity_logits || !sh || !src->means || !src->quats ||
+        !src->log_scales || !src->opacity_logits || !src->sh)
+        return c->fail(GS3_EINVAL, "spawn: null array");
+    if (means == src->means || quats == src->quats || log_scales == src->log_scales ||
+        opacity_logits == src->opacity_logits || sh == src->sh)
+        return c->fail(GS3_EINVAL, "spawn: outputs alias the sources");
+    GaussDev gd{};
+    gd.means = src->means; gd.quats = src->quats; gd.log_scales = src->log_scales; gd.opac = src->opacity_logits;
+    gd.sh = src->sh; gd.n = src->n; gd.sh_degree = src->sh_degree;
+    const float logit0 = (float)log(0.1 / 0.9), shrink = (float)log(0.8);
+    spawn(c->L(), gd, idx, m, z, mode, logit0, shrink, means, quats, log_scales, opacity_logits, sh);
+    return c->check_launch("spawn");
 }
 
 /* ---- loss / optimiser ----------------------------------------------------- */

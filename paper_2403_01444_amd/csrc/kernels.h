@@ -100,6 +100,7 @@ void blend_backward(const Launch& L, const CamDev& cam, const uint2* ranges, con
 struct GradsDev {
     float *d_means, *d_quats, *d_log_scales, *d_opac, *d_sh, *d_dmu, *d_dq;
     float *d_uv, *d_conic, *d_opacity, *d_rgb;
+    float *vgrad, *vcount;   // view-space gradient norm and visibility count (accumulated)
 };
 void preprocess_backward(const Launch& L, const GaussDev& g, const CamDev& cam, const float* accum,
                          const GatherDev& ga, const GradsDev& out);
@@ -115,6 +116,16 @@ struct ShRotConst {
 ShRotConst make_shrot_const();
 void transform_bake(const Launch& L, const GaussDev& g, const ShRotConst& rc, float* mu_out, float* q_out,
                     float* sh_out);
+
+// ---- Stage 2 (stage2.hip) -------------------------------------------------------
+// idx <- ascending indices i with den ? (den[i] > 0 && num[i]/den[i] > thr)
+// : num[i] >= thr; the count lands in *total.  flag, pos: n u32 scratch.
+void select_indices(const Launch& L, const float* num, const float* den, int64_t n, float thr, uint32_t* flag,
+                    uint32_t* pos, uint64_t* total, uint64_t* tmp, uint32_t* idx);
+// mode 0: spawn (identity rotation, opacity logit0); mode 1: split (rotation
+// and opacity kept, log-scale + log_shrink).  Position mu + sqrt(2) R S z.
+void spawn(const Launch& L, const GaussDev& g, const uint32_t* idx, int64_t m, const float* z, int mode,
+           float logit0, float log_shrink, float* mu, float* q, float* ls, float* lo, float* sh);
 
 // ---- loss (loss.hip) ---------------------------------------------------------
 struct LossWork {

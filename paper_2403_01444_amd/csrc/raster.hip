@@ -616,6 +616,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussDev g, CamDev cam, 
     const float du = a9[0], dv = a9[1], dA = a9[2], dB = a9[3], dC = a9[4], dop = a9[5];
     const float drgb[3] = {a9[6], a9[7], a9[8]};
     if (out.d_uv) { out.d_uv[2 * i] += du; out.d_uv[2 * i + 1] += dv; }
+    if (out.vgrad) {
+        // gradient with respect to the normalised-device-coordinate mean
+        const float gx = du * (0.5f * (float)cam.W), gy = dv * (0.5f * (float)cam.H);
+        out.vgrad[i] += sqrtf(gx * gx + gy * gy);
+        out.vcount[i] += 1.0f;
+    }
     if (out.d_conic) { out.d_conic[3 * i] += dA; out.d_conic[3 * i + 1] += dB; out.d_conic[3 * i + 2] += dC; }
     if (out.d_opacity) out.d_opacity[i] += dop;
     if (out.d_rgb) for (int k = 0; k < 3; k++) out.d_rgb[3 * i + k] += drgb[k];

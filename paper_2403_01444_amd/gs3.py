@@ -57,7 +57,8 @@ class CameraC(C.Structure):
 
 
 GRAD_FIELDS = ("d_means", "d_quats", "d_log_scales", "d_opacity_logits", "d_sh", "d_dmu", "d_dq", "d_uv",
-               "d_conic", "d_opacity", "d_rgb")
+               "d_conic", "d_opacity", "d_rgb", "vspace_grad", "vspace_count")
+GS3_SPAWN, GS3_SPLIT = 0, 1
 
 
 class GradsC(C.Structure):
@@ -67,7 +68,7 @@ class GradsC(C.Structure):
 EXPORTED = ("gs3_create", "gs3_destroy", "gs3_last_error", "gs3_set_stream", "gs3_morton_order",
             "gs3_gather_rows", "gs3_ntc_num_params",
             "gs3_ntc_load", "gs3_ntc_save", "gs3_ntc_forward", "gs3_ntc_backward", "gs3_ntc_prepare", "gs3_ntc_step",
-            "gs3_ntc_grads", "gs3_ntc_zero_grads", "gs3_warmup_loss", "gs3_render", "gs3_render_backward", "gs3_transform_bake",
+            "gs3_ntc_grads", "gs3_ntc_zero_grads", "gs3_warmup_loss", "gs3_render", "gs3_render_backward", "gs3_transform_bake", "gs3_select", "gs3_spawn",
             "gs3_loss", "gs3_adam", "gs3_zero", "gs3_debug_counts", "gs3_debug_pairs", "gs3_debug_ranges",
             "gs3_debug_gaussians", "gs3_debug_pixels", "gs3_check_flags", "gs3_profile_enable",
             "gs3_profile_reset", "gs3_profile_query")
@@ -104,6 +105,8 @@ def lib():
         "gs3_render": [vp, i32, C.POINTER(GaussiansC), vp, vp, C.POINTER(CameraC), vp],
         "gs3_render_backward": [vp, i32, vp, C.POINTER(GradsC)],
         "gs3_transform_bake": [vp, C.POINTER(GaussiansC), vp, vp, vp, vp, vp],
+        "gs3_select": [vp, vp, vp, i64, C.c_float, vp, C.POINTER(C.c_int64)],
+        "gs3_spawn": [vp, C.POINTER(GaussiansC), vp, i64, vp, i32, vp, vp, vp, vp, vp],
         "gs3_loss": [vp, vp, vp, i32, i32, f32, vp, vp],
         "gs3_adam": [vp, vp, vp, vp, vp, i64, i32, f32, f32, f32, f32],
         "gs3_zero": [vp, vp, i64],
@@ -228,7 +231,10 @@ def gs3_morton_order(h, means, aabb_min, inv_extent, perm):
 
 
 def gs3_gather_rows(h, src, perm, n, row_floats, dst):
-    _check(h, lib().gs3_gather_rows(h, _ptr(src, numel=n * row_floats), _ptr(perm, numel=n), n, row_floats,
+    """dst[i] = src[perm[i]] for n rows; src may hold more rows than dst."""
+    if src.numel() % max(row_floats, 1) or src.numel() < n * row_floats:
+        raise ValueError("src must hold whole rows of row_floats floats")
+    _check(h, lib().gs3_gather_rows(h, _ptr(src, name="src"), _ptr(perm, numel=n), n, row_floats,
                                     _ptr(dst, numel=n * row_floats)))
 
 
@@ -303,6 +309,20 @@ def gs3_transform_bake(h, gs: GaussiansGPU, dmu, dq, means_out, quats_out, sh_ou
     _check(h, lib().gs3_transform_bake(h, C.byref(gsc), _ptr(dmu, numel=3 * n, name="dmu"),
                                        _ptr(dq, numel=4 * n, name="dq"), _ptr(means_out, numel=3 * n),
                                        _ptr(quats_out, numel=4 * n), _ptr(sh_out, numel=gs.sh.numel())))
+
+
+def gs3_select(h, num, den, n, threshold, idx) -> int:
+    count = C.c_int64(0)
+    _check(h, lib().gs3_select(h, _ptr(num, numel=n, name="num"), _ptr(den, numel=n, name="den"), n,
+                               float(threshold), _ptr(idx, name="idx"), C.byref(count)))
+    return int(count.value)
+
+
+def gs3_spawn(h, src: GaussiansGPU, idx, m, z, mode, means, quats, log_scales, logits, sh):
+    sc = src.struct()
+    _check(h, lib().gs3_spawn(h, C.byref(sc), _ptr(idx, name="idx"), m, _ptr(z, numel=3 * m, name="z"), mode,
+                              _ptr(means, numel=3 * m), _ptr(quats, numel=4 * m), _ptr(log_scales, numel=3 * m),
+                              _ptr(logits, numel=m), _ptr(sh, numel=m * 3 * (src.sh_degree + 1) ** 2)))
 
 
 def gs3_loss(h, image, target, height, width, lam, loss, d_image):
@@ -448,6 +468,16 @@ class Context:
         gs3_gather_rows(self.h, src, perm, n, src.numel() // max(n, 1), dst)
         return dst
 
+    def take_rows(self, src, idx):
+        """src[idx] along the first axis (idx: int tensor on the device)."""
+        import torch
+        m = int(idx.numel())
+        rows = src.shape[0]
+        dst = torch.empty((m,) + tuple(src.shape[1:]), dtype=src.dtype, device=src.device)
+        if m:
+            gs3_gather_rows(self.h, src, idx.to(torch.int32).contiguous(), m, src.numel() // max(rows, 1), dst)
+        return dst
+
     def reorder(self, gs: "GaussiansGPU", aabb_min, inv_extent):
         """Morton-ordered copy of a Gaussian set and the permutation used."""
         perm = self.morton_order(gs.means, aabb_min, inv_extent)
@@ -502,6 +532,25 @@ class Context:
     def render_backward(self, d_image, grads: dict, slot=0):
         gs3_render_backward(self.h, slot, d_image, grads)
         return grads
+
+    def select(self, num, den=None, threshold=0.0):
+        """Ascending indices passing the threshold (int64 tensor on the device)."""
+        import torch
+        n = num.numel()
+        idx = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        m = gs3_select(self.h, num, den, n, threshold, idx)
+        return idx[:m].long()
+
+    def spawn(self, src: GaussiansGPU, idx, z, mode=GS3_SPAWN) -> GaussiansGPU:
+        """Additional Gaussians around src[idx] (positions from z ~ N(0, I))."""
+        import torch
+        m = int(idx.numel())
+        idx32 = idx.to(torch.int32).contiguous()
+        K = (src.sh_degree + 1) ** 2
+        out = GaussiansGPU(self.empty(m, 3), self.empty(m, 4), self.empty(m, 3), self.empty(m),
+                           self.empty(m, K, 3), src.sh_degree)
+        gs3_spawn(self.h, src, idx32, m, z, mode, out.means, out.quats, out.log_scales, out.opacity_logits, out.sh)
+        return out
 
     def transform_bake(self, gs: GaussiansGPU, dmu=None, dq=None) -> GaussiansGPU:
         """The transformed Gaussians (frame carry-over)."""

@@ -319,6 +319,40 @@ def object_motion(scene: SurfaceScene, seed: int, angle_deg: float = 1.5, transl
     return out
 
 
+def emerging_object(g: Gaussians, seed: int, n_obj: int = 2000, centre=(0.25, 0.05, -0.3),
+                    radius: float = 0.12) -> Gaussians:
+    """`g` plus a new textured sphere of `n_obj` flat, nearly opaque
+    Gaussians (an object that was not in the previous frame: something only
+    Stage 2 can add)."""
+    rng = np.random.default_rng(seed)
+    d = rng.normal(size=(n_obj, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    pts = np.asarray(centre) + radius * d
+    a = rng.normal(size=(n_obj, 3))
+    t1 = a - (a * d).sum(1, keepdims=True) * d
+    t1 /= np.linalg.norm(t1, axis=1, keepdims=True)
+    q = _quat_from_frame(t1, np.cross(d, t1), d)
+    spacing = math.sqrt(4 * math.pi * radius * radius / n_obj)
+    ls = np.stack([np.log(1.2 * spacing) + rng.normal(0, 0.15, n_obj),
+                   np.log(1.2 * spacing) + rng.normal(0, 0.15, n_obj),
+                   np.log(0.2 * spacing) + rng.normal(0, 0.15, n_obj)], 1)
+    col = np.tile(rng.uniform(0.2, 0.8, size=3), (n_obj, 1))
+    for amp, freq in ((0.15, 4.0), (0.1, 12.0)):
+        for ch in range(3):
+            f = rng.normal(size=3)
+            f *= freq / np.linalg.norm(f)
+            col[:, ch] += amp * np.sin(2 * math.pi * (pts @ f) + rng.uniform(0, 2 * math.pi))
+    col = np.clip(col, 0.02, 0.98)
+    K = (g.sh_degree + 1) ** 2
+    sh = np.zeros((n_obj, K, 3))
+    sh[:, 0, :] = (col - 0.5) / _Y00
+    f32 = np.float32
+    return Gaussians(np.concatenate([g.means, pts.astype(f32)]), np.concatenate([g.quats, q.astype(f32)]),
+                     np.concatenate([g.log_scales, ls.astype(f32)]),
+                     np.concatenate([g.opacity_logits, rng.normal(2.5, 0.5, n_obj).astype(f32)]),
+                     np.concatenate([g.sh, sh.astype(f32)]), g.sh_degree)
+
+
 # --- NTC configuration and initial parameters --------------------------------
 
 @dataclass
@@ -397,6 +431,8 @@ def workload(name: str, seed: int = 0):
                       forward arc (azimuth in [-30, 30] deg) + one held-out
                       camera at azimuth 1.5 deg.
     grad-200-32px   : 200 Gaussians, SH3, one 32x32 camera.
+    surfaces-300k-1352px-new : the same, and in the next frame a new object
+                      (a textured sphere of about 2K Gaussians) appears.
     surfaces-50k-256px : 50K Gaussians (SH1) of the same kind of scene, 12 arc
                       cameras at 256x256, held-out camera at azimuth 0 (midway
                       between two training views).
@@ -424,6 +460,11 @@ def workload(name: str, seed: int = 0):
         cams = arc_cameras(12, 256, 256)
         nxt = object_motion(sc, seed + 1000)
         return sc.gaussians, cams, [look_at_camera(256, 256, azimuth_deg=0.0)], nxt
+    if name == "surfaces-300k-1352px-new":
+        sc = surface_scene(300_000, 3, seed)
+        cams = arc_cameras(20, 1352, 1014)
+        nxt = emerging_object(object_motion(sc, seed + 1000), seed + 2000)
+        return sc.gaussians, cams, [look_at_camera(1352, 1014, azimuth_deg=1.5)], nxt
     if name == "surfaces-300k-1352px":
         sc = surface_scene(300_000, 3, seed)
         cams = arc_cameras(20, 1352, 1014)

@@ -47,7 +47,9 @@ class Stage1NTC:
         # per-frame setup: the means stay frozen for the whole of Stage 1
         ctx.ntc_prepare(gauss.means)
 
-    def step(self) -> int:
+    def step(self, track=None) -> int:
+        """One iteration.  `track` = (vspace_grad, vspace_count) accumulates
+        the view-space gradient statistics Stage 2 selects from."""
         ctx, cam = self.ctx, None
         v = self.views.next()
         cam = self.cams[v]
@@ -57,10 +59,23 @@ class Stage1NTC:
         ctx.render(self.g, cam, self.dmu, self.dq, image=img)
         ctx.loss(img, self.targets[v], self.lam, loss=self.loss, d_image=dimg)
         ctx.zero(self.d_dmu, self.d_dq)
-        ctx.render_backward(dimg, {"d_dmu": self.d_dmu, "d_dq": self.d_dq})
+        grads = {"d_dmu": self.d_dmu, "d_dq": self.d_dq}
+        if track is not None:
+            grads["vspace_grad"], grads["vspace_count"] = track
+        ctx.render_backward(dimg, grads)
         ctx.ntc_backward(self.g.means, self.d_dmu, self.d_dq)
         ctx.ntc_step(self.lr, self.betas[0], self.betas[1], self.eps)
         return v
+
+    def run(self, iters: int):
+        """`iters` iterations; the view-space gradient statistics of the last
+        epoch (the last len(views) iterations) are returned for Stage 2."""
+        n = self.g.n
+        vg, vc = self.ctx.zeros(n), self.ctx.zeros(n)
+        last = min(iters, len(self.cams))
+        for it in range(iters):
+            self.step((vg, vc) if it >= iters - last else None)
+        return vg, vc
 
     def transform(self):
         self.ctx.ntc_forward(self.g.means, self.dmu, self.dq)
@@ -105,6 +120,112 @@ class Stage1Direct:
 
     def transform(self):
         return self.dmu, self.dq
+
+
+class Stage2:
+    """Adaptive 3DG addition (Sec. 4.2).  Additional Gaussians are spawned
+    around the frame's (transformed, baked) Gaussians whose average view-space
+    gradient over the last Stage-1 epoch exceeds tau_grad, at positions drawn
+    from N(mu, 2 Sigma), with the source's SH and scale, identity rotation and
+    opacity 0.1.  Only the additional Gaussians are optimised, with the same
+    loss as Stage 1 and 3DG-S's per-attribute learning rates (Suppl. A).  At
+    the end of each epoch, additional Gaussians above tau_grad are split
+    (rotation, SH, opacity kept, 80% scale) and those below opacity tau_alpha
+    are discarded.  The additional Gaussians belong to this frame only."""
+
+    LR = {"means": 0.0024, "sh": 0.0375, "opacity_logits": 0.75, "log_scales": 0.075, "quats": 0.015}
+    ATTRS = ("means", "quats", "log_scales", "opacity_logits", "sh")
+
+    def __init__(self, ctx: gs3.Context, base: gs3.GaussiansGPU, cams, targets, vgrad, vcount, lam: float = 0.2,
+                 tau_grad: float = 0.00015, tau_alpha: float = 0.01, max_add: int | None = None, seed: int = 0,
+                 betas=(0.9, 0.999), eps: float = 1e-15):
+        import torch
+        self.ctx, self.base, self.cams, self.targets = ctx, base, cams, targets
+        self.lam, self.tau_grad, self.betas, self.eps = lam, tau_grad, betas, eps
+        self.logit_alpha = float(np.float32(math.log(tau_alpha / (1.0 - tau_alpha))))
+        self.rng = np.random.default_rng(seed)
+        self.max_add = max_add
+        self.views = _Views(len(cams), seed + 1)
+        idx = ctx.select(vgrad, vcount, tau_grad)
+        idx = self._cap(idx, 0)
+        z = torch.from_numpy(self.rng.normal(size=(int(idx.numel()), 3)).astype(np.float32)).to(ctx.device)
+        add = ctx.spawn(base, idx, z, gs3.GS3_SPAWN)
+        self.spawned = int(idx.numel())
+        self._set(add, None)
+        H = max(c.height for c in cams)
+        W = max(c.width for c in cams)
+        self.img, self.dimg = ctx.empty(3 * H * W), ctx.empty(3 * H * W)
+        self.loss = ctx.empty(1)
+        self.t = 0
+        self.it = 0
+
+    def _cap(self, idx, current):
+        if self.max_add is not None and idx.numel() + current > self.max_add:
+            idx = idx[: max(self.max_add - current, 0)]
+        return idx
+
+    def _set(self, add: gs3.GaussiansGPU, state):
+        """Union [base | add] with its Adam state (state: previous m, v rows
+        of `add`, or None for zeros) and fresh view-space statistics."""
+        import torch
+        ctx, b = self.ctx, self.base
+        self.n_base, self.m = b.n, add.n
+        self.all = gs3.GaussiansGPU(*(torch.cat([getattr(b, a), getattr(add, a)]).contiguous() for a in self.ATTRS),
+                                    b.sh_degree)
+        self.grad = {a: torch.zeros_like(getattr(self.all, a)) for a in self.ATTRS}
+        if state is None:
+            state = {a: (torch.zeros_like(getattr(add, a)), torch.zeros_like(getattr(add, a))) for a in self.ATTRS}
+        self.state = state
+        self.vg, self.vc = ctx.zeros(self.n_base + self.m), ctx.zeros(self.n_base + self.m)
+
+    def added(self) -> gs3.GaussiansGPU:
+        return gs3.GaussiansGPU(*(getattr(self.all, a)[self.n_base:] for a in self.ATTRS), self.all.sh_degree)
+
+    def step(self) -> int:
+        ctx = self.ctx
+        v = self.views.next()
+        cam = self.cams[v]
+        P = 3 * cam.height * cam.width
+        img, dimg = self.img[:P].view(3, cam.height, cam.width), self.dimg[:P].view(3, cam.height, cam.width)
+        ctx.render(self.all, cam, image=img)
+        ctx.loss(img, self.targets[v], self.lam, loss=self.loss, d_image=dimg)
+        if self.m:
+            ctx.zero(*self.grad.values())
+            g = {"d_means": self.grad["means"], "d_quats": self.grad["quats"],
+                 "d_log_scales": self.grad["log_scales"], "d_opacity_logits": self.grad["opacity_logits"],
+                 "d_sh": self.grad["sh"], "vspace_grad": self.vg, "vspace_count": self.vc}
+            ctx.render_backward(dimg, g)
+            self.t += 1
+            nb = self.n_base
+            for a in self.ATTRS:
+                p = getattr(self.all, a)[nb:]
+                m_, v_ = self.state[a]
+                ctx.adam(p, self.grad[a][nb:], m_, v_, self.t, self.LR[a], self.betas[0], self.betas[1], self.eps)
+        self.it += 1
+        if self.it % len(self.cams) == 0:
+            self.control()
+        return v
+
+    def control(self):
+        """Quantity control at the end of an epoch: split the additional
+        Gaussians above tau_grad, then drop those below opacity tau_alpha."""
+        import torch
+        if self.m == 0:
+            return
+        ctx, nb = self.ctx, self.n_base
+        add = self.added()
+        idx = ctx.select(self.vg[nb:].contiguous(), self.vc[nb:].contiguous(), self.tau_grad)
+        idx = self._cap(idx, self.m)
+        z = torch.from_numpy(self.rng.normal(size=(int(idx.numel()), 3)).astype(np.float32)).to(ctx.device)
+        new = ctx.spawn(add, idx, z, gs3.GS3_SPLIT)
+        merged = gs3.GaussiansGPU(*(torch.cat([getattr(add, a), getattr(new, a)]).contiguous() for a in self.ATTRS),
+                                  add.sh_degree)
+        state = {a: tuple(torch.cat([s, torch.zeros_like(getattr(new, a))]).contiguous() for s in self.state[a])
+                 for a in self.ATTRS}
+        keep = ctx.select(merged.opacity_logits, None, self.logit_alpha)
+        kept = gs3.GaussiansGPU(*(ctx.take_rows(getattr(merged, a), keep) for a in self.ATTRS), add.sh_degree)
+        state = {a: tuple(ctx.take_rows(s, keep) for s in state[a]) for a in self.ATTRS}
+        self._set(kept, state)
 
 
 def warmup(ctx: gs3.Context, points, iters: int = 3000, lr: float = 0.002, betas=(0.9, 0.99), eps: float = 1e-15):

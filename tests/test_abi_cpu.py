@@ -46,7 +46,7 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(gs3.NtcConfigC) == 4 * 27
     assert ctypes.sizeof(gs3.ConfigC) == 16 + 24 + 4 * 27 + 4   # padded to 8
     assert ctypes.sizeof(gs3.CameraC) == 4 * (7 + 12 + 3 + 3)
-    assert ctypes.sizeof(gs3.GradsC) == 8 * 11
+    assert ctypes.sizeof(gs3.GradsC) == 8 * 13
 
 
 def test_context_refuses_without_gpu():
