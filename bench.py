@@ -49,6 +49,12 @@ def parse():
     ap.add_argument("--quality-workload", default="surfaces-300k-1352px",
                     help="capture-like scene for the equal-PSNR comparison")
     ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--stream", type=int, default=0,
+                    help="instead of the timing run, stream this many frames of a capture-like sequence "
+                         "(Stage 1 + bake + Stage 2 + four novel views per frame)")
+    ap.add_argument("--stream-gaussians", type=int, default=500_000)
+    ap.add_argument("--stream-size", default="1920x1080")
+    ap.add_argument("--stream-views", type=int, default=15)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB, a kernel of known traffic "
                          "for calibrating the HBM byte counters")
@@ -116,6 +122,45 @@ def quality(args, workload, iters=150, direct_iters=300):
         res["direct_log"] = [(i, round(t, 5), round(p, 4)) for i, t, p in direct_log]
         res["ntc_without_warmup_log"] = [(i, round(t, 5), round(p, 4)) for i, t, p in cold_log]
     return res
+
+
+def stream(args):
+    """Streaming run: per frame Stage 1 (150 iterations), bake, Stage 2 (100
+    iterations), four novel views; new objects appear at 1/3 and 2/3 of the
+    sequence.  Prints one JSON line with per-frame and mean figures."""
+    import torch
+    from paper_2403_01444_amd import gs3, stream as st, synth
+    W, H = (int(v) for v in args.stream_size.split("x"))
+    cfg = synth.NTCConfig()
+    sc = synth.surface_scene(args.stream_gaussians, 3, 0)
+    cams = synth.arc_cameras(args.stream_views, W, H)
+    novel = st.novel_cameras(W, H)
+    cap = 100_000
+    ctx = gs3.Context(sc.gaussians.n + cap + 2 * 2000, 120_000_000, W, H, ntc=cfg, precision=args.precision)
+    g0 = gs3.GaussiansGPU.from_host(sc.gaussians)
+    tr = st.StreamTrainer(ctx, g0, cams, novel, cfg, warmup_iters=args.warmup_iters, max_add=cap)
+    frames = []
+    new_at = (max(1, args.stream // 3), max(2, 2 * args.stream // 3))
+    for f, gt in st.synthetic_sequence(sc, args.stream, 1, new_objects=new_at):
+        gtg = gs3.GaussiansGPU.from_host(gt)
+        targets = [ctx.render(gtg, c).clone() for c in cams]
+        novel_t = [ctx.render(gtg, c).clone() for c in novel]
+        r = tr.frame(f, targets, novel_t)
+        frames.append(r)
+        print(json.dumps({"frame": f, "stage1_s": round(r.stage1_s, 4), "stage2_s": round(r.stage2_s, 4),
+                          "spawned": r.spawned, "additional": r.additional,
+                          "psnr_stage1": round(r.psnr_stage1, 3), "psnr_stage2": round(r.psnr_stage2, 3),
+                          "render_fps": round(r.render_fps, 1)}), file=sys.stderr, flush=True)
+    mean = lambda k: float(np.mean([getattr(r, k) for r in frames]))
+    print(json.dumps({
+        "mode": "stream", "frames": len(frames), "gaussians": sc.gaussians.n, "width": W, "height": H,
+        "training_views": len(cams), "novel_views": len(novel), "new_objects_at": list(new_at),
+        "warmup_s": round(tr.warmup_s, 3),
+        "s_per_frame": round(mean("stage1_s") + mean("stage2_s"), 4),
+        "stage1_s": round(mean("stage1_s"), 4), "stage2_s": round(mean("stage2_s"), 4),
+        "psnr_stage1": round(mean("psnr_stage1"), 3), "psnr_stage2": round(mean("psnr_stage2"), 3),
+        "render_fps": round(mean("render_fps"), 1), "additional_mean": round(mean("additional"), 1),
+        "ntc_precision": args.precision, "data": "synthetic"}))
 
 
 # Per-unit algorithmic work of each kernel.  The blend kernels are bound by
@@ -225,6 +270,9 @@ def main():
     torch.cuda.set_device(0)
     if args.protocol:
         print(json.dumps(quality(args, args.quality_workload, direct_iters=args.protocol_iters)))
+        return
+    if args.stream:
+        stream(args)
         return
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib << 18, device="cuda")
