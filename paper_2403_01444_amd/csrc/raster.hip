@@ -340,7 +340,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                 const float4 w0 = s_w0[j], w1 = s_w1[j], w2 = s_w2[j];
                 const bool full = s_full[j];
                 const uint32_t bx0 = __float_as_uint(w2.y), bx1 = __float_as_uint(w2.z);
-                const bool inx = full || (px >= (int)(bx0 & 0xFFFFu) && px <= (int)(bx1 & 0xFFFFu));
+                const bool inx = full | ((px >= (int)(bx0 & 0xFFFFu)) & (px <= (int)(bx1 & 0xFFFFu)));
                 const int y0 = (int)(bx0 >> 16), y1 = (int)(bx1 >> 16);
                 const float pthr = w2.w;
                 float adx2, bdx;
@@ -352,9 +352,9 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                 for (int k = 0; k < R; k++) {
                     const int py = py0 + k;
                     power[k] = blend_power(adx2, bdx, (float)py - w0.y, w1.x);
-                    ok[k] = !done[k] && inx && (full || (py >= y0 && py <= y1)) && power[k] <= 0.0f &&
-                            power[k] >= pthr - 1e-4f;
-                    band[k] = ok[k] && power[k] < pthr + 1e-4f;
+                    ok[k] = !done[k] & inx & (full | ((py >= y0) & (py <= y1))) & (power[k] <= 0.0f) &
+                            (power[k] >= pthr - 1e-4f);
+                    band[k] = ok[k] & (power[k] < pthr + 1e-4f);
                     any_band = any_band || band[k];
                 }
                 if (__any(any_band)) {
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
             const float4 w0 = s_w0[j], w1 = s_w1[j], w2 = s_w2[j];
             const bool full = s_full[j];
             const uint32_t bx0 = __float_as_uint(w2.y), bx1 = __float_as_uint(w2.z);
-            const bool inx = full || (px >= (int)(bx0 & 0xFFFFu) && px <= (int)(bx1 & 0xFFFFu));
+            const bool inx = full | ((px >= (int)(bx0 & 0xFFFFu)) & (px <= (int)(bx1 & 0xFFFFu)));
             const int y0 = (int)(bx0 >> 16), y1 = (int)(bx1 >> 16);
             const float pthr = w2.w;
             const float cr = w1.z, cg = w1.w, cb = w2.x;
@@ -504,9 +504,9 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
                 const int py = py0 + k;
                 dy[k] = (float)py - w0.y;
                 power[k] = blend_power(adx2, bdx, dy[k], w1.x);
-                ok[k] = ej < last[k] && inx && (full || (py >= y0 && py <= y1)) && power[k] <= 0.0f &&
-                        power[k] >= pthr - 1e-4f;
-                band[k] = ok[k] && power[k] < pthr + 1e-4f;
+                ok[k] = (ej < last[k]) & inx & (full | ((py >= y0) & (py <= y1))) & (power[k] <= 0.0f) &
+                        (power[k] >= pthr - 1e-4f);
+                band[k] = ok[k] & (power[k] < pthr + 1e-4f);
                 any_band = any_band || band[k];
             }
             if (__any(any_band)) {
@@ -522,7 +522,8 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
                 const float raw = w1.y * G;
                 const float alpha = fminf(0.99f, raw);
                 act = act || ok[k];
-                const float Tk = ok[k] ? T[k] / (1.0f - alpha) : T[k];
+                // T recovery T_i = T_{i+1} / (1 - alpha_i), with the hardware reciprocal (1 ulp)
+                const float Tk = ok[k] ? T[k] * __builtin_amdgcn_rcpf(1.0f - alpha) : T[k];
                 T[k] = Tk;
                 const float wgt = ok[k] ? alpha * Tk : 0.0f;
                 gr[5] += g0[k] * wgt;
