@@ -53,7 +53,10 @@ void emit_pairs(const Launch& L, int64_t n, const uint32_t* key, const uint2* re
 void ranges_from_keys(const Launch& L, const uint64_t* keys, int64_t K, int ntiles, uint2* ranges);
 // depth-first path: per-chunk tile histograms of depth-ordered Gaussians,
 // then an order-preserving scatter of Gaussian indices.
-constexpr int kBinChunk = 2048;
+#ifndef GS3_BIN_CHUNK
+#define GS3_BIN_CHUNK 512
+#endif
+constexpr int kBinChunk = GS3_BIN_CHUNK;
 constexpr int kMaxTilesX = 256;   // widest image: 4096 pixels
 // tile rectangles (empty for culled Gaussians) and, when sgoff is set, the
 // first pair slots goff, gathered into depth order

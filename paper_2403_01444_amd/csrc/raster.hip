@@ -147,8 +147,9 @@ __global__ __launch_bounds__(256) void k_bin_rows(const uint32_t* __restrict__ o
     __shared__ uint32_t s_id[kBinChunk];
     __shared__ uint32_t s_goff[kScatter ? kBinChunk : 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rg = (int)blockIdx.y;
     const int64_t chunk = blockIdx.x;
-    const int row = blockIdx.y * kBinRowsPerBlock + w;
+    const int row = rg * kBinRowsPerBlock + w;
     const int64_t e0 = chunk * kBinChunk;
     const int m = (int)min((int64_t)kBinChunk, n - e0);
     for (int e = threadIdx.x; e < m; e += 256) {
@@ -826,13 +827,16 @@ void bin_gather(const Launch& L, const uint32_t* order, int64_t n, const uint2* 
     if (L.prof) L.prof->end(L.st);
 }
 
+static dim3 bin_grid(int64_t nchunks, int tiles_y) {
+    return dim3((unsigned)nchunks, (unsigned)((tiles_y + kBinRowsPerBlock - 1) / kBinRowsPerBlock));
+}
+
 void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, int tiles_x, int tiles_y,
                uint32_t* hist) {
     const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_count", L.st);
-    dim3 grid((unsigned)nchunks, (unsigned)((tiles_y + kBinRowsPerBlock - 1) / kBinRowsPerBlock));
-    hipLaunchKernelGGL((k_bin_rows<false>), grid, dim3(256), 0, L.st, order, n, srect, (const uint32_t*)nullptr,
+    hipLaunchKernelGGL((k_bin_rows<false>), bin_grid(nchunks, tiles_y), dim3(256), 0, L.st, order, n, srect, (const uint32_t*)nullptr,
                        tiles_x, tiles_y, nchunks, hist, (const uint64_t*)nullptr, 0u, (uint32_t*)nullptr,
                        (uint32_t*)nullptr);
     if (L.prof) L.prof->end(L.st);
@@ -843,8 +847,7 @@ void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2*
     const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_scatter", L.st);
-    dim3 grid((unsigned)nchunks, (unsigned)((tiles_y + kBinRowsPerBlock - 1) / kBinRowsPerBlock));
-    hipLaunchKernelGGL((k_bin_rows<true>), grid, dim3(256), 0, L.st, order, n, srect, sgoff, tiles_x, tiles_y,
+    hipLaunchKernelGGL((k_bin_rows<true>), bin_grid(nchunks, tiles_y), dim3(256), 0, L.st, order, n, srect, sgoff, tiles_x, tiles_y,
                        nchunks, (uint32_t*)nullptr, base, (uint32_t)cap, vals, gpos);
     if (L.prof) L.prof->end(L.st);
 }
