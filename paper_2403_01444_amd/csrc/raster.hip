@@ -3,8 +3,11 @@
 // per-Gaussian kernels.
 #include "kernels.h"
 
-#ifndef GS3_BLEND_ROWS
-#define GS3_BLEND_ROWS 1
+#ifndef GS3_BLEND_ROWS_FWD
+#define GS3_BLEND_ROWS_FWD 1
+#endif
+#ifndef GS3_BLEND_ROWS_BWD
+#define GS3_BLEND_ROWS_BWD 1
 #endif
 
 namespace gs3 {
@@ -874,7 +877,8 @@ void pairs_total_check(const Launch& L, const uint64_t* total, uint64_t cap, int
 static unsigned blend_grid(int ntiles) { return (unsigned)(((ntiles + 7) / 8) * 8); }
 
 // pixels per thread of the blend kernels
-constexpr int kBlendRows = GS3_BLEND_ROWS;
+constexpr int kBlendRows = GS3_BLEND_ROWS_FWD;
+constexpr int kBlendRowsBwd = GS3_BLEND_ROWS_BWD;
 
 void tile_order(const Launch& L, const uint2* ranges, const uint32_t* walk, int ntiles, int* order) {
     if (L.prof) L.prof->begin("tile_order", L.st);
@@ -898,7 +902,7 @@ void blend_backward(const Launch& L, const CamDev& cam, const uint2* ranges, con
     const int ntiles = cam.tiles_x * cam.tiles_y;
     if (L.prof) L.prof->begin("blend_bwd", L.st);
     const bool records = ga.grec_cap > 0;
-    constexpr int R = kBlendRows;
+    constexpr int R = kBlendRowsBwd;
     auto kern = records ? (want_opacity ? k_blend_bwd<R, true, true> : k_blend_bwd<R, true, false>)
                         : (want_opacity ? k_blend_bwd<R, false, true> : k_blend_bwd<R, false, false>);
     hipLaunchKernelGGL(kern, dim3(order ? (unsigned)ntiles : blend_grid(ntiles)), dim3(kTile * kTile / R), 0, L.st,
