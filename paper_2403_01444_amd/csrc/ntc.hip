@@ -577,9 +577,27 @@ __global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ ro
     uint2 r = make_uint2(0u, 0u);
     if (e < entries) r = rows[e];
     float a0 = 0.f, a1 = 0.f;
-    for (uint32_t k = r.x + sub; k < r.y; k += 8) {
-        const uint32_t c = pid[k];
-        const float2 d = *reinterpret_cast<const float2*>(denc + 2 * ((int64_t)((c >> 3) & 15) * n + (c >> 7)));
+    auto enc = [&](uint32_t c) {
+        return *reinterpret_cast<const float2*>(denc + 2 * ((int64_t)((c >> 3) & 15) * n + (c >> 7)));
+    };
+    uint32_t k = r.x + sub;
+    // four independent contribution loads in flight per lane; the sum keeps
+    // the order k, k + 8, k + 16, ...
+    for (; k + 24 < r.y; k += 32) {
+        const uint32_t c0 = pid[k], c1 = pid[k + 8], c2 = pid[k + 16], c3 = pid[k + 24];
+        const float w0 = w[k], w1 = w[k + 8], w2 = w[k + 16], w3 = w[k + 24];
+        const float2 d0 = enc(c0), d1 = enc(c1), d2 = enc(c2), d3 = enc(c3);
+        a0 += w0 * d0.x;
+        a1 += w0 * d0.y;
+        a0 += w1 * d1.x;
+        a1 += w1 * d1.y;
+        a0 += w2 * d2.x;
+        a1 += w2 * d2.y;
+        a0 += w3 * d3.x;
+        a1 += w3 * d3.y;
+    }
+    for (; k < r.y; k += 8) {
+        const float2 d = enc(pid[k]);
         const float wk = w[k];
         a0 += wk * d.x;
         a1 += wk * d.y;
