@@ -280,6 +280,50 @@ __device__ __forceinline__ void quat_to_rot(const float q[4], float R[9]) {
 // Colour of a Gaussian: direction from the camera centre to the translated
 // mean, rotated back into the frame of the untransformed Gaussian
 // (d_loc = R(qh) R(q')^T d), then max(0, SH(d_loc) + 0.5).
+// 0.5 + sum_k Y_k c_k for one Gaussian's K x 3 SH row; rows of 12 or 48
+// floats are 16-byte aligned and read as float4 (12 loads instead of 48).
+template <int K>
+__device__ __forceinline__ void sh_colour(const float* __restrict__ sh, const float Y[16], float raw[3]) {
+    float v[3 * K];
+    if constexpr ((3 * K) % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < 3 * K / 4; q++) {
+            const float4 t = reinterpret_cast<const float4*>(sh)[q];
+            v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3 * K; q++) v[q] = sh[q];
+    }
+    float c0 = 0.5f, c1 = 0.5f, c2 = 0.5f;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        c0 += Y[k] * v[3 * k + 0];
+        c1 += Y[k] * v[3 * k + 1];
+        c2 += Y[k] * v[3 * k + 2];
+    }
+    raw[0] = c0; raw[1] = c1; raw[2] = c2;
+}
+
+// wk_k = sum_c gch_c SH_{k,c} (the colour gradient pulled back onto the
+// basis values), with the same row loads as sh_colour.
+template <int K>
+__device__ __forceinline__ void sh_weights(const float* __restrict__ sh, const float gch[3], float wk[16]) {
+    float v[3 * K];
+    if constexpr ((3 * K) % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < 3 * K / 4; q++) {
+            const float4 t = reinterpret_cast<const float4*>(sh)[q];
+            v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3 * K; q++) v[q] = sh[q];
+    }
+#pragma unroll
+    for (int k = 0; k < K; k++) wk[k] = gch[0] * v[3 * k] + gch[1] * v[3 * k + 1] + gch[2] * v[3 * k + 2];
+}
+
 struct ColourCtx {
     float dir[3], wn;     // unit direction and |mu' - c|
     float Rh[9];          // R(qh) (only with a rotation delta)
@@ -309,15 +353,12 @@ __device__ __forceinline__ void colour_forward(const GaussDev& g, const CamDev& 
     }
     float Y[16];
     sh_basis(g.sh_degree, cc.dl[0], cc.dl[1], cc.dl[2], Y);
-    int K = (g.sh_degree + 1) * (g.sh_degree + 1);
-    const float* sh = g.sh + i * (int64_t)K * 3;
-    float c0 = 0.5f, c1 = 0.5f, c2 = 0.5f;
-    for (int k = 0; k < K; k++) {
-        c0 += Y[k] * sh[3 * k + 0];
-        c1 += Y[k] * sh[3 * k + 1];
-        c2 += Y[k] * sh[3 * k + 2];
+    switch (g.sh_degree) {
+        case 3: sh_colour<16>(g.sh + i * 48, Y, cc.raw); break;
+        case 1: sh_colour<4>(g.sh + i * 12, Y, cc.raw); break;
+        case 2: sh_colour<9>(g.sh + i * 27, Y, cc.raw); break;
+        default: sh_colour<1>(g.sh + i * 3, Y, cc.raw); break;
     }
-    cc.raw[0] = c0; cc.raw[1] = c1; cc.raw[2] = c2;
 }
 
 // alpha of a Gaussian record at pixel (px, py); false when the candidate is

@@ -173,11 +173,22 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, c
 __global__ __launch_bounds__(256) void k_loss_finalize(const double* __restrict__ bsum, int64_t nblk, int64_t N,
                                                        float lam, float* __restrict__ loss, int* __restrict__ nonfinite) {
     __shared__ double s[2][4];
-    double a = 0.0, b = 0.0;
-    for (int64_t k = threadIdx.x; k < nblk; k += 256) {
-        a += bsum[2 * k];
-        b += bsum[2 * k + 1];
+    // four independent partial sums per thread (fixed order), then combined
+    double a4[4] = {0.0, 0.0, 0.0, 0.0}, b4[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t k = threadIdx.x;
+    for (; k + 768 < nblk; k += 1024) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const double2 v = reinterpret_cast<const double2*>(bsum)[k + 256 * u];
+            a4[u] += v.x;
+            b4[u] += v.y;
+        }
     }
+    for (; k < nblk; k += 256) {
+        a4[0] += bsum[2 * k];
+        b4[0] += bsum[2 * k + 1];
+    }
+    double a = (a4[0] + a4[1]) + (a4[2] + a4[3]), b = (b4[0] + b4[1]) + (b4[2] + b4[3]);
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_xor(a, off, 64);
         b += __shfl_xor(b, off, 64);

@@ -642,19 +642,21 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussDev g, CamDev cam, 
     float gch[3];
     for (int k = 0; k < 3; k++) gch[k] = cc.raw[k] > 0.f ? drgb[k] : 0.f;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
-    const float* sh = g.sh + i * (int64_t)K * 3;
     float wk[16];
-    {
+    switch (g.sh_degree) {
+        case 3: sh_weights<16>(g.sh + i * 48, gch, wk); break;
+        case 1: sh_weights<4>(g.sh + i * 12, gch, wk); break;
+        case 2: sh_weights<9>(g.sh + i * 27, gch, wk); break;
+        default: sh_weights<1>(g.sh + i * 3, gch, wk); break;
+    }
+    if (out.d_sh) {
         float Y[16];
         sh_basis(g.sh_degree, cc.dl[0], cc.dl[1], cc.dl[2], Y);
         for (int k = 0; k < K; k++) {
-            wk[k] = gch[0] * sh[3 * k] + gch[1] * sh[3 * k + 1] + gch[2] * sh[3 * k + 2];
-            if (out.d_sh) {
-                float* ds = out.d_sh + i * (int64_t)K * 3 + 3 * k;
-                ds[0] += gch[0] * Y[k];
-                ds[1] += gch[1] * Y[k];
-                ds[2] += gch[2] * Y[k];
-            }
+            float* ds = out.d_sh + i * (int64_t)K * 3 + 3 * k;
+            ds[0] += gch[0] * Y[k];
+            ds[1] += gch[1] * Y[k];
+            ds[2] += gch[2] * Y[k];
         }
     }
     float gdl[3];
