@@ -340,7 +340,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
         if (!all) {
             // branch-free per-pixel body: every lane evaluates, selects keep
             // the state of pixels that do not take the contribution
-            for (int j = 0; j < cnt; j++) {
+            auto eval = [&](int j) {
                 const float4 w0 = s_w0[j], w1 = s_w1[j], w2 = s_w2[j];
                 const bool full = s_full[j];
                 const uint32_t bx0 = __float_as_uint(w2.y), bx1 = __float_as_uint(w2.z);
@@ -366,24 +366,32 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                     for (int k = 0; k < R; k++)
                         if (band[k]) ok[k] = blend_exact_test(power[k], w1.y);
                 }
-                bool active = false;
 #pragma unroll
                 for (int k = 0; k < R; k++) {
                     const float alpha = fminf(0.99f, w1.y * __expf(power[k]));
                     const float Tn = T[k] * (1.0f - alpha);
-                    const bool stop = ok[k] && Tn < 1e-4f;
-                    const bool take = ok[k] && !stop;
+                    const bool stop = ok[k] & (Tn < 1e-4f);
+                    const bool take = ok[k] & !stop;
                     const float wgt = alpha * T[k];
                     c0[k] = take ? c0[k] + wgt * w1.z : c0[k];
                     c1[k] = take ? c1[k] + wgt * w1.w : c1[k];
                     c2[k] = take ? c2[k] + wgt * w2.x : c2[k];
                     T[k] = take ? Tn : T[k];
                     last[k] = take ? b - start + (uint32_t)j + 1u : last[k];
-                    done[k] = done[k] || stop;
-                    active = active || !done[k];
+                    done[k] = done[k] | stop;
                 }
+            };
+            // two entries per trip; the wave leaves once all its pixels have stopped
+            int j = 0;
+            for (; j + 1 < cnt; j += 2) {
+                eval(j);
+                eval(j + 1);
+                bool active = false;
+#pragma unroll
+                for (int k = 0; k < R; k++) active = active | !done[k];
                 if (!__any(active)) break;
             }
+            if (j + 1 == cnt) eval(j);
         }
         __syncthreads();
     }
