@@ -437,27 +437,38 @@ __device__ __forceinline__ float dpp_add(float x) {
     return x + __builtin_bit_cast(float, moved);
 }
 
+// Lane exchanges of gfx950: v_permlane32_swap exchanges the upper 32 lanes
+// of its first operand with the lower 32 lanes of its second, so afterwards
+// x + y holds, in lanes 0-31, x[l] + x[l + 32] and, in lanes 32-63,
+// y[l - 32] + y[l]; v_permlane16_swap does the same between the odd 16-lane
+// rows of x and the even rows of y.  Written as inline assembly with both
+// operands read and written (the compiler's two-result builtin for these
+// instructions dropped the second result); the s_nop keeps the VALU write
+// of the operands apart from the exchange.
+__device__ __forceinline__ float swap_add32(float x, float y) {
+    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(x), "+v"(y));
+    return x + y;
+}
+
+__device__ __forceinline__ float swap_add16(float x, float y) {
+    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(x), "+v"(y));
+    return x + y;
+}
+
 // Eight per-lane values -> their eight wave sums, spread over lane groups:
 // after the call, every lane of the 8-lane group g (lanes 8g..8g+7) holds
-// the total of term g.  Two exchanges halve the set (lanes ^32 swap four
-// terms, lanes ^16 swap two), a third (^8, DPP row_ror:8) leaves one term per
-// lane, then DPP sums the 8-lane group: 10 moves instead of 8 x 6.
+// the total of term g.  Two exchanges halve the set (permlane32: terms 0-3
+// stay in the lower half, 4-7 in the upper; permlane16: two terms per 16-lane
+// row), a third (^8, DPP row_ror:8) leaves one term per lane, then DPP sums
+// the 8-lane group.
 __device__ __forceinline__ float wave_reduce_scatter8(const float v[8], int lane) {
     float a[4], b[2], c;
-    const bool hi32 = lane & 32, hi16 = lane & 16, hi8 = lane & 8;
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-        const float send = hi32 ? v[k] : v[4 + k];
-        const float keep = hi32 ? v[4 + k] : v[k];
-        a[k] = keep + __shfl_xor(send, 32, 64);
-    }
+    for (int k = 0; k < 4; k++) a[k] = swap_add32(v[k], v[4 + k]);
 #pragma unroll
-    for (int k = 0; k < 2; k++) {
-        const float send = hi16 ? a[k] : a[2 + k];
-        const float keep = hi16 ? a[2 + k] : a[k];
-        b[k] = keep + __shfl_xor(send, 16, 64);
-    }
+    for (int k = 0; k < 2; k++) b[k] = swap_add16(a[k], a[2 + k]);
     {
+        const bool hi8 = lane & 8;
         const float send = hi8 ? b[0] : b[1];
         const float keep = hi8 ? b[1] : b[0];
         const int moved = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, send), 0x128, 0xF, 0xF, false);
@@ -466,7 +477,7 @@ __device__ __forceinline__ float wave_reduce_scatter8(const float v[8], int lane
     c = dpp_add<0xB1, 0xF>(c);    // quad_perm [1,0,3,2]
     c = dpp_add<0x4E, 0xF>(c);    // quad_perm [2,3,0,1]
     c = dpp_add<0x141, 0xF>(c);   // row_half_mirror: the 8-lane group total in every lane
-    return c;                     // term index: (lane >> 5) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1)
+    return c;                     // term index: lane >> 3
 }
 
 // Sum over the 64 lanes with DPP moves (no LDS traffic); the result is
