@@ -119,7 +119,11 @@ __global__ __launch_bounds__(256) void k_ranges_from_keys(const uint64_t* __rest
 // (chunk, position in chunk), i.e. by (depth bits, index): the order a stable
 // (tile, depth) sort gives.
 // ---------------------------------------------------------------------------
-constexpr int kBinRowsPerBlock = 4;
+#ifndef GS3_BIN_ROWS
+#define GS3_BIN_ROWS 8
+#endif
+constexpr int kBinRowsPerBlock = GS3_BIN_ROWS;   // one wave per tile row
+constexpr int kBinThreads = 64 * kBinRowsPerBlock;
 constexpr int kBinColSlots = kMaxTilesX / 64;   // register cursors per lane
 
 __global__ __launch_bounds__(256) void k_bin_gather(const uint32_t* __restrict__ order, int64_t n,
@@ -137,7 +141,7 @@ __global__ __launch_bounds__(256) void k_bin_gather(const uint32_t* __restrict__
 }
 
 template <bool kScatter>
-__global__ __launch_bounds__(256) void k_bin_rows(const uint32_t* __restrict__ order, int64_t n,
+__global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __restrict__ order, int64_t n,
                                                   const uint2* __restrict__ srect, const uint32_t* __restrict__ sgoff,
                                                   int tiles_x, int tiles_y, int64_t nchunks,
                                                   uint32_t* __restrict__ hist, const uint64_t* __restrict__ base,
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(256) void k_bin_rows(const uint32_t* __restrict__ o
     const int row = rg * kBinRowsPerBlock + w;
     const int64_t e0 = chunk * kBinChunk;
     const int m = (int)min((int64_t)kBinChunk, n - e0);
-    for (int e = threadIdx.x; e < m; e += 256) {
+    for (int e = threadIdx.x; e < m; e += kBinThreads) {
         s_id[e] = order[e0 + e];
         s_rect[e] = srect[e0 + e];
         if (kScatter) s_goff[e] = gpos ? sgoff[e0 + e] : 0u;
@@ -849,7 +853,7 @@ void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* s
     const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_count", L.st);
-    hipLaunchKernelGGL((k_bin_rows<false>), bin_grid(nchunks, tiles_y), dim3(256), 0, L.st, order, n, srect, (const uint32_t*)nullptr,
+    hipLaunchKernelGGL((k_bin_rows<false>), bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, order, n, srect, (const uint32_t*)nullptr,
                        tiles_x, tiles_y, nchunks, hist, (const uint64_t*)nullptr, 0u, (uint32_t*)nullptr,
                        (uint32_t*)nullptr);
     if (L.prof) L.prof->end(L.st);
@@ -860,7 +864,7 @@ void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2*
     const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_scatter", L.st);
-    hipLaunchKernelGGL((k_bin_rows<true>), bin_grid(nchunks, tiles_y), dim3(256), 0, L.st, order, n, srect, sgoff, tiles_x, tiles_y,
+    hipLaunchKernelGGL((k_bin_rows<true>), bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, order, n, srect, sgoff, tiles_x, tiles_y,
                        nchunks, (uint32_t*)nullptr, base, (uint32_t)cap, vals, gpos);
     if (L.prof) L.prof->end(L.st);
 }
