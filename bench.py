@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--stream-gaussians", type=int, default=500_000)
     ap.add_argument("--stream-size", default="1920x1080")
     ap.add_argument("--stream-views", type=int, default=15)
+    ap.add_argument("--scale", action="store_true",
+                    help="instead of the timing run: forward + backward of 1M Gaussians at 1920x1080, "
+                         "with the memory the context holds")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB, a kernel of known traffic "
                          "for calibrating the HBM byte counters")
@@ -122,6 +125,54 @@ def quality(args, workload, iters=150, direct_iters=300):
         res["direct_log"] = [(i, round(t, 5), round(p, 4)) for i, t, p in direct_log]
         res["ntc_without_warmup_log"] = [(i, round(t, 5), round(p, 4)) for i, t, p in cold_log]
     return res
+
+
+def scale(args):
+    """1M Gaussians (SH3) at 1920x1080 with a small transform: render and
+    renderer backward timed; device memory of the context; the per-pixel
+    state kept between them (8 B: final transmittance and last walked entry)
+    against storing a transmittance per walked (pixel, entry) (4 B each; an
+    upper bound of the per-contributor count)."""
+    import torch
+    from paper_2403_01444_amd import gs3, synth
+    g = synth.make_gaussians(1_000_000, 3, 21)
+    cam = synth.look_at_camera(1920, 1080)
+    rng = np.random.default_rng(22)
+    dmu = torch.from_numpy((rng.normal(size=(g.n, 3)) * 0.005).astype(np.float32)).cuda()
+    dq = torch.from_numpy((np.array([1, 0, 0, 0]) + rng.normal(size=(g.n, 4)) * 0.02).astype(np.float32)).cuda()
+    ctx = gs3.Context(g.n, 400_000_000, 1920, 1080, num_slots=1)
+    gg = gs3.GaussiansGPU.from_host(g)
+    img = ctx.render(gg, cam, dmu, dq)
+    dimg = torch.full_like(img, 1e-7)
+    grads = {"d_dmu": ctx.zeros(g.n, 3), "d_dq": ctx.zeros(g.n, 4)}
+    for _ in range(2):
+        ctx.render(gg, cam, dmu, dq, image=img)
+        ctx.render_backward(dimg, grads)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_reset()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.render(gg, cam, dmu, dq, image=img)
+        ctx.render_backward(dimg, grads)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ctx.profile(False)
+    kernels = {}
+    for name in ("preprocess_fwd", "radix_pass", "bin_count", "bin_scatter", "blend_fwd", "blend_bwd",
+                 "preprocess_bwd"):
+        ms, cnt = ctx.profile_query(name)
+        if cnt:
+            kernels[name] = round(ms / cnt, 4)
+    K, _ = ctx.debug_counts()
+    T, last = ctx.debug_pixels(cam)
+    walked = int(last.to(torch.int64).sum())
+    print(json.dumps({"mode": "scale", "gaussians": g.n, "width": 1920, "height": 1080, "pairs": int(K),
+                      "ms_forward_backward": round(1000 * dt, 3), "kernels_ms": kernels,
+                      "context_bytes": ctx.workspace_bytes(),
+                      "per_pixel_state_bytes": 8 * 1920 * 1080,
+                      "stored_T_counterfactual_bytes": 4 * walked, "data": "synthetic"}))
 
 
 def stream(args):
@@ -273,6 +324,9 @@ def main():
         return
     if args.stream:
         stream(args)
+        return
+    if args.scale:
+        scale(args)
         return
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib << 18, device="cuda")

@@ -312,6 +312,12 @@ gs3_status gs3_debug_gaussians(gs3_ctx* ctx, int32_t slot, uint32_t* key, int32_
  * entries walked up to the last contributor (H x W int32), DEVICE. */
 gs3_status gs3_debug_pixels(gs3_ctx* ctx, int32_t slot, float* T_final, int32_t* last);
 
+/* Device memory the context holds (workspaces sized at gs3_create plus the
+ * per-frame NTC contribution lists), in bytes.  Per-pixel render state is
+ * 8 bytes (final transmittance and last walked entry): transmittance is
+ * recomputed in the backward, never stored per contributor (Eq. 4). */
+gs3_status gs3_workspace_bytes(const gs3_ctx* ctx, int64_t* bytes);
+
 /* Check the device flags raised since the last check (overflow of any slot,
  * non-finite loss) and clear them.  Synchronises. */
 gs3_status gs3_check_flags(gs3_ctx* ctx);

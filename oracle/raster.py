@@ -83,6 +83,15 @@ def preprocess(g, cam, dmu=None, dq=None, tile: int = 16) -> dict:
     return out
 
 
+def pair_count(g, cam, dmu=None, dq=None, tile: int = 16) -> int:
+    """Number of (tile, Gaussian) pairs, without building the list."""
+    p = _Pinned(g, dmu, dq)
+    c = _cam(cam)
+    K = lib().orc_sorted_pairs(C.byref(p.s), C.byref(c), C.c_int(tile), None, None, C.c_int64(0), None)
+    assert K >= 0, K
+    return int(K)
+
+
 def sorted_pairs(g, cam, dmu=None, dq=None, tile: int = 16):
     """(keys u64, vals u32, ranges (tiles, 2) u32) in (tile, depth bits, id) order."""
     p = _Pinned(g, dmu, dq)

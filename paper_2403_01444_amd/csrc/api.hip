@@ -133,6 +133,8 @@ struct gs3_ctx {
 
     Launch L() { return Launch{st, prof_on ? &prof : nullptr}; }
 
+    int64_t bytes = 0;       // device memory held by the context (fixed workspaces)
+    int64_t csr_bytes = 0;   // and by the per-frame contribution lists
     template <typename T>
     bool alloc(T** out, int64_t count) {
         *out = nullptr;
@@ -143,6 +145,7 @@ struct gs3_ctx {
             return false;
         }
         allocs.push_back(ptr);
+        bytes += (int64_t)count * (int64_t)sizeof(T);
         *out = (T*)ptr;
         return true;
     }
@@ -380,11 +383,13 @@ gs3_status gs3_ntc_prepare(gs3_ctx* c, const float* means, int64_t n) {
     if (n > c->csr_cap) {
         hipDeviceSynchronize();
         for (void* p : c->csr_allocs) hipFree(p);
+        c->csr_bytes = 0;
         c->csr_allocs.clear();
         auto get = [&](void** out, size_t bytes) {
             *out = nullptr;
             if (hipMalloc(out, bytes) != hipSuccess) return false;
             c->csr_allocs.push_back(*out);
+            c->csr_bytes += (int64_t)bytes;
             return true;
         };
         const int64_t entries = c->n_table_floats / 2;
@@ -735,6 +740,12 @@ gs3_status gs3_debug_pixels(gs3_ctx* c, int32_t slot, float* T_final, int32_t* l
         return c->fail(GS3_EHIP, "debug_pixels: copy failed");
     if (last && hipMemcpyAsync(last, sl.last, P * 4, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
         return c->fail(GS3_EHIP, "debug_pixels: copy failed");
+    return GS3_OK;
+}
+
+gs3_status gs3_workspace_bytes(const gs3_ctx* c, int64_t* bytes) {
+    if (!c || !bytes) return GS3_EINVAL;
+    *bytes = c->bytes + c->csr_bytes;
     return GS3_OK;
 }
 

@@ -70,7 +70,7 @@ EXPORTED = ("gs3_create", "gs3_destroy", "gs3_last_error", "gs3_set_stream", "gs
             "gs3_ntc_load", "gs3_ntc_save", "gs3_ntc_forward", "gs3_ntc_backward", "gs3_ntc_prepare", "gs3_ntc_step",
             "gs3_ntc_grads", "gs3_ntc_zero_grads", "gs3_warmup_loss", "gs3_render", "gs3_render_backward", "gs3_transform_bake", "gs3_select", "gs3_spawn",
             "gs3_loss", "gs3_adam", "gs3_zero", "gs3_debug_counts", "gs3_debug_pairs", "gs3_debug_ranges",
-            "gs3_debug_gaussians", "gs3_debug_pixels", "gs3_check_flags", "gs3_profile_enable",
+            "gs3_debug_gaussians", "gs3_debug_pixels", "gs3_check_flags", "gs3_workspace_bytes", "gs3_profile_enable",
             "gs3_profile_reset", "gs3_profile_query")
 
 _lib = None
@@ -116,6 +116,7 @@ def lib():
         "gs3_debug_gaussians": [vp, i32, vp, vp, vp],
         "gs3_debug_pixels": [vp, i32, vp, vp],
         "gs3_check_flags": [vp],
+        "gs3_workspace_bytes": [vp, C.POINTER(i64)],
         "gs3_profile_enable": [vp, i32],
         "gs3_profile_reset": [vp],
         "gs3_profile_query": [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)],
@@ -311,6 +312,12 @@ def gs3_transform_bake(h, gs: GaussiansGPU, dmu, dq, means_out, quats_out, sh_ou
                                        _ptr(quats_out, numel=4 * n), _ptr(sh_out, numel=gs.sh.numel())))
 
 
+def gs3_workspace_bytes(h) -> int:
+    b = C.c_int64(0)
+    _check(h, lib().gs3_workspace_bytes(h, C.byref(b)))
+    return int(b.value)
+
+
 def gs3_select(h, num, den, n, threshold, idx) -> int:
     count = C.c_int64(0)
     _check(h, lib().gs3_select(h, _ptr(num, numel=n, name="num"), _ptr(den, numel=n, name="den"), n,
@@ -425,6 +432,7 @@ class Context:
         self.device = torch.device(device or "cuda")
         self.ntc_cfg = ntc
         self.precision = precision
+        self._held = {}   # per slot: the buffers the last render read
         with torch.cuda.device(self.device):
             self.h = gs3_create(make_config(max_gaussians, max_pairs, max_width, max_height, num_slots, sort_mode,
                                             ntc, precision, grad_record_log2))
@@ -439,6 +447,7 @@ class Context:
         if getattr(self, "h", None) is not None:
             gs3_destroy(self.h)
             self.h = None
+        self._held = {}
 
     def __del__(self):
         try:
@@ -527,11 +536,16 @@ class Context:
     def render(self, gs: GaussiansGPU, cam, dmu=None, dq=None, slot=0, image=None):
         image = self.empty(3, cam.height, cam.width) if image is None else image
         gs3_render(self.h, slot, gs, dmu, dq, cam, image)
+        # the slot's backward reads these buffers again: keep them alive
+        self._held[slot] = (gs, dmu, dq)
         return image
 
     def render_backward(self, d_image, grads: dict, slot=0):
         gs3_render_backward(self.h, slot, d_image, grads)
         return grads
+
+    def workspace_bytes(self) -> int:
+        return gs3_workspace_bytes(self.h)
 
     def select(self, num, den=None, threshold=0.0):
         """Ascending indices passing the threshold (int64 tensor on the device)."""
