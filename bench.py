@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--render-reps", type=int, default=50)
+    ap.add_argument("--batch-views", type=int, default=4,
+                    help="views per step of the multi-view batch variant (1 = skip it)")
+    ap.add_argument("--other-precisions", default="f32,bf16",
+                    help="NTC precisions also timed (comma-separated; empty = none)")
     ap.add_argument("--protocol", action="store_true",
                     help="only the equal-PSNR comparison, with full logs")
     ap.add_argument("--protocol-iters", type=int, default=300, help="direct-optimisation iterations in the protocol")
@@ -308,6 +312,19 @@ def cpu_baseline(g, cam, target_np, params, cfg):
                       f"total {total:.1f}s"}
 
 
+def time_stage1(st, steps, warmup):
+    """Stage-1 iterations per second of a Stage1NTC loop."""
+    import torch
+    for _ in range(warmup):
+        st.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.step()
+    torch.cuda.synchronize()
+    return steps / (time.perf_counter() - t0)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -374,6 +391,24 @@ def main():
         st1.step()
     torch.cuda.synchronize()
     ctx.check_flags()
+    # per-kernel device times: every launch bracketed by HIP events, in a pass
+    # of its own before the timed region
+    ctx.profile(True)
+    ctx.profile_reset()
+    for _ in range(args.steps):
+        st1.step()
+    torch.cuda.synchronize()
+    ctx.profile(False)
+    kernels = {}
+    for name in ("ntc_fwd", "preprocess_fwd", "radix_pass", "bin_count", "scan", "bin_gather", "bin_scatter", "tile_ranges", "tile_order",
+                 "blend_fwd", "loss", "blend_bwd", "preprocess_bwd", "ntc_bwd", "ntc_scatter", "ntc_adam"):
+        ms, cnt = ctx.profile_query(name)
+        if cnt:
+            kernels[name] = {"ms_per_launch": ms / cnt, "launches_per_step": cnt / args.steps}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"] * kernels[k]["launches_per_step"]) if kernels else None
+    # the timed region: only the dominant kernel's launches carry events, and
+    # its roofline uses their average duration
+    ctx.profile_only(dom)
     ctx.profile(True)
     ctx.profile_reset()
     torch.cuda.synchronize()
@@ -383,13 +418,12 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ctx.profile(False)
+    ctx.profile_only(None)
     ctx.check_flags()
-    kernels = {}
-    for name in ("ntc_fwd", "preprocess_fwd", "radix_pass", "bin_count", "scan", "bin_gather", "bin_scatter", "tile_ranges", "tile_order",
-                 "blend_fwd", "loss", "blend_bwd", "preprocess_bwd", "ntc_bwd", "ntc_scatter", "ntc_adam"):
-        ms, cnt = ctx.profile_query(name)
-        if cnt:
-            kernels[name] = {"ms_per_launch": ms / cnt, "launches_per_step": cnt / args.steps}
+    dom_ms = None
+    if dom is not None:
+        ms, cnt = ctx.profile_query(dom)
+        dom_ms = ms / cnt
     iters_per_s = args.steps / elapsed
 
     # pairs, walked list entries and per-pixel evaluations, averaged over the
@@ -429,6 +463,27 @@ def main():
     torch.cuda.synchronize()
     fps_plain = args.render_reps / (time.perf_counter() - t0)
 
+    # multi-view batch: several views per NTC query, NTC backward and Adam step
+    multi_view = None
+    if args.batch_views > 1:
+        stb = train.Stage1NTC(ctx, gg, cams, targets, lam=0.2, views_per_step=args.batch_views)
+        ips = time_stage1(stb, args.steps, args.warmup)
+        multi_view = {"views_per_step": args.batch_views, "iters_per_s": round(ips, 3),
+                      "views_per_s": round(ips * args.batch_views, 3)}
+        del stb
+        ctx.ntc_load(params_warm)
+
+    # the same iteration with the NTC in the other precisions
+    by_precision = {args.precision: round(iters_per_s, 3)}
+    for prec in args.other_precisions.split(","):
+        if not prec or prec == args.precision:
+            continue
+        c2 = gs3.Context(g.n, max_pairs, W, H, num_slots=1, sort_mode=args.sort_mode, ntc=cfg, precision=prec)
+        c2.ntc_load(params_warm)
+        by_precision[prec] = round(time_stage1(train.Stage1NTC(c2, gg, cams, targets, lam=0.2),
+                                               args.steps, args.warmup), 3)
+        c2.close()
+
     # FP32 direct optimisation comparator (same renderer and loss)
     direct = None
     if not args.no_direct:
@@ -448,13 +503,12 @@ def main():
               sh_floats=3 * (g.sh_degree + 1) ** 2, K=K0, contribs=8 * cfg.levels * g.n,
               table_bytes=n_table_entries * 2 * (4 if args.precision == "f32" else 2),
               table_entries=n_table_entries)
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"] * kernels[k]["launches_per_step"]) if kernels else None
     roof = None
     if dom is not None:
         w = algorithmic_work(dom, st)
         if w is not None:
             bound, amount, unit = w
-            sec = kernels[dom]["ms_per_launch"] * 1e-3
+            sec = dom_ms * 1e-3
             if bound == "alu":
                 ach, peak, u = amount / sec / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
             else:
@@ -463,7 +517,7 @@ def main():
                     "frac": round(ach / peak, 4), "traffic": measured_traffic(dom, args.workload),
                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     "algorithmic_per_launch": int(amount),
-                    "algorithmic_unit": unit, "ms_per_launch": round(kernels[dom]["ms_per_launch"], 5)}
+                    "algorithmic_unit": unit, "ms_per_launch": round(dom_ms, 5)}
     all_roof = {}
     for k, v in kernels.items():
         w = algorithmic_work(k, st)
@@ -496,6 +550,7 @@ def main():
         "s_per_frame_150_iters": round(150.0 / iters_per_s, 4),
         "render_fps_with_ntc": round(fps, 2), "render_fps_without_ntc": round(fps_plain, 2),
         "direct_f32_iters_per_s": None if direct is None else round(direct, 3),
+        "iters_per_s_by_ntc_precision": by_precision, "multi_view_batch": multi_view,
         "pairs_per_view": int(K0), "walked_entries": walked, "pixel_evals": n_evals,
         "heldout_psnr_after_steps": round(psnr_ntc, 3),
         "warmup_s": round(t_warm, 3), "warmup_iters": args.warmup_iters, "frame_setup_s": round(t_prepare + t_reorder, 4),

@@ -326,8 +326,11 @@ gs3_status gs3_check_flags(gs3_ctx* ctx);
 
 /* When on, every kernel launch is bracketed by HIP events on the context
  * stream; gs3_profile_query returns the summed device time (ms) and launch
- * count of one kernel by name, synchronising first. */
+ * count of one kernel by name, synchronising first.  gs3_profile_only
+ * restricts the timing to the launches of one kernel (NULL or "": all), so
+ * that a timed loop carries two events per launch of that kernel only. */
 gs3_status gs3_profile_enable(gs3_ctx* ctx, int32_t on);
+gs3_status gs3_profile_only(gs3_ctx* ctx, const char* kernel);
 gs3_status gs3_profile_reset(gs3_ctx* ctx);
 gs3_status gs3_profile_query(gs3_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
 

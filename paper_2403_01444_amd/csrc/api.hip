@@ -17,22 +17,37 @@ namespace {
 struct EventProfiler : Profiler {
     struct Rec {
         std::string name;
-        hipEvent_t a, b;
+        hipEvent_t a, b;   // null when the launch is not timed
     };
+    std::string only;                 // time only this kernel (empty: every kernel)
+    std::vector<hipEvent_t> pool;     // created events, reused across launches
     std::vector<Rec> pending;
     std::vector<Rec> open;
     std::map<std::string, std::pair<double, int64_t>> totals;
+    hipEvent_t take() {
+        hipEvent_t e = nullptr;
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
+        } else {
+            hipEventCreate(&e);
+        }
+        return e;
+    }
     void begin(const char* name, hipStream_t st) override {
         Rec r{name, nullptr, nullptr};
-        hipEventCreate(&r.a);
-        hipEventCreate(&r.b);
-        hipEventRecord(r.a, st);
+        if (only.empty() || only == name) {
+            r.a = take();
+            r.b = take();
+            hipEventRecord(r.a, st);
+        }
         open.push_back(r);
     }
     void end(hipStream_t st) override {
         if (open.empty()) return;
         Rec r = open.back();
         open.pop_back();
+        if (!r.a) return;
         hipEventRecord(r.b, st);
         pending.push_back(r);
     }
@@ -44,16 +59,14 @@ struct EventProfiler : Profiler {
             auto& t = totals[r.name];
             t.first += ms;
             t.second += 1;
-            hipEventDestroy(r.a);
-            hipEventDestroy(r.b);
+            pool.push_back(r.a);
+            pool.push_back(r.b);
         }
         pending.clear();
     }
     ~EventProfiler() override {
-        for (auto& r : pending) {
-            hipEventDestroy(r.a);
-            hipEventDestroy(r.b);
-        }
+        collect();
+        for (auto e : pool) hipEventDestroy(e);
     }
 };
 
@@ -766,6 +779,12 @@ gs3_status gs3_check_flags(gs3_ctx* c) {
 gs3_status gs3_profile_enable(gs3_ctx* c, int32_t on) {
     if (!c) return GS3_EINVAL;
     c->prof_on = on != 0;
+    return GS3_OK;
+}
+
+gs3_status gs3_profile_only(gs3_ctx* c, const char* kernel) {
+    if (!c) return GS3_EINVAL;
+    c->prof.only = kernel ? kernel : "";
     return GS3_OK;
 }
 

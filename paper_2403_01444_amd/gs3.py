@@ -71,7 +71,7 @@ EXPORTED = ("gs3_create", "gs3_destroy", "gs3_last_error", "gs3_set_stream", "gs
             "gs3_ntc_grads", "gs3_ntc_zero_grads", "gs3_warmup_loss", "gs3_render", "gs3_render_backward", "gs3_transform_bake", "gs3_select", "gs3_spawn",
             "gs3_loss", "gs3_adam", "gs3_zero", "gs3_debug_counts", "gs3_debug_pairs", "gs3_debug_ranges",
             "gs3_debug_gaussians", "gs3_debug_pixels", "gs3_check_flags", "gs3_workspace_bytes", "gs3_profile_enable",
-            "gs3_profile_reset", "gs3_profile_query")
+            "gs3_profile_only", "gs3_profile_reset", "gs3_profile_query")
 
 _lib = None
 
@@ -118,6 +118,7 @@ def lib():
         "gs3_check_flags": [vp],
         "gs3_workspace_bytes": [vp, C.POINTER(i64)],
         "gs3_profile_enable": [vp, i32],
+        "gs3_profile_only": [vp, C.c_char_p],
         "gs3_profile_reset": [vp],
         "gs3_profile_query": [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)],
     }
@@ -380,6 +381,10 @@ def gs3_profile_enable(h, on: bool):
     _check(h, lib().gs3_profile_enable(h, 1 if on else 0))
 
 
+def gs3_profile_only(h, kernel):
+    _check(h, lib().gs3_profile_only(h, None if not kernel else kernel.encode()))
+
+
 def gs3_profile_reset(h):
     _check(h, lib().gs3_profile_reset(h))
 
@@ -627,6 +632,9 @@ class Context:
 
     def profile(self, on=True):
         gs3_profile_enable(self.h, on)
+
+    def profile_only(self, kernel=None):
+        gs3_profile_only(self.h, kernel)
 
     def profile_reset(self):
         gs3_profile_reset(self.h)

@@ -33,46 +33,64 @@ class _Views:
 
 class Stage1NTC:
     def __init__(self, ctx: gs3.Context, gauss: gs3.GaussiansGPU, cams, targets, lam: float = 0.2,
-                 lr: float = 0.002, betas=(0.9, 0.99), eps: float = 1e-15, seed: int = 0):
+                 lr: float = 0.002, betas=(0.9, 0.99), eps: float = 1e-15, seed: int = 0,
+                 views_per_step: int = 1):
+        if not 1 <= views_per_step <= len(cams):
+            raise ValueError(f"views_per_step must be in [1, {len(cams)}]")
         self.ctx, self.g, self.cams, self.targets = ctx, gauss, cams, targets
         self.lam, self.lr, self.betas, self.eps = lam, lr, betas, eps
+        self.views_per_step = views_per_step
         n = gauss.n
         self.dmu, self.dq = ctx.empty(n, 3), ctx.empty(n, 4)
         self.d_dmu, self.d_dq = ctx.zeros(n, 3), ctx.zeros(n, 4)
         H = max(c.height for c in cams)
         W = max(c.width for c in cams)
         self.img, self.dimg = ctx.empty(3 * H * W), ctx.empty(3 * H * W)
-        self.loss = ctx.empty(1)
+        self.loss = ctx.empty(views_per_step)   # per view of the last step
         self.views = _Views(len(cams), seed)
         # per-frame setup: the means stay frozen for the whole of Stage 1
         ctx.ntc_prepare(gauss.means)
 
-    def step(self, track=None) -> int:
-        """One iteration.  `track` = (vspace_grad, vspace_count) accumulates
-        the view-space gradient statistics Stage 2 selects from."""
-        ctx, cam = self.ctx, None
-        v = self.views.next()
-        cam = self.cams[v]
-        P = 3 * cam.height * cam.width
-        img, dimg = self.img[:P].view(3, cam.height, cam.width), self.dimg[:P].view(3, cam.height, cam.width)
+    def accumulate(self, views, track=None):
+        """NTC gradient of the summed loss over `views`: one NTC query, then
+        per view render, loss and renderer backward, the (dmu, dq) gradients
+        of all views summed, and one NTC backward.  With one view this is the
+        paper's iteration; with several it is the multi-view batch, which
+        queries and back-propagates the NTC once per batch.  (Adam's update is
+        unchanged by a constant gradient scale apart from eps, so the sum and
+        the mean over the views step alike.)"""
+        ctx = self.ctx
         ctx.ntc_forward(self.g.means, self.dmu, self.dq)
-        ctx.render(self.g, cam, self.dmu, self.dq, image=img)
-        ctx.loss(img, self.targets[v], self.lam, loss=self.loss, d_image=dimg)
         ctx.zero(self.d_dmu, self.d_dq)
         grads = {"d_dmu": self.d_dmu, "d_dq": self.d_dq}
         if track is not None:
             grads["vspace_grad"], grads["vspace_count"] = track
-        ctx.render_backward(dimg, grads)
+        for k, v in enumerate(views):
+            cam = self.cams[v]
+            P = 3 * cam.height * cam.width
+            img, dimg = self.img[:P].view(3, cam.height, cam.width), self.dimg[:P].view(3, cam.height, cam.width)
+            ctx.render(self.g, cam, self.dmu, self.dq, image=img)
+            ctx.loss(img, self.targets[v], self.lam, loss=self.loss[k:k + 1], d_image=dimg)
+            ctx.render_backward(dimg, grads)
         ctx.ntc_backward(self.g.means, self.d_dmu, self.d_dq)
-        ctx.ntc_step(self.lr, self.betas[0], self.betas[1], self.eps)
-        return v
+
+    def step(self, track=None):
+        """One iteration over `views_per_step` views of the epoch's
+        permutation (returns the view, or the list of views).  `track` =
+        (vspace_grad, vspace_count) accumulates the view-space gradient
+        statistics Stage 2 selects from."""
+        vs = [self.views.next() for _ in range(self.views_per_step)]
+        self.accumulate(vs, track)
+        self.ctx.ntc_step(self.lr, self.betas[0], self.betas[1], self.eps)
+        return vs[0] if self.views_per_step == 1 else vs
 
     def run(self, iters: int):
         """`iters` iterations; the view-space gradient statistics of the last
-        epoch (the last len(views) iterations) are returned for Stage 2."""
+        epoch (the iterations that cover the last len(views) views) are
+        returned for Stage 2."""
         n = self.g.n
         vg, vc = self.ctx.zeros(n), self.ctx.zeros(n)
-        last = min(iters, len(self.cams))
+        last = min(iters, -(-len(self.cams) // self.views_per_step))
         for it in range(iters):
             self.step((vg, vc) if it >= iters - last else None)
         return vg, vc
