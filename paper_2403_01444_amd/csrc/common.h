@@ -415,14 +415,25 @@ __device__ __forceinline__ bool blend_alpha_dy(float adx2, float bdx, float dy, 
     return true;
 }
 
-// does the pixel box cover the whole tile [x0, x1] x [y0, y1]?
-__device__ __forceinline__ bool box_covers(uint32_t b0, uint32_t b1, int x0, int y0, int x1, int y1) {
-    return (int)(b0 & 0xFFFFu) <= x0 && (int)(b0 >> 16) <= y0 && (int)(b1 & 0xFFFFu) >= x1 && (int)(b1 >> 16) >= y1;
+// bits lo..hi of a 16-bit span, clipped to 0..15 (0 when empty)
+__device__ __forceinline__ uint32_t span_mask16(int lo, int hi) {
+    lo = lo > 0 ? lo : 0;
+    hi = hi < 15 ? hi : 15;
+    return lo <= hi ? (0xFFFFu >> (15 - hi + lo)) << lo : 0u;
 }
 
-__device__ __forceinline__ bool box_contains(uint32_t b0, uint32_t b1, int px, int py) {
-    int x0 = (int)(b0 & 0xFFFFu), y0 = (int)(b0 >> 16), x1 = (int)(b1 & 0xFFFFu), y1 = (int)(b1 >> 16);
-    return px >= x0 && px <= x1 && py >= y0 && py <= y1;
+// The LDS form of a record's third quad in the blend loops of the tile whose
+// first pixel is (tx0p, ty0p): colour b, the lower and upper edge of the
+// exponent band around the opacity threshold (pthr -/+ 1e-4, the same
+// single-precision operations the per-pixel test used), and the pixel box as
+// a mask of the tile columns (bits 0-15) and rows (bits 16-31) it covers.  A
+// pixel at (lx, ly) of the tile is inside the box iff both of its bits
+// (1 << lx) | (1 << (16 + ly)) are set.
+__device__ __forceinline__ float4 blend_stage_w2(const float4& w2, int tx0p, int ty0p) {
+    const uint32_t b0 = __float_as_uint(w2.y), b1 = __float_as_uint(w2.z);
+    const uint32_t cm = span_mask16((int)(b0 & 0xFFFFu) - tx0p, (int)(b1 & 0xFFFFu) - tx0p);
+    const uint32_t rm = span_mask16((int)(b0 >> 16) - ty0p, (int)(b1 >> 16) - ty0p);
+    return make_float4(w2.x, w2.w - 1e-4f, w2.w + 1e-4f, __uint_as_float(cm | (rm << 16)));
 }
 
 // wave64 helpers

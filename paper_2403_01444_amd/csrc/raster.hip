@@ -304,14 +304,15 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
     const int tile = order ? order[blockIdx.x] : tile_of_block(blockIdx.x, ntiles);
     __shared__ float4 s_w0[NT];
     __shared__ float4 s_w1[NT];
-    __shared__ float4 s_w2[NT];
-    __shared__ uint8_t s_full[NT];
+    __shared__ float4 s_w2[NT];   // blend_stage_w2 form
     if (tile >= ntiles) return;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int tx0p = tx * kTile, ty0p = ty * kTile;
-    const int tx1p = min(tx0p + kTile - 1, cam.W - 1), ty1p = min(ty0p + kTile - 1, cam.H - 1);
     const int px = tx0p + (threadIdx.x & 15), py0 = ty0p + (threadIdx.x >> 4) * R;
     const float fpx = (float)px;
+    uint32_t sel[R];   // this thread's column and row bits in the box masks
+#pragma unroll
+    for (int k = 0; k < R; k++) sel[k] = (1u << (threadIdx.x & 15)) | (1u << (16 + (threadIdx.x >> 4) * R + k));
     const uint2 rg = ranges[tile];
     const uint32_t start = rg.x, end = rg.y;
     float T[R], c0[R], c1[R], c2[R];
@@ -335,9 +336,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
             const uint32_t id = vals[e];
             s_w0[threadIdx.x] = rec[3 * (int64_t)id + 0];
             s_w1[threadIdx.x] = rec[3 * (int64_t)id + 1];
-            const float4 w2 = rec[3 * (int64_t)id + 2];
-            s_w2[threadIdx.x] = w2;
-            s_full[threadIdx.x] = box_covers(__float_as_uint(w2.y), __float_as_uint(w2.z), tx0p, ty0p, tx1p, ty1p);
+            s_w2[threadIdx.x] = blend_stage_w2(rec[3 * (int64_t)id + 2], tx0p, ty0p);
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, end - b);
@@ -346,11 +345,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
             // the state of pixels that do not take the contribution
             auto eval = [&](int j) {
                 const float4 w0 = s_w0[j], w1 = s_w1[j], w2 = s_w2[j];
-                const bool full = s_full[j];
-                const uint32_t bx0 = __float_as_uint(w2.y), bx1 = __float_as_uint(w2.z);
-                const bool inx = full | ((px >= (int)(bx0 & 0xFFFFu)) & (px <= (int)(bx1 & 0xFFFFu)));
-                const int y0 = (int)(bx0 >> 16), y1 = (int)(bx1 >> 16);
-                const float pthr = w2.w;
+                const uint32_t box = __float_as_uint(w2.w);
                 float adx2, bdx;
                 blend_dx_terms(fpx - w0.x, w0, adx2, bdx);
                 float power[R];
@@ -358,11 +353,9 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                 bool any_band = false;
 #pragma unroll
                 for (int k = 0; k < R; k++) {
-                    const int py = py0 + k;
-                    power[k] = blend_power(adx2, bdx, (float)py - w0.y, w1.x);
-                    ok[k] = !done[k] & inx & (full | ((py >= y0) & (py <= y1))) & (power[k] <= 0.0f) &
-                            (power[k] >= pthr - 1e-4f);
-                    band[k] = ok[k] & (power[k] < pthr + 1e-4f);
+                    power[k] = blend_power(adx2, bdx, (float)(py0 + k) - w0.y, w1.x);
+                    ok[k] = !done[k] & ((box & sel[k]) == sel[k]) & (power[k] <= 0.0f) & (power[k] >= w2.y);
+                    band[k] = ok[k] & (power[k] < w2.z);
                     any_band = any_band || band[k];
                 }
                 if (__any(any_band)) {
@@ -376,10 +369,10 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                     const float Tn = T[k] * (1.0f - alpha);
                     const bool stop = ok[k] & (Tn < 1e-4f);
                     const bool take = ok[k] & !stop;
-                    const float wgt = alpha * T[k];
-                    c0[k] = take ? c0[k] + wgt * w1.z : c0[k];
-                    c1[k] = take ? c1[k] + wgt * w1.w : c1[k];
-                    c2[k] = take ? c2[k] + wgt * w2.x : c2[k];
+                    const float wgt = take ? alpha * T[k] : 0.0f;
+                    c0[k] += wgt * w1.z;
+                    c1[k] += wgt * w1.w;
+                    c2[k] += wgt * w2.x;
                     T[k] = take ? Tn : T[k];
                     last[k] = take ? b - start + (uint32_t)j + 1u : last[k];
                     done[k] = done[k] | stop;
@@ -429,6 +422,10 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
 // (fixed summation order; gathered per Gaussian by the preprocess backward),
 // atomics only past its capacity; otherwise one global atomic per term and
 // (tile, Gaussian).  kOpacity: also reduce the opacity term.
+// factors of the nine reduced terms: the conic terms are summed as dx^2,
+// dx dy and dy^2 (powers of two: the scaling is exact)
+__constant__ float kConicScale[9] = {1.f, 1.f, -0.5f, -1.f, -0.5f, 1.f, 1.f, 1.f, 1.f};
+
 template <int R, bool kRecords, bool kOpacity>
 __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int ntiles,
                                                                  const uint2* __restrict__ ranges,
@@ -445,9 +442,8 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
     constexpr int NT = kTile * kTile / R, NW = NT / 64;
     __shared__ float4 s_w0[NT];
     __shared__ float4 s_w1[NT];
-    __shared__ float4 s_w2[NT];
+    __shared__ float4 s_w2[NT];   // blend_stage_w2 form
     __shared__ uint32_t s_id[NT];
-    __shared__ uint8_t s_full[NT];
     __shared__ float s_g[NW][9][NT];   // per-wave sums, [wave][term][entry]
     const int tile = order ? order[blockIdx.x] : tile_of_block(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
@@ -455,9 +451,11 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
     if (maxlast == 0) return;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int tx0p = tx * kTile, ty0p = ty * kTile;
-    const int tx1p = min(tx0p + kTile - 1, cam.W - 1), ty1p = min(ty0p + kTile - 1, cam.H - 1);
     const int px = tx0p + (threadIdx.x & 15), py0 = ty0p + (threadIdx.x >> 4) * R;
     const float fpx = (float)px;
+    uint32_t sel[R];   // this thread's column and row bits in the box masks
+#pragma unroll
+    for (int k = 0; k < R; k++) sel[k] = (1u << (threadIdx.x & 15)) | (1u << (16 + (threadIdx.x >> 4) * R + k));
     const uint32_t start = ranges[tile].x;
     const uint32_t woff = kRecords ? walk_off[tile] : 0u;
     const int64_t P = (int64_t)cam.W * cam.H;
@@ -491,23 +489,17 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
             s_id[threadIdx.x] = id;
             s_w0[threadIdx.x] = rec[3 * (int64_t)id + 0];
             s_w1[threadIdx.x] = rec[3 * (int64_t)id + 1];
-            const float4 w2 = rec[3 * (int64_t)id + 2];
-            s_w2[threadIdx.x] = w2;
-            s_full[threadIdx.x] = box_covers(__float_as_uint(w2.y), __float_as_uint(w2.z), tx0p, ty0p, tx1p, ty1p);
+            s_w2[threadIdx.x] = blend_stage_w2(rec[3 * (int64_t)id + 2], tx0p, ty0p);
         }
         __syncthreads();
         const int cnt = (int)min((int64_t)NT, (int64_t)maxlast - jb);
         for (int j = cnt - 1; j >= 0; j--) {
             const uint32_t ej = (uint32_t)jb + (uint32_t)j;
-            float gr[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float gr[8];   // this thread's sums of the eight terms over its R pixels
             float gop = 0.f;
             bool act = false;
             const float4 w0 = s_w0[j], w1 = s_w1[j], w2 = s_w2[j];
-            const bool full = s_full[j];
-            const uint32_t bx0 = __float_as_uint(w2.y), bx1 = __float_as_uint(w2.z);
-            const bool inx = full | ((px >= (int)(bx0 & 0xFFFFu)) & (px <= (int)(bx1 & 0xFFFFu)));
-            const int y0 = (int)(bx0 >> 16), y1 = (int)(bx1 >> 16);
-            const float pthr = w2.w;
+            const uint32_t box = __float_as_uint(w2.w);
             const float cr = w1.z, cg = w1.w, cb = w2.x;
             const float dx = fpx - w0.x;
             float adx2, bdx;
@@ -517,12 +509,10 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
             bool any_band = false;
 #pragma unroll
             for (int k = 0; k < R; k++) {
-                const int py = py0 + k;
-                dy[k] = (float)py - w0.y;
+                dy[k] = (float)(py0 + k) - w0.y;
                 power[k] = blend_power(adx2, bdx, dy[k], w1.x);
-                ok[k] = (ej < last[k]) & inx & (full | ((py >= y0) & (py <= y1))) & (power[k] <= 0.0f) &
-                        (power[k] >= pthr - 1e-4f);
-                band[k] = ok[k] & (power[k] < pthr + 1e-4f);
+                ok[k] = (ej < last[k]) & ((box & sel[k]) == sel[k]) & (power[k] <= 0.0f) & (power[k] >= w2.y);
+                band[k] = ok[k] & (power[k] < w2.z);
                 any_band = any_band || band[k];
             }
             if (__any(any_band)) {
@@ -541,22 +531,25 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
                 // T recovery T_i = T_{i+1} / (1 - alpha_i), with the hardware reciprocal (1 ulp)
                 const float Tk = ok[k] ? T[k] * __builtin_amdgcn_rcpf(1.0f - alpha) : T[k];
                 T[k] = Tk;
-                const float wgt = ok[k] ? alpha * Tk : 0.0f;
-                gr[5] += g0[k] * wgt;
-                gr[6] += g1[k] * wgt;
-                gr[7] += g2[k] * wgt;
-                const float dal = Tk * (g0[k] * (cr - b0[k]) + g1[k] * (cg - b1[k]) + g2[k] * (cb - b2[k]));
-                b0[k] = ok[k] ? alpha * cr + (1.0f - alpha) * b0[k] : b0[k];
-                b1[k] = ok[k] ? alpha * cg + (1.0f - alpha) * b1[k] : b1[k];
-                b2[k] = ok[k] ? alpha * cb + (1.0f - alpha) * b2[k] : b2[k];
+                const float aok = ok[k] ? alpha : 0.0f;   // zero: the pixel's state is kept
+                const float wgt = aok * Tk;
+                const float e0 = cr - b0[k], e1 = cg - b1[k], e2 = cb - b2[k];
+                const float dal = Tk * (g0[k] * e0 + g1[k] * e1 + g2[k] * e2);
+                // colour behind the next contributor: alpha c + (1 - alpha) b
+                b0[k] += aok * e0;
+                b1[k] += aok * e1;
+                b2[k] += aok * e2;
                 const bool unclamped = ok[k] && raw < 0.99f;
                 const float dp = unclamped ? dal * raw : 0.0f;
                 gop += unclamped ? dal * G : 0.0f;
-                gr[0] += dp * (w0.z * dx + w0.w * dy[k]);
-                gr[1] += dp * (w0.w * dx + w1.x * dy[k]);
-                gr[2] += dp * (-0.5f * dx * dx);
-                gr[3] += dp * (-dx * dy[k]);
-                gr[4] += dp * (-0.5f * dy[k] * dy[k]);
+                // d power / d(u, v) = (A dx + B dy, B dx + C dy); the conic
+                // terms -dx^2 / 2, -dx dy, -dy^2 / 2 get their constant factors
+                // after the reduction (kConicScale)
+                const float tx = dp * dx, ty = dp * dy[k];
+                const float t8[8] = {w0.z * tx + w0.w * ty, w0.w * tx + w1.x * ty, tx * dx, tx * dy[k],
+                                     ty * dy[k], g0[k] * wgt, g1[k] * wgt, g2[k] * wgt};
+#pragma unroll
+                for (int c = 0; c < 8; c++) gr[c] = k == 0 ? t8[c] : gr[c] + t8[c];
             }
             const bool any = __any(act);
             float red = 0.f, redop = 0.f;
@@ -580,6 +573,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
                 float v = s_g[0][k][threadIdx.x];
 #pragma unroll
                 for (int w = 1; w < NW; w++) v += s_g[w][k][threadIdx.x];
+                v *= kConicScale[k];
                 if (fits)
                     grec[(int64_t)k * grec_cap + widx] = v;
                 else if (v != 0.f)
