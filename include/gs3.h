@@ -201,7 +201,7 @@ gs3_status gs3_ntc_backward(gs3_ctx* ctx, const float* means, int64_t n,
  * (no atomics, fixed order).  The caller guarantees that the contents of
  * `means` do not change until the next gs3_ntc_prepare; a call with another
  * pointer or n uses the atomic scatter.  Allocates device memory on first
- * use or growth (about 1 KB per mean) and synchronises. */
+ * use or growth (about 3.2 KB per mean) and synchronises. */
 gs3_status gs3_ntc_prepare(gs3_ctx* ctx, const float* means, int64_t n);
 
 /* One Adam step on the NTC parameters with the accumulated gradients,

@@ -410,7 +410,7 @@ gs3_status gs3_ntc_prepare(gs3_ctx* c, const float* means, int64_t n) {
                   get((void**)&c->csr_vals[0], m * 4) && get((void**)&c->csr_vals[1], m * 4) &&
                   get((void**)&c->csr_hist, radix_hist_words(m) * 4) &&
                   get((void**)&c->csr_tmp, (scan_tmp_words(radix_hist_words(m)) + 4) * 8) &&
-                  get((void**)&c->csr.rows, entries * 8) && get((void**)&c->csr.w, m * 4) &&
+                  get((void**)&c->csr.rows, entries * 8) && get((void**)&c->csr.pw, m * 8) &&
                   get((void**)&c->csr.denc, n * 32 * 4);
         if (!ok) {
             for (void* p : c->csr_allocs) hipFree(p);

@@ -17,9 +17,9 @@ struct NtcDev {
 // Per-frame contribution lists of the table gradient (see ntc.hip).
 struct NtcCsr {
     int64_t entries = 0;      // table entries
-    uint2* rows = nullptr;    // [entries]: [start, end) into pid / w
+    uint2* rows = nullptr;    // [entries]: [start, end) into pw
     uint32_t* pid = nullptr;  // point << 7 | level << 3 | corner, sorted by entry
-    float* w = nullptr;       // trilinear weight of each contribution
+    uint2* pw = nullptr;      // (pid, float bits of the trilinear weight) of each contribution
     float* denc = nullptr;    // [16 levels][n][2] encoding gradient of the current backward
 };
 

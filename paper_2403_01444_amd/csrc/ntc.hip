@@ -547,14 +547,14 @@ __global__ __launch_bounds__(256) void k_csr_rows(const uint32_t* __restrict__ k
 
 __global__ __launch_bounds__(256) void k_csr_weights(NtcDev nd, const float* __restrict__ means,
                                                      const uint32_t* __restrict__ key, const uint32_t* __restrict__ pid,
-                                                     int64_t m, uint32_t sentinel, float* __restrict__ w) {
+                                                     int64_t m, uint32_t sentinel, uint2* __restrict__ pw) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= m) return;
+    const uint32_t c = pid[k];
     if (key[k] == sentinel) {
-        w[k] = 0.f;
+        pw[k] = make_uint2(c, 0u);
         return;
     }
-    const uint32_t c = pid[k];
     const int64_t pt = c >> 7;
     const int lv = (c >> 3) & 15, corner = c & 7;
     const float mu[3] = {means[3 * pt], means[3 * pt + 1], means[3 * pt + 2]};
@@ -563,15 +563,16 @@ __global__ __launch_bounds__(256) void k_csr_weights(NtcDev nd, const float* __r
     int64_t ent[8];
     float wt[8];
     ntc_corners(nd, lv, x, ent, wt);
-    w[k] = wt[corner];
+    pw[k] = make_uint2(c, __float_as_uint(wt[corner]));
 }
 
-// 8 lanes per table entry: the entry's contributions are read 8 at a time
-// (coalesced), each lane gathers its point's encoding gradient, and the group
-// sums with DPP (pairs, quads, half-row mirror): fixed order.
-__global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ rows, const uint32_t* __restrict__ pid,
-                                                    const float* __restrict__ w, const float* __restrict__ denc,
-                                                    int64_t n, int64_t entries, float* __restrict__ g_table) {
+// 8 lanes per table entry: the entry's (point, weight) contributions are
+// read 8 at a time (coalesced, one 8-byte load each), each lane gathers its
+// point's encoding gradient, and the group sums with DPP (pairs, quads,
+// half-row mirror): fixed order.
+__global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ rows, const uint2* __restrict__ pw,
+                                                    const float* __restrict__ denc, int64_t n, int64_t entries,
+                                                    float* __restrict__ g_table) {
     const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 3;
     const int sub = threadIdx.x & 7;
     uint2 r = make_uint2(0u, 0u);
@@ -584,9 +585,10 @@ __global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ ro
     // four independent contribution loads in flight per lane; the sum keeps
     // the order k, k + 8, k + 16, ...
     for (; k + 24 < r.y; k += 32) {
-        const uint32_t c0 = pid[k], c1 = pid[k + 8], c2 = pid[k + 16], c3 = pid[k + 24];
-        const float w0 = w[k], w1 = w[k + 8], w2 = w[k + 16], w3 = w[k + 24];
-        const float2 d0 = enc(c0), d1 = enc(c1), d2 = enc(c2), d3 = enc(c3);
+        const uint2 c0 = pw[k], c1 = pw[k + 8], c2 = pw[k + 16], c3 = pw[k + 24];
+        const float2 d0 = enc(c0.x), d1 = enc(c1.x), d2 = enc(c2.x), d3 = enc(c3.x);
+        const float w0 = __uint_as_float(c0.y), w1 = __uint_as_float(c1.y);
+        const float w2 = __uint_as_float(c2.y), w3 = __uint_as_float(c3.y);
         a0 += w0 * d0.x;
         a1 += w0 * d0.y;
         a0 += w1 * d1.x;
@@ -597,8 +599,9 @@ __global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ ro
         a1 += w3 * d3.y;
     }
     for (; k < r.y; k += 8) {
-        const float2 d = enc(pid[k]);
-        const float wk = w[k];
+        const uint2 c = pw[k];
+        const float2 d = enc(c.x);
+        const float wk = __uint_as_float(c.y);
         a0 += wk * d.x;
         a1 += wk * d.y;
     }
@@ -734,8 +737,8 @@ void bwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* 
                            (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, csr->denc);
         if (L.prof) L.prof->end(L.st);
         if (L.prof) L.prof->begin("ntc_scatter", L.st);
-        hipLaunchKernelGGL(k_csr_gather, dim3(nblk(csr->entries * 8, 256)), dim3(256), 0, L.st, csr->rows, csr->pid,
-                           csr->w, csr->denc, n, csr->entries, g_table);
+        hipLaunchKernelGGL(k_csr_gather, dim3(nblk(csr->entries * 8, 256)), dim3(256), 0, L.st, csr->rows, csr->pw,
+                           csr->denc, n, csr->entries, g_table);
     } else {
         hipLaunchKernelGGL((k_ntc_bwd<P, false>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
                            (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, (float*)nullptr);
@@ -790,7 +793,7 @@ void ntc_csr_build(const Launch& L, const NtcDev& nd, const float* means, int64_
     fill_u32(inner, reinterpret_cast<uint32_t*>(csr.rows), 0u, 2 * csr.entries);
     hipLaunchKernelGGL(k_csr_rows, dim3(nblk(m, 256)), dim3(256), 0, L.st, keys[r], m, sentinel, csr.rows);
     hipLaunchKernelGGL(k_csr_weights, dim3(nblk(m, 256)), dim3(256), 0, L.st, nd, means, keys[r], csr.pid, m, sentinel,
-                       csr.w);
+                       csr.pw);
     if (L.prof) L.prof->end(L.st);
 }
 

@@ -317,19 +317,23 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
     const uint32_t start = rg.x, end = rg.y;
     float T[R], c0[R], c1[R], c2[R];
     uint32_t last[R];
-    bool done[R];
+    // pixel row coordinate, NaN once the pixel has stopped (and for pixels
+    // outside the image): every comparison of its exponent is then false, so
+    // a stopped pixel takes no further contribution without a flag test
+    const float kStopped = __int_as_float(0x7FC00000);
+    float fpy[R];
 #pragma unroll
     for (int k = 0; k < R; k++) {
         T[k] = 1.0f;
         c0[k] = c1[k] = c2[k] = 0.f;
         last[k] = 0u;
-        done[k] = !(px < cam.W && py0 + k < cam.H);
+        fpy[k] = (px < cam.W && py0 + k < cam.H) ? (float)(py0 + k) : kStopped;
     }
     if (threadIdx.x == 0) s_walk = 0u;
     for (uint32_t b = start; b < end; b += NT) {
         bool all = true;
 #pragma unroll
-        for (int k = 0; k < R; k++) all = all && done[k];
+        for (int k = 0; k < R; k++) all = all && (fpy[k] != fpy[k]);
         if (__syncthreads_count(all) == NT) break;
         const uint32_t e = b + threadIdx.x;
         if (e < end) {
@@ -353,8 +357,8 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                 bool any_band = false;
 #pragma unroll
                 for (int k = 0; k < R; k++) {
-                    power[k] = blend_power(adx2, bdx, (float)(py0 + k) - w0.y, w1.x);
-                    ok[k] = !done[k] & ((box & sel[k]) == sel[k]) & (power[k] <= 0.0f) & (power[k] >= w2.y);
+                    power[k] = blend_power(adx2, bdx, fpy[k] - w0.y, w1.x);
+                    ok[k] = ((box & sel[k]) == sel[k]) & (power[k] <= 0.0f) & (power[k] >= w2.y);
                     band[k] = ok[k] & (power[k] < w2.z);
                     any_band = any_band || band[k];
                 }
@@ -375,7 +379,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                     c2[k] += wgt * w2.x;
                     T[k] = take ? Tn : T[k];
                     last[k] = take ? b - start + (uint32_t)j + 1u : last[k];
-                    done[k] = done[k] | stop;
+                    fpy[k] = stop ? kStopped : fpy[k];
                 }
             };
             // two entries per trip; the wave leaves once all its pixels have stopped
@@ -385,7 +389,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                 eval(j + 1);
                 bool active = false;
 #pragma unroll
-                for (int k = 0; k < R; k++) active = active | !done[k];
+                for (int k = 0; k < R; k++) active = active | (fpy[k] == fpy[k]);
                 if (!__any(active)) break;
             }
             if (j + 1 == cnt) eval(j);
