@@ -87,6 +87,17 @@ __device__ __forceinline__ typename P::AF frag_k_strided(const typename P::S* ba
     return f;
 }
 
+// Inside the batch loops each wave works on its own activation arrays in LDS
+// (the staged weights are read-only there), so the waves of a workgroup only
+// order their own LDS accesses: a wave-level barrier that keeps the compiler
+// from moving LDS accesses across it (a wave's LDS operations complete in
+// issue order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Row strides (elements) of the LDS arrays; +4 breaks bank regularity.
 constexpr int kMlpParams = 64 * 32 + 64 * 64 + 7 * 64;
 constexpr int LD32 = 32 + 4;
@@ -95,13 +106,18 @@ constexpr int LD16 = 16 + 4;
 constexpr int kWaves = 4;
 constexpr int kPts = 16;
 
+// the two features of a table entry; the entry's byte offset fits in 32 bits
+// (at most 2^26 entries), so the load takes a scalar base and a 32-bit offset
 template <class P>
-__device__ __forceinline__ float2 load2(const typename P::S* table, int64_t entry) {
+__device__ __forceinline__ float2 load2(const typename P::S* table, uint32_t entry) {
+    const unsigned char* base = reinterpret_cast<const unsigned char*>(table);
+    const uint32_t off = entry * (uint32_t)(2 * sizeof(typename P::S));
     if constexpr (sizeof(typename P::S) == 4) {
-        return *reinterpret_cast<const float2*>(table + 2 * entry);
+        return *reinterpret_cast<const float2*>(base + off);
     } else {
-        const typename P::S* e = table + 2 * entry;
-        return make_float2(P::tof(e[0]), P::tof(e[1]));
+        typedef typename P::S s2v __attribute__((ext_vector_type(2)));
+        const s2v v = *reinterpret_cast<const s2v*>(base + off);
+        return make_float2(P::tof(v.x), P::tof(v.y));
     }
 }
 
@@ -117,7 +133,7 @@ __device__ __forceinline__ bool ntc_normalise(const NtcDev& nd, const float* mu,
 }
 
 // corner entries and trilinear weights of level lv
-__device__ __forceinline__ void ntc_corners(const NtcDev& nd, int lv, const float x[3], int64_t ent[8], float wt[8]) {
+__device__ __forceinline__ void ntc_corners(const NtcDev& nd, int lv, const float x[3], uint32_t ent[8], float wt[8]) {
     float w[3];
     uint32_t i0[3];
     {
@@ -143,7 +159,7 @@ __device__ __forceinline__ void ntc_corners(const NtcDev& nd, int lv, const floa
             idx = vx + (uint32_t)N1 * (vy + (uint32_t)N1 * vz);
         else
             idx = ((vx * 1u) ^ (vy * 2654435761u) ^ (vz * 805459861u)) & nd.T_mask;
-        ent[c] = nd.off[lv] + (int64_t)idx;
+        ent[c] = (uint32_t)nd.off[lv] + idx;
         wt[c] = ((c & 1) ? w[0] : 1.0f - w[0]) * (((c >> 1) & 1) ? w[1] : 1.0f - w[1]) *
                 (((c >> 2) & 1) ? w[2] : 1.0f - w[2]);
     }
@@ -196,7 +212,7 @@ __device__ __forceinline__ void encode_lane(const NtcDev& nd, const typename P::
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const int lv = 4 * g + j;
-        int64_t ent[8];
+        uint32_t ent[8];
         float wt[8];
         ntc_corners(nd, lv, x, ent, wt);
         float e0 = 0.f, e1 = 0.f;
@@ -219,6 +235,7 @@ __global__ __launch_bounds__(256) void k_ntc_fwd(NtcDev nd, const typename P::S*
     __shared__ S sW1[64 * LD32], sW2[64 * LD64], sW3[16 * LD64];
     __shared__ S sX[kWaves][kPts * LD32], sH1[kWaves][kPts * LD64], sH2[kWaves][kPts * LD64];
     load_weights<P>(mlp, sW1, sW2, sW3, nullptr, nullptr, nullptr);
+    __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int p = lane & 15, g = lane >> 4;
     S* X = sX[w];
@@ -234,25 +251,25 @@ __global__ __launch_bounds__(256) void k_ntc_fwd(NtcDev nd, const typename P::S*
             const float mu[3] = {means[3 * pt], means[3 * pt + 1], means[3 * pt + 2]};
             in = ntc_normalise(nd, mu, x);
         }
-        __syncthreads();   // weights staged / previous batch's reads of X done
+        wave_sync();   // previous batch's reads of X done
         if (in) {
             encode_lane<P>(nd, table, x, g, X, p);
         } else {
             for (int j = 0; j < 8; j++) X[p * LD32 + 8 * g + j] = P::cvt(0.f);
         }
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int mt = 0; mt < 4; mt++) {
             const f4v a = layer_tile<P, 32>(sW1, LD32, mt * 16, X, LD32, lane);
             for (int r = 0; r < 4; r++) H1[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(fmaxf(a[r], 0.f));
         }
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int mt = 0; mt < 4; mt++) {
             const f4v a = layer_tile<P, 64>(sW2, LD64, mt * 16, H1, LD64, lane);
             for (int r = 0; r < 4; r++) H2[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(fmaxf(a[r], 0.f));
         }
-        __syncthreads();
+        wave_sync();
         const f4v o = layer_tile<P, 64>(sW3, LD64, 0, H2, LD64, lane);
         if (valid && g < 2) {
             if (g == 0) {
@@ -274,13 +291,18 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-// power of two s with max * s in [2^12, 2^13); 1 when max is 0
-__device__ __forceinline__ float pow2_scale(float mx) {
-    if (!(mx > 0.f) || !isfinite(mx)) return 1.0f;
+// exponent k of the power of two 2^k with max * 2^k in [2^12, 2^13); 0 when
+// max is 0 or not finite
+__device__ __forceinline__ int pow2_exp(float mx) {
+    if (!(mx > 0.f) || !isfinite(mx)) return 0;
     int e;
     frexpf(mx, &e);   // mx = f 2^e, f in [0.5, 1)
-    return ldexpf(1.0f, 13 - e);
+    return 13 - e;
 }
+
+// the scale exponents stay inside the normal range of float, so 2^k and
+// 2^-k are exact
+__device__ __forceinline__ int clamp_exp(int k) { return k < -126 ? -126 : (k > 126 ? 126 : k); }
 
 // kCSR: write the encoding gradient (n x 32 floats) to `denc` for the
 // per-entry gather of the prepared contribution lists; otherwise scatter-add
@@ -304,6 +326,7 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
     __shared__ S sO[kWaves][kPts * LD16];
     __shared__ float sE[kWaves][kPts * 33];
     load_weights<P>(mlp, sW1, sW2, nullptr, sW1t, sW2t, sW3t);
+    __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int p = lane & 15, g = lane >> 4, col = lane & 15;
     S* X = sX[w];
@@ -317,6 +340,13 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
         for (int b = 0; b < 4; b++) gW2[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
         gW3[a] = f4v{0.f, 0.f, 0.f, 0.f};
     }
+    // the level slices this lane writes in the level-major encoding gradient:
+    // levels 2 g and 8 + 2 g (and the level after each)
+    float2* dlev[2] = {nullptr, nullptr};
+    if (kCSR) {
+        dlev[0] = reinterpret_cast<float2*>(denc) + (int64_t)(2 * g) * n;
+        dlev[1] = reinterpret_cast<float2*>(denc) + (int64_t)(8 + 2 * g) * n;
+    }
     const int64_t nb = (n + kPts - 1) / kPts;
     for (int64_t b0 = (int64_t)blockIdx.x * kWaves; b0 < nb; b0 += (int64_t)gridDim.x * kWaves) {
         const int64_t pt = (b0 + w) * kPts + p;
@@ -327,7 +357,7 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
             const float mu[3] = {means[3 * pt], means[3 * pt + 1], means[3 * pt + 2]};
             in = ntc_normalise(nd, mu, x);
         }
-        __syncthreads();
+        wave_sync();
         // 1. encoding
         if (in) {
             encode_lane<P>(nd, table, x, g, X, p);
@@ -346,27 +376,30 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
             dv[1] = d_dq[4 * pt + 2];
             dv[2] = d_dq[4 * pt + 3];
         }
-        float s0 = 1.0f;
+        // the activation gradients of this batch are held scaled by 2^k0,
+        // 2^k1, 2^k2 (exact powers of two; the weight gradients unscale them)
+        int k0 = 0;
         if (P::kScaled)
-            s0 = pow2_scale(wave_max(fmaxf(fmaxf(fabsf(dv[0]), fabsf(dv[1])), fmaxf(fabsf(dv[2]), fabsf(dv[3])))));
+            k0 = clamp_exp(pow2_exp(wave_max(fmaxf(fmaxf(fabsf(dv[0]), fabsf(dv[1])), fmaxf(fabsf(dv[2]), fabsf(dv[3]))))));
+        const float s0 = ldexpf(1.0f, k0);
         for (int r = 0; r < 4; r++) O[p * LD16 + 4 * g + r] = P::cvt(dv[r] * s0);   // rows 8..15 stay zero
-        __syncthreads();
+        wave_sync();
         // 2. forward recompute
 #pragma unroll
         for (int mt = 0; mt < 4; mt++) {
             const f4v a = layer_tile<P, 32>(sW1, LD32, mt * 16, X, LD32, lane);
             for (int r = 0; r < 4; r++) H1[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(fmaxf(a[r], 0.f));
         }
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int mt = 0; mt < 4; mt++) {
             const f4v a = layer_tile<P, 64>(sW2, LD64, mt * 16, H1, LD64, lane);
             for (int r = 0; r < 4; r++) H2[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(fmaxf(a[r], 0.f));
         }
-        __syncthreads();
+        wave_sync();
         // 3. dW3[o][m] += sum_p dO[p][o] H2[p][m]
         {
-            const float inv = 1.0f / s0;
+            const float inv = ldexpf(1.0f, -k0);
 #pragma unroll
             for (int nt = 0; nt < 4; nt++) {
                 f4v t = {0.f, 0.f, 0.f, 0.f};
@@ -390,18 +423,18 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
                 m2 = fmaxf(m2, fabsf(d2[mt][r]));
             }
         }
-        float s1 = s0;
-        if (P::kScaled) s1 = s0 * pow2_scale(wave_max(m2));
-        __syncthreads();   // all reads of H2 (step 3) done
+        int k1 = k0;
+        if (P::kScaled) k1 = clamp_exp(k0 + pow2_exp(wave_max(m2)));
+        wave_sync();   // all reads of H2 (step 3) done
         {
-            const float f = s1 / s0;
+            const float f = ldexpf(1.0f, k1 - k0);
             for (int mt = 0; mt < 4; mt++)
                 for (int r = 0; r < 4; r++) H2[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(d2[mt][r] * f);
         }
-        __syncthreads();
+        wave_sync();
         // 5. dW2[m][k] += sum_p dH2[p][m] H1[p][k]
         {
-            const float inv = 1.0f / s1;
+            const float inv = ldexpf(1.0f, -k1);
 #pragma unroll
             for (int mt = 0; mt < 4; mt++)
 #pragma unroll
@@ -428,18 +461,18 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
                 m1 = fmaxf(m1, fabsf(d1[mt][r]));
             }
         }
-        float s2 = s1;
-        if (P::kScaled) s2 = s1 * pow2_scale(wave_max(m1));
-        __syncthreads();   // all reads of H1 (step 5) done
+        int k2 = k1;
+        if (P::kScaled) k2 = clamp_exp(k1 + pow2_exp(wave_max(m1)));
+        wave_sync();   // all reads of H1 (step 5) done
         {
-            const float f = s2 / s1;
+            const float f = ldexpf(1.0f, k2 - k1);
             for (int mt = 0; mt < 4; mt++)
                 for (int r = 0; r < 4; r++) H1[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(d1[mt][r] * f);
         }
-        __syncthreads();
+        wave_sync();
         // 7. dW1[m][k] += sum_p dH1[p][m] X[p][k];  dX = W1^T dH1
         {
-            const float inv = 1.0f / s2;
+            const float inv = ldexpf(1.0f, -k2);
 #pragma unroll
             for (int mt = 0; mt < 4; mt++)
 #pragma unroll
@@ -460,30 +493,29 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
                     // level-major [level][point][2]: one level's slice (8 n bytes)
                     // stays cache-resident while the gather walks that level
                     if (valid) {
-                        const int lv = mt * 8 + 2 * g;
-                        *reinterpret_cast<float2*>(denc + 2 * ((int64_t)lv * n + pt)) = make_float2(e[0] * inv, e[1] * inv);
-                        *reinterpret_cast<float2*>(denc + 2 * ((int64_t)(lv + 1) * n + pt)) =
-                            make_float2(e[2] * inv, e[3] * inv);
+                        float2* d = dlev[mt] + pt;
+                        d[0] = make_float2(e[0] * inv, e[1] * inv);
+                        d[n] = make_float2(e[2] * inv, e[3] * inv);   // level lv + 1
                     }
                 } else {
                     for (int r = 0; r < 4; r++) E[p * 33 + mt * 16 + 4 * g + r] = e[r] * inv;
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
         // 8. scatter-add the encoding gradient into the table gradient
         if (!kCSR && in) {
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const int lv = 4 * g + j;
-                int64_t ent[8];
+                uint32_t ent[8];
                 float wt[8];
                 ntc_corners(nd, lv, x, ent, wt);
                 const float e0 = E[p * 33 + 2 * lv], e1 = E[p * 33 + 2 * lv + 1];
 #pragma unroll
                 for (int c = 0; c < 8; c++) {
-                    atomicAdd(g_table + 2 * ent[c], wt[c] * e0);
-                    atomicAdd(g_table + 2 * ent[c] + 1, wt[c] * e1);
+                    atomicAdd(g_table + 2 * (int64_t)ent[c], wt[c] * e0);
+                    atomicAdd(g_table + 2 * (int64_t)ent[c] + 1, wt[c] * e1);
                 }
             }
         }
@@ -526,7 +558,7 @@ __global__ __launch_bounds__(256) void k_csr_contrib(NtcDev nd, const float* __r
     const float mu[3] = {means[3 * pt], means[3 * pt + 1], means[3 * pt + 2]};
     float x[3];
     const bool in = ntc_normalise(nd, mu, x);
-    int64_t ent[8];
+    uint32_t ent[8];
     float wt[8];
     ntc_corners(nd, lv, x, ent, wt);
     for (int c = 0; c < 8; c++) {
@@ -560,7 +592,7 @@ __global__ __launch_bounds__(256) void k_csr_weights(NtcDev nd, const float* __r
     const float mu[3] = {means[3 * pt], means[3 * pt + 1], means[3 * pt + 2]};
     float x[3];
     ntc_normalise(nd, mu, x);
-    int64_t ent[8];
+    uint32_t ent[8];
     float wt[8];
     ntc_corners(nd, lv, x, ent, wt);
     pw[k] = make_uint2(c, __float_as_uint(wt[corner]));
