@@ -5,8 +5,9 @@
 // consecutive items (256 threads x 8).
 //
 // Radix sort: 8-bit digits, one histogram kernel and one scatter kernel per
-// pass.  A block owns 2048 consecutive items; wave w takes the 512 items
-// starting at w*512 in eight rounds of 64.  Inside a round the lanes that
+// pass.  A block owns 256 x I consecutive items (I = 8, or 4 for inputs
+// under kSmallSort items so that the launch still covers the chip); wave w
+// takes the 64 I items starting at w 64 I in I rounds of 64.  Inside a round the lanes that
 // share a digit are found with eight ballots (one per digit bit); a lane's
 // rank is the number of earlier lanes with its digit plus the wave's running
 // count for that digit.  Items keep their order (block, wave, round, lane),
@@ -123,15 +124,15 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d) {
     return m;
 }
 
-template <typename K>
+template <typename K, int I>
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const K* __restrict__ keys, int64_t n, int shift,
                                                          uint32_t* __restrict__ hist, int64_t nblocks) {
     __shared__ uint32_t s_h[256];
     s_h[threadIdx.x] = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kTileItems + w * (64 * kItems);
-    for (int r = 0; r < kItems; r++) {
+    const int64_t base = (int64_t)blockIdx.x * (kThreads * I) + w * (64 * I);
+    for (int r = 0; r < I; r++) {
         const int64_t idx = base + r * 64 + lane;
         const bool valid = idx < n;
         const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & 0xFFu : 0u;
@@ -142,21 +143,38 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const K* __restrict__ k
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = s_h[threadIdx.x];
 }
 
-template <typename K>
+// offs: per (digit, block) output offsets; with dtotal (per-digit scan) they
+// are relative to the digit's base, which the block adds from the totals.
+template <typename K, int I>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                             K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                             int64_t n, int shift, const uint32_t* __restrict__ offs,
-                                                            int64_t nblocks) {
+                                                            int64_t nblocks, const uint32_t* __restrict__ dtotal) {
     __shared__ uint32_t s_cnt[4][256];
     __shared__ uint32_t s_base[4][256];
+    __shared__ uint32_t s_dw[4];
     for (int k = threadIdx.x; k < 4 * 256; k += kThreads) (&s_cnt[0][0])[k] = 0;
+    uint32_t dbase = 0;   // exclusive prefix of the digit totals at digit threadIdx.x
+    if (dtotal) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const uint32_t v = dtotal[threadIdx.x];
+        uint32_t x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) s_dw[w] = x;
+        __syncthreads();
+        dbase = x - v;
+        for (int k = 0; k < w; k++) dbase += s_dw[k];
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kTileItems + w * (64 * kItems);
-    K key[kItems];
-    uint32_t val[kItems], rank[kItems], dig[kItems];
+    const int64_t base = (int64_t)blockIdx.x * (kThreads * I) + w * (64 * I);
+    K key[I];
+    uint32_t val[I], rank[I], dig[I];
 #pragma unroll
-    for (int r = 0; r < kItems; r++) {
+    for (int r = 0; r < I; r++) {
         const int64_t idx = base + r * 64 + lane;
         const bool valid = idx < n;
         key[r] = valid ? kin[idx] : (K)0;
@@ -172,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict_
     __syncthreads();
     {
         const int d = threadIdx.x;
-        uint32_t run = offs[(int64_t)d * nblocks + blockIdx.x];
+        uint32_t run = dbase + offs[(int64_t)d * nblocks + blockIdx.x];
         for (int k = 0; k < 4; k++) {
             s_base[k][d] = run;
             run += s_cnt[k][d];
@@ -180,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict_
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kItems; r++) {
+    for (int r = 0; r < I; r++) {
         const int64_t idx = base + r * 64 + lane;
         if (idx < n) {
             const uint32_t pos = s_base[w][dig[r]] + rank[r];
@@ -190,24 +208,64 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict_
     }
 }
 
-template <typename K>
-int radix_impl(const Launch& L, K* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist, uint64_t* tmp) {
+// One wave per digit d: exclusive scan over the blocks of hist[d][0..nb) in
+// place, the digit's total to dtotal[d].  With the totals, the scatter adds
+// the digit's base (the totals of the smaller digits) itself.
+__global__ __launch_bounds__(64) void k_radix_digit_scan(uint32_t* __restrict__ hist, int64_t nb,
+                                                         uint32_t* __restrict__ dtotal) {
+    uint32_t* h = hist + (int64_t)blockIdx.x * nb;
+    const int lane = threadIdx.x;
+    uint32_t carry = 0;
+    for (int64_t i0 = 0; i0 < nb; i0 += 64) {
+        const int64_t i = i0 + lane;
+        const uint32_t v = i < nb ? h[i] : 0u;
+        uint32_t x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (i < nb) h[i] = carry + x - v;
+        carry += __shfl(x, 63, 64);
+    }
+    if (lane == 0) dtotal[blockIdx.x] = carry;
+}
+
+// blocks per pass up to which the per-digit scan is used
+constexpr int64_t kDigitScanBlocks = 4096;
+
+template <typename K, int I>
+int radix_passes(const Launch& L, K* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist, uint64_t* tmp) {
     int cur = 0;
-    if (n <= 1) return cur;
-    const int64_t nb = (n + kTileItems - 1) / kTileItems;
+    const int64_t nb = (n + kThreads * I - 1) / (kThreads * I);
     const int64_t hn = nb * 256;
     for (int shift = 0; shift < bits; shift += 8) {
         if (L.prof) L.prof->begin("radix_pass", L.st);
-        hipLaunchKernelGGL((k_radix_hist<K>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, keys[cur], n, shift, hist,
-                           nb);
+        hipLaunchKernelGGL((k_radix_hist<K, I>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, keys[cur], n, shift,
+                           hist, nb);
         Launch inner{L.st, nullptr};
-        scan_impl<uint32_t>(inner, hist, hn, hist, (uint64_t*)(tmp), tmp + 1);
-        hipLaunchKernelGGL((k_radix_scatter<K>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, keys[cur], vals[cur],
-                           keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, nb);
+        uint32_t* dtotal = nullptr;
+        if (nb <= kDigitScanBlocks) {
+            dtotal = hist + hn;   // radix_hist_words leaves 256 words after the histogram
+            hipLaunchKernelGGL(k_radix_digit_scan, dim3(256), dim3(64), 0, L.st, hist, nb, dtotal);
+        } else {
+            scan_impl<uint32_t>(inner, hist, hn, hist, (uint64_t*)(tmp), tmp + 1);
+        }
+        hipLaunchKernelGGL((k_radix_scatter<K, I>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, keys[cur],
+                           vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, nb, dtotal);
         if (L.prof) L.prof->end(L.st);
         cur ^= 1;
     }
     return cur;
+}
+
+// inputs below this size take four items per thread (twice the workgroups)
+constexpr int64_t kSmallSort = (int64_t)1 << 21;
+
+template <typename K>
+int radix_impl(const Launch& L, K* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist, uint64_t* tmp) {
+    if (n <= 1) return 0;
+    if (n < kSmallSort) return radix_passes<K, 4>(L, keys, vals, n, bits, hist, tmp);
+    return radix_passes<K, 8>(L, keys, vals, n, bits, hist, tmp);
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
@@ -279,7 +337,9 @@ void scan_u32_to_u32(const Launch& L, const uint32_t* in, int64_t n, uint32_t* o
     scan_impl<uint32_t>(L, in, n, out, total, tmp);
 }
 
-int64_t radix_hist_words(int64_t n) { return ((n + kTileItems - 1) / kTileItems) * 256; }
+// histogram words for sorting any number of items up to n (the smaller,
+// 1024-item tiles bound both pass layouts), plus 256 for the digit totals
+int64_t radix_hist_words(int64_t n) { return ((n + kThreads * 4 - 1) / (kThreads * 4)) * 256 + 256; }
 
 int radix_sort_u32(const Launch& L, uint32_t* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist,
                    uint64_t* tmp) {
