@@ -1,22 +1,28 @@
 // Stage-1 loss (Eq. 6): L = (1 - lambda) L1 + lambda (1 - SSIM), and dL/dx.
 //
 // SSIM uses an 11 x 11 Gaussian window (sigma 1.5) with zero padding, per
-// channel, means over 3 x H x W.  The window is separable, so each 16 x 16
-// output tile loads a 26 x 26 halo tile into LDS and filters rows then
-// columns.  Forward: five filtered maps -> SSIM and its partial derivatives
-// with respect to the filtered mean, E[x^2] and E[xy] at each pixel.
-// Backward: the adjoint of a zero-padded correlation with a symmetric window
-// is the same correlation, so the three partial maps are filtered again and
-// combined with x and y.
+// channel, means over 3 x H x W.  The window is separable: each workgroup
+// loads a 42 x 42 halo tile for a 32 x 32 output tile into LDS, filters the
+// rows (a thread takes four adjacent outputs of a halo row, so it reads 14
+// inputs and forms their products once), then the columns (a thread takes
+// four outputs of one column from 14 row-filtered values).  Forward: five
+// filtered maps -> SSIM and its partial derivatives with respect to the
+// filtered mean, E[x^2] and E[xy] at each pixel.  Backward: the adjoint of a
+// zero-padded correlation with a symmetric window is the same correlation,
+// so the three partial maps are filtered again and combined with x and y.
 #include "kernels.h"
 
 namespace gs3 {
 
 namespace {
 
-constexpr int kT = 16;          // output tile edge
-constexpr int kR = 5;           // window radius
-constexpr int kH = kT + 2 * kR; // halo tile edge (26)
+constexpr int kTW = 32;              // output tile width
+constexpr int kTH = 32;              // output tile height
+constexpr int kR = 5;                // window radius
+constexpr int kHW = kTW + 2 * kR;    // halo tile width (42)
+constexpr int kHH = kTH + 2 * kR;    // halo tile height (42)
+constexpr int kQ = 4;                // outputs per thread in each filter pass
+constexpr int kIn = kQ + 2 * kR;     // inputs per thread in each filter pass (14)
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
 
@@ -56,83 +62,152 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ x, const f
     block_sum2(l1, 0.0, bsum + 2 * (int64_t)blockIdx.x);
 }
 
+// Row filter: for the tasks t = threadIdx.x, threadIdx.x + 256, ... of the
+// 42 x 8 (halo row r, column quad q) tasks, outputs at columns 4 q .. 4 q + 3.
+// kProducts: the five SSIM moments of src[0] = x and src[1] = y; otherwise
+// the NM maps src[m] -> dst[m].
+template <int NM, bool kProducts>
+__device__ __forceinline__ void row_filter(const Win& win, const float (*src)[kHH][kHW + 1],
+                                           float (*dst)[kHH][kTW + 1]) {
+    for (int t = threadIdx.x; t < kHH * (kTW / kQ); t += 256) {
+        const int r = t / (kTW / kQ), c0 = (t % (kTW / kQ)) * kQ;
+        if constexpr (kProducts) {
+            // the five SSIM moments of x (src) and y (src2)
+            float u[kIn], v[kIn];
+#pragma unroll
+            for (int i = 0; i < kIn; i++) {
+                u[i] = src[0][r][c0 + i];
+                v[i] = src[1][r][c0 + i];
+            }
+#pragma unroll
+            for (int o = 0; o < kQ; o++) {
+                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+#pragma unroll
+                for (int j = 0; j < 11; j++) {
+                    const float uj = u[o + j], vj = v[o + j], wj = win.g[j];
+                    a0 += wj * uj;
+                    a1 += wj * vj;
+                    a2 += wj * uj * uj;
+                    a3 += wj * vj * vj;
+                    a4 += wj * uj * vj;
+                }
+                dst[0][r][c0 + o] = a0;
+                dst[1][r][c0 + o] = a1;
+                dst[2][r][c0 + o] = a2;
+                dst[3][r][c0 + o] = a3;
+                dst[4][r][c0 + o] = a4;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < NM; m++) {
+                float u[kIn];
+#pragma unroll
+                for (int i = 0; i < kIn; i++) u[i] = src[m][r][c0 + i];
+#pragma unroll
+                for (int o = 0; o < kQ; o++) {
+                    float a = 0.f;
+#pragma unroll
+                    for (int j = 0; j < 11; j++) a += win.g[j] * u[o + j];
+                    dst[m][r][c0 + o] = a;
+                }
+            }
+        }
+    }
+}
+
+// column filter of map m: outputs rows 4 g .. 4 g + 3 of column c
+__device__ __forceinline__ void col_filter(const Win& win, const float (*src)[kTW + 1], int g, int c, float out[kQ]) {
+    float u[kIn];
+#pragma unroll
+    for (int i = 0; i < kIn; i++) u[i] = src[kQ * g + i][c];
+#pragma unroll
+    for (int o = 0; o < kQ; o++) {
+        float a = 0.f;
+#pragma unroll
+        for (int j = 0; j < 11; j++) a += win.g[j] * u[o + j];
+        out[o] = a;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, const float* __restrict__ y, int H,
                                                   int W, Win win, float* __restrict__ maps, double* __restrict__ bsum) {
-    __shared__ float sx[kH][kH + 1];
-    __shared__ float sy[kH][kH + 1];
-    __shared__ float sh[5][kH][kT + 1];
+    __shared__ float s_img[2][kHH][kHW + 1];   // x, y halo tiles
+    __shared__ float sh[5][kHH][kTW + 1];
+    __shared__ float s_w[2][4];
     const int ch = blockIdx.z;
     const int bx = blockIdx.x, by = blockIdx.y;
     const int64_t P = (int64_t)H * W;
     const float* xc = x + ch * P;
     const float* yc = y + ch * P;
-    for (int k = threadIdx.x; k < kH * kH; k += 256) {
-        const int r = k / kH, c = k % kH;
-        const int gy = by * kT + r - kR, gx = bx * kT + c - kR;
+    for (int k = threadIdx.x; k < kHH * kHW; k += 256) {
+        const int r = k / kHW, c = k % kHW;
+        const int gy = by * kTH + r - kR, gx = bx * kTW + c - kR;
         const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-        sx[r][c] = in ? xc[(int64_t)gy * W + gx] : 0.f;
-        sy[r][c] = in ? yc[(int64_t)gy * W + gx] : 0.f;
+        s_img[0][r][c] = in ? xc[(int64_t)gy * W + gx] : 0.f;
+        s_img[1][r][c] = in ? yc[(int64_t)gy * W + gx] : 0.f;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < kH * kT; k += 256) {
-        const int r = k / kT, c = k % kT;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+    row_filter<5, true>(win, s_img, sh);
+    __syncthreads();
+    const int c = threadIdx.x % kTW, g = threadIdx.x / kTW;
+    float mx[kQ], my[kQ], exx[kQ], eyy[kQ], exy[kQ];
+    col_filter(win, sh[0], g, c, mx);
+    col_filter(win, sh[1], g, c, my);
+    col_filter(win, sh[2], g, c, exx);
+    col_filter(win, sh[3], g, c, eyy);
+    col_filter(win, sh[4], g, c, exy);
+    const int gx = bx * kTW + c;
+    const int64_t N = 3 * P;
+    float s_sum = 0.f, l1 = 0.f;
 #pragma unroll
-        for (int j = 0; j < 11; j++) {
-            const float u = sx[r][c + j], v = sy[r][c + j], wj = win.g[j];
-            a0 += wj * u;
-            a1 += wj * v;
-            a2 += wj * u * u;
-            a3 += wj * v * v;
-            a4 += wj * u * v;
+    for (int o = 0; o < kQ; o++) {
+        const int r = kQ * g + o;
+        const int gy = by * kTH + r;
+        if (gy < H && gx < W) {
+            const float sxx = exx[o] - mx[o] * mx[o], syy = eyy[o] - my[o] * my[o], sxy = exy[o] - mx[o] * my[o];
+            const float a1 = 2.f * mx[o] * my[o] + kC1, a2 = 2.f * sxy + kC2;
+            const float b1 = mx[o] * mx[o] + my[o] * my[o] + kC1, b2 = sxx + syy + kC2;
+            const float ib = 1.0f / (b1 * b2);
+            const float S = a1 * a2 * ib;
+            const float dS_da1 = a2 * ib, dS_da2 = a1 * ib, dS_db1 = -S / b1, dS_db2 = -S / b2;
+            const float d_mx = 2.f * my[o] * (dS_da1 - dS_da2) + 2.f * mx[o] * (dS_db1 - dS_db2);
+            const int64_t p = ch * P + (int64_t)gy * W + gx;
+            maps[p] = d_mx;
+            maps[N + p] = dS_db2;
+            maps[2 * N + p] = 2.f * dS_da2;
+            s_sum += S;
+            l1 += fabsf(s_img[0][r + kR][c + kR] - s_img[1][r + kR][c + kR]);
         }
-        sh[0][r][c] = a0; sh[1][r][c] = a1; sh[2][r][c] = a2; sh[3][r][c] = a3; sh[4][r][c] = a4;
+    }
+    // block sums: float within a wave, double across the four waves
+    for (int off = 32; off > 0; off >>= 1) {
+        l1 += __shfl_xor(l1, off, 64);
+        s_sum += __shfl_xor(s_sum, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_w[0][w] = l1;
+        s_w[1][w] = s_sum;
     }
     __syncthreads();
-    const int r = threadIdx.x / kT, c = threadIdx.x % kT;
-    float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
-#pragma unroll
-    for (int j = 0; j < 11; j++) {
-        const float wj = win.g[j];
-        mx += wj * sh[0][r + j][c];
-        my += wj * sh[1][r + j][c];
-        exx += wj * sh[2][r + j][c];
-        eyy += wj * sh[3][r + j][c];
-        exy += wj * sh[4][r + j][c];
+    if (threadIdx.x == 0) {
+        const int64_t blk = ((int64_t)ch * gridDim.y + by) * gridDim.x + bx;
+        bsum[2 * blk] = ((double)s_w[0][0] + (double)s_w[0][1]) + ((double)s_w[0][2] + (double)s_w[0][3]);
+        bsum[2 * blk + 1] = ((double)s_w[1][0] + (double)s_w[1][1]) + ((double)s_w[1][2] + (double)s_w[1][3]);
     }
-    const int gy = by * kT + r, gx = bx * kT + c;
-    double s_sum = 0.0, l1 = 0.0;
-    if (gy < H && gx < W) {
-        const float sxx = exx - mx * mx, syy = eyy - my * my, sxy = exy - mx * my;
-        const float a1 = 2.f * mx * my + kC1, a2 = 2.f * sxy + kC2;
-        const float b1 = mx * mx + my * my + kC1, b2 = sxx + syy + kC2;
-        const float ib = 1.0f / (b1 * b2);
-        const float S = a1 * a2 * ib;
-        const float dS_da1 = a2 * ib, dS_da2 = a1 * ib, dS_db1 = -S / b1, dS_db2 = -S / b2;
-        const float d_mx = 2.f * my * (dS_da1 - dS_da2) + 2.f * mx * (dS_db1 - dS_db2);
-        const int64_t p = ch * P + (int64_t)gy * W + gx;
-        const int64_t N = 3 * P;
-        maps[p] = d_mx;
-        maps[N + p] = dS_db2;
-        maps[2 * N + p] = 2.f * dS_da2;
-        s_sum = S;
-        l1 = fabsf(sx[r + kR][c + kR] - sy[r + kR][c + kR]);
-    }
-    const int64_t blk = ((int64_t)ch * gridDim.y + by) * gridDim.x + bx;
-    block_sum2(l1, s_sum, bsum + 2 * blk);
 }
 
 __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, const float* __restrict__ y, int H,
                                                   int W, Win win, float lam, const float* __restrict__ maps,
                                                   float* __restrict__ d) {
-    __shared__ float sm[3][kH][kH + 1];
-    __shared__ float sh[3][kH][kT + 1];
+    __shared__ float sm[3][kHH][kHW + 1];
+    __shared__ float sh[3][kHH][kTW + 1];
     const int ch = blockIdx.z;
     const int bx = blockIdx.x, by = blockIdx.y;
     const int64_t P = (int64_t)H * W, N = 3 * P;
-    for (int k = threadIdx.x; k < kH * kH; k += 256) {
-        const int r = k / kH, c = k % kH;
-        const int gy = by * kT + r - kR, gx = bx * kT + c - kR;
+    for (int k = threadIdx.x; k < kHH * kHW; k += 256) {
+        const int r = k / kHW, c = k % kHW;
+        const int gy = by * kTH + r - kR, gx = bx * kTW + c - kR;
         const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
         const int64_t p = ch * P + (int64_t)gy * W + gx;
         sm[0][r][c] = in ? maps[p] : 0.f;
@@ -140,34 +215,24 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, c
         sm[2][r][c] = in ? maps[2 * N + p] : 0.f;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < kH * kT; k += 256) {
-        const int r = k / kT, c = k % kT;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-#pragma unroll
-        for (int j = 0; j < 11; j++) {
-            const float wj = win.g[j];
-            a0 += wj * sm[0][r][c + j];
-            a1 += wj * sm[1][r][c + j];
-            a2 += wj * sm[2][r][c + j];
-        }
-        sh[0][r][c] = a0; sh[1][r][c] = a1; sh[2][r][c] = a2;
-    }
+    row_filter<3, false>(win, sm, sh);
     __syncthreads();
-    const int r = threadIdx.x / kT, c = threadIdx.x % kT;
-    const int gy = by * kT + r, gx = bx * kT + c;
-    if (gy >= H || gx >= W) return;
-    float fm = 0.f, fe = 0.f, ff = 0.f;
-#pragma unroll
-    for (int j = 0; j < 11; j++) {
-        const float wj = win.g[j];
-        fm += wj * sh[0][r + j][c];
-        fe += wj * sh[1][r + j][c];
-        ff += wj * sh[2][r + j][c];
-    }
-    const int64_t p = ch * P + (int64_t)gy * W + gx;
-    const float xv = x[p], yv = y[p];
+    const int c = threadIdx.x % kTW, g = threadIdx.x / kTW;
+    float fm[kQ], fe[kQ], ff[kQ];
+    col_filter(win, sh[0], g, c, fm);
+    col_filter(win, sh[1], g, c, fe);
+    col_filter(win, sh[2], g, c, ff);
+    const int gx = bx * kTW + c;
     const float invN = 1.0f / (float)N;
-    d[p] = (1.f - lam) * sgnf(xv - yv) * invN - lam * invN * (fm + 2.f * xv * fe + yv * ff);
+#pragma unroll
+    for (int o = 0; o < kQ; o++) {
+        const int gy = by * kTH + kQ * g + o;
+        if (gy < H && gx < W) {
+            const int64_t p = ch * P + (int64_t)gy * W + gx;
+            const float xv = x[p], yv = y[p];
+            d[p] = (1.f - lam) * sgnf(xv - yv) * invN - lam * invN * (fm[o] + 2.f * xv * fe[o] + yv * ff[o]);
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_loss_finalize(const double* __restrict__ bsum, int64_t nblk, int64_t N,
@@ -224,7 +289,7 @@ Win make_window() {
 int64_t loss_map_floats(int H, int W) { return 3 * 3 * (int64_t)H * W; }
 
 int loss_blocks(int H, int W) {
-    const int a = 3 * ((W + kT - 1) / kT) * ((H + kT - 1) / kT);
+    const int a = 3 * ((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH);
     const int b = (int)((3 * (int64_t)H * W + 255) / 256);
     return a > b ? a : b;
 }
@@ -240,7 +305,7 @@ void loss_forward_backward(const Launch& L, const float* x, const float* y, int 
                            nonfinite);
     } else {
         const Win win = make_window();
-        dim3 grid((W + kT - 1) / kT, (H + kT - 1) / kT, 3);
+        dim3 grid((W + kTW - 1) / kTW, (H + kTH - 1) / kTH, 3);
         hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, L.st, x, y, H, W, win, w.partial_maps, w.block_sums);
         hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, L.st, x, y, H, W, win, lambda, w.partial_maps, d_image);
         const int64_t nblk = (int64_t)grid.x * grid.y * grid.z;
