@@ -598,15 +598,16 @@ __global__ __launch_bounds__(256) void k_csr_weights(NtcDev nd, const float* __r
     pw[k] = make_uint2(c, __float_as_uint(wt[corner]));
 }
 
-// 8 lanes per table entry: the entry's (point, weight) contributions are
-// read 8 at a time (coalesced, one 8-byte load each), each lane gathers its
+// 16 lanes per table entry: the entry's (point, weight) contributions are
+// read 16 at a time (coalesced, one 8-byte load each), each lane gathers its
 // point's encoding gradient, and the group sums with DPP (pairs, quads,
-// half-row mirror): fixed order.
+// half-row and row mirror): fixed order.
+constexpr int kGatherLanes = 16;
 __global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ rows, const uint2* __restrict__ pw,
                                                     const float* __restrict__ denc, int64_t n, int64_t entries,
                                                     float* __restrict__ g_table) {
-    const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 3;
-    const int sub = threadIdx.x & 7;
+    const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kGatherLanes;
+    const int sub = threadIdx.x % kGatherLanes;
     uint2 r = make_uint2(0u, 0u);
     if (e < entries) r = rows[e];
     float a0 = 0.f, a1 = 0.f;
@@ -615,9 +616,10 @@ __global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ ro
     };
     uint32_t k = r.x + sub;
     // four independent contribution loads in flight per lane; the sum keeps
-    // the order k, k + 8, k + 16, ...
-    for (; k + 24 < r.y; k += 32) {
-        const uint2 c0 = pw[k], c1 = pw[k + 8], c2 = pw[k + 16], c3 = pw[k + 24];
+    // the order k, k + 16, k + 32, ...
+    constexpr int G = kGatherLanes;
+    for (; k + 3 * G < r.y; k += 4 * G) {
+        const uint2 c0 = pw[k], c1 = pw[k + G], c2 = pw[k + 2 * G], c3 = pw[k + 3 * G];
         const float2 d0 = enc(c0.x), d1 = enc(c1.x), d2 = enc(c2.x), d3 = enc(c3.x);
         const float w0 = __uint_as_float(c0.y), w1 = __uint_as_float(c1.y);
         const float w2 = __uint_as_float(c2.y), w3 = __uint_as_float(c3.y);
@@ -630,19 +632,21 @@ __global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ ro
         a0 += w3 * d3.x;
         a1 += w3 * d3.y;
     }
-    for (; k < r.y; k += 8) {
+    for (; k < r.y; k += G) {
         const uint2 c = pw[k];
         const float2 d = enc(c.x);
         const float wk = __uint_as_float(c.y);
         a0 += wk * d.x;
         a1 += wk * d.y;
     }
-    a0 = dpp_add<0xB1, 0xF>(a0);
-    a0 = dpp_add<0x4E, 0xF>(a0);
-    a0 = dpp_add<0x141, 0xF>(a0);
+    a0 = dpp_add<0xB1, 0xF>(a0);    // quad_perm [1,0,3,2]
+    a0 = dpp_add<0x4E, 0xF>(a0);    // quad_perm [2,3,0,1]
+    a0 = dpp_add<0x141, 0xF>(a0);   // row_half_mirror
+    a0 = dpp_add<0x140, 0xF>(a0);   // row_mirror: lane 0 of the row holds the sum
     a1 = dpp_add<0xB1, 0xF>(a1);
     a1 = dpp_add<0x4E, 0xF>(a1);
     a1 = dpp_add<0x141, 0xF>(a1);
+    a1 = dpp_add<0x140, 0xF>(a1);
     if (sub == 0 && e < entries && r.y > r.x) {
         g_table[2 * e] += a0;
         g_table[2 * e + 1] += a1;
@@ -769,7 +773,7 @@ void bwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* 
                            (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, csr->denc);
         if (L.prof) L.prof->end(L.st);
         if (L.prof) L.prof->begin("ntc_scatter", L.st);
-        hipLaunchKernelGGL(k_csr_gather, dim3(nblk(csr->entries * 8, 256)), dim3(256), 0, L.st, csr->rows, csr->pw,
+        hipLaunchKernelGGL(k_csr_gather, dim3(nblk(csr->entries * kGatherLanes, 256)), dim3(256), 0, L.st, csr->rows, csr->pw,
                            csr->denc, n, csr->entries, g_table);
     } else {
         hipLaunchKernelGGL((k_ntc_bwd<P, false>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
