@@ -520,8 +520,10 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
             const int r = radix_sort_u32(L, c->dkeys, c->dvals, n, 32, c->radix_hist, c->scan_tmp);
             const uint32_t* order = c->dvals[r];
             const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
-            scan_u32_to_u64(L, sl.count, n, sl.goff, c->goff_total, c->scan_tmp);
             const bool rec_mode = c->grec_cap > 0;
+            // first pair slot of each Gaussian: only the record mode's
+            // gradient gather needs it
+            if (rec_mode) scan_u32_to_u64(L, sl.count, n, sl.goff, c->goff_total, c->scan_tmp);
             bin_gather(L, order, n, sl.rect, sl.count, sl.goff, cap, c->bin_rect, rec_mode ? c->bin_goff : nullptr);
             bin_count(L, order, n, c->bin_rect, cd.tiles_x, cd.tiles_y, c->bin_hist);
             scan_u32_to_u64(L, c->bin_hist, (int64_t)ntiles * nchunks, c->bin_base, sl.total, c->scan_tmp);

@@ -140,19 +140,71 @@ __global__ __launch_bounds__(256) void k_bin_gather(const uint32_t* __restrict__
     }
 }
 
-template <bool kScatter>
+// Counting pass of the depth-first binning: for a tile row (one wave) and a
+// chunk of depth-ordered Gaussians, how many of the chunk's Gaussians have a
+// tile rectangle covering each tile of the row.  Every covering Gaussian
+// adds +1 at its first column and -1 past its last to an LDS difference
+// array; a prefix sum over the row's columns gives the counts (the same
+// coverage test the scatter applies tile by tile).
+__global__ __launch_bounds__(kBinThreads) void k_bin_count(const uint2* __restrict__ srect, int64_t n, int tiles_x,
+                                                           int tiles_y, int64_t nchunks, uint32_t* __restrict__ hist) {
+    __shared__ uint2 s_rect[kBinChunk];
+    __shared__ int s_diff[kBinRowsPerBlock][kMaxTilesX + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int row = (int)blockIdx.y * kBinRowsPerBlock + w;
+    const int64_t chunk = blockIdx.x;
+    const int64_t e0 = chunk * kBinChunk;
+    const int m = (int)min((int64_t)kBinChunk, n - e0);
+    for (int e = threadIdx.x; e < m; e += kBinThreads) s_rect[e] = srect[e0 + e];
+    for (int k = lane; k <= kMaxTilesX; k += 64) s_diff[w][k] = 0;
+    __syncthreads();
+    if (row >= tiles_y) return;
+    for (int e = lane; e < m; e += 64) {
+        const uint2 r = s_rect[e];
+        if ((int)(r.x >> 16) <= row && row <= (int)(r.y >> 16)) {
+            atomicAdd(&s_diff[w][r.x & 0xFFFFu], 1);
+            atomicAdd(&s_diff[w][(r.y & 0xFFFFu) + 1u], -1);
+        }
+    }
+    // the wave's atomics are done before its reads below (LDS operations of
+    // one wave complete in order); lane l takes columns 4 l .. 4 l + 3
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int a[4];
+    int t = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        t += s_diff[w][4 * lane + k];
+        a[k] = t;
+    }
+    int x = t;   // inclusive scan of the lane totals
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    const int pre = x - t;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int tx = 4 * lane + k;
+        if (tx < tiles_x) hist[((int64_t)row * tiles_x + tx) * nchunks + chunk] = (uint32_t)(pre + a[k]);
+    }
+}
+
+// Scatter pass: each wave walks the chunk's Gaussians covering its tile row
+// in depth order; lane l keeps the output cursors of tile columns l, l + 64,
+// ... in registers, starting at the slots the scan of the counts gave.
 __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __restrict__ order, int64_t n,
                                                   const uint2* __restrict__ srect, const uint32_t* __restrict__ sgoff,
                                                   int tiles_x, int tiles_y, int64_t nchunks,
-                                                  uint32_t* __restrict__ hist, const uint64_t* __restrict__ base,
-                                                  uint32_t cap, uint32_t* __restrict__ vals,
-                                                  uint32_t* __restrict__ gpos) {
+                                                  const uint64_t* __restrict__ base, uint32_t cap,
+                                                  uint32_t* __restrict__ vals, uint32_t* __restrict__ gpos) {
     // A cursor starts at min(first slot, cap) and moves at most kBinChunk
     // past it, so with cap < 2^31 it never wraps; slots at or past cap are
     // not written.
     __shared__ uint2 s_rect[kBinChunk];
     __shared__ uint32_t s_id[kBinChunk];
-    __shared__ uint32_t s_goff[kScatter ? kBinChunk : 1];
+    __shared__ uint32_t s_goff[kBinChunk];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int rg = (int)blockIdx.y;
     const int64_t chunk = blockIdx.x;
@@ -162,14 +214,14 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __rest
     for (int e = threadIdx.x; e < m; e += kBinThreads) {
         s_id[e] = order[e0 + e];
         s_rect[e] = srect[e0 + e];
-        if (kScatter) s_goff[e] = gpos ? sgoff[e0 + e] : 0u;
+        s_goff[e] = gpos ? sgoff[e0 + e] : 0u;
     }
     uint32_t cur[kBinColSlots];
 #pragma unroll
     for (int k = 0; k < kBinColSlots; k++) {
         const int tx = k * 64 + lane;
         cur[k] = 0u;
-        if (kScatter && row < tiles_y && tx < tiles_x) {
+        if (row < tiles_y && tx < tiles_x) {
             const uint64_t b = base[((int64_t)row * tiles_x + tx) * nchunks + chunk];
             cur[k] = b < (uint64_t)cap ? (uint32_t)b : cap;
         }
@@ -189,30 +241,20 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __rest
             mask &= mask - 1;
             const uint2 r = s_rect[eb + j];
             const int tx0 = (int)(r.x & 0xFFFF), tx1 = (int)(r.y & 0xFFFF);
-            uint32_t idj = 0u, k0 = 0u;
-            if (kScatter) {
-                idj = s_id[eb + j];
-                // slot of this Gaussian's first tile of this row in its own pair range
-                k0 = s_goff[eb + j] + (uint32_t)((row - (int)(r.x >> 16)) * (tx1 - tx0 + 1));
-            }
+            const uint32_t idj = s_id[eb + j];
+            // slot of this Gaussian's first tile of this row in its own pair range
+            const uint32_t k0 = s_goff[eb + j] + (uint32_t)((row - (int)(r.x >> 16)) * (tx1 - tx0 + 1));
 #pragma unroll
             for (int k = 0; k < kBinColSlots; k++) {
                 const int tx = k * 64 + lane;
                 if (tx < tx0 || tx > tx1) continue;
                 const uint32_t pos = cur[k]++;
-                if (kScatter && pos < cap) {
+                if (pos < cap) {
                     vals[pos] = idj;
                     const uint32_t kk = k0 + (uint32_t)(tx - tx0);
                     if (gpos && kk < cap) gpos[kk] = pos;
                 }
             }
-        }
-    }
-    if (!kScatter) {
-#pragma unroll
-        for (int k = 0; k < kBinColSlots; k++) {
-            const int tx = k * 64 + lane;
-            if (tx < tiles_x) hist[((int64_t)row * tiles_x + tx) * nchunks + chunk] = cur[k];
         }
     }
 }
@@ -851,9 +893,8 @@ void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* s
     const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_count", L.st);
-    hipLaunchKernelGGL((k_bin_rows<false>), bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, order, n, srect, (const uint32_t*)nullptr,
-                       tiles_x, tiles_y, nchunks, hist, (const uint64_t*)nullptr, 0u, (uint32_t*)nullptr,
-                       (uint32_t*)nullptr);
+    hipLaunchKernelGGL(k_bin_count, bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, srect, n, tiles_x, tiles_y,
+                       nchunks, hist);
     if (L.prof) L.prof->end(L.st);
 }
 
@@ -862,8 +903,8 @@ void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2*
     const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_scatter", L.st);
-    hipLaunchKernelGGL((k_bin_rows<true>), bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, order, n, srect, sgoff, tiles_x, tiles_y,
-                       nchunks, (uint32_t*)nullptr, base, (uint32_t)cap, vals, gpos);
+    hipLaunchKernelGGL(k_bin_rows, bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, order, n, srect, sgoff,
+                       tiles_x, tiles_y, nchunks, base, (uint32_t)cap, vals, gpos);
     if (L.prof) L.prof->end(L.st);
 }
 
