@@ -191,9 +191,14 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const uint2* __restri
     }
 }
 
-// Scatter pass: each wave walks the chunk's Gaussians covering its tile row
-// in depth order; lane l keeps the output cursors of tile columns l, l + 64,
-// ... in registers, starting at the slots the scan of the counts gave.
+// Scatter pass, one wave per (tile row, chunk of depth-ordered Gaussians):
+// the wave lists the chunk's Gaussians covering its row in depth order with
+// the prefix of their column counts, then writes the row's pairs 64 at a
+// time, lane = pair.  A lane finds its Gaussian by binary search in the
+// prefix; lanes of one batch that share a tile column are ranked by lane
+// (eight ballots on the column bits), so every tile's entries keep the depth
+// order, and per-column cursors in LDS, starting at the slots the scan of the
+// counts gave, carry the ranks across batches.
 __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __restrict__ order, int64_t n,
                                                   const uint2* __restrict__ srect, const uint32_t* __restrict__ sgoff,
                                                   int tiles_x, int tiles_y, int64_t nchunks,
@@ -205,10 +210,12 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __rest
     __shared__ uint2 s_rect[kBinChunk];
     __shared__ uint32_t s_id[kBinChunk];
     __shared__ uint32_t s_goff[kBinChunk];
+    __shared__ uint32_t s_cur[kBinRowsPerBlock][kMaxTilesX];   // per-column cursors of each wave's row
+    __shared__ uint16_t s_gl[kBinRowsPerBlock][kBinChunk];      // covering Gaussians (chunk positions)
+    __shared__ uint32_t s_wp[kBinRowsPerBlock][kBinChunk];      // exclusive prefix of their column counts
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int rg = (int)blockIdx.y;
+    const int row = (int)blockIdx.y * kBinRowsPerBlock + w;
     const int64_t chunk = blockIdx.x;
-    const int row = rg * kBinRowsPerBlock + w;
     const int64_t e0 = chunk * kBinChunk;
     const int m = (int)min((int64_t)kBinChunk, n - e0);
     for (int e = threadIdx.x; e < m; e += kBinThreads) {
@@ -216,46 +223,81 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __rest
         s_rect[e] = srect[e0 + e];
         s_goff[e] = gpos ? sgoff[e0 + e] : 0u;
     }
-    uint32_t cur[kBinColSlots];
-#pragma unroll
-    for (int k = 0; k < kBinColSlots; k++) {
-        const int tx = k * 64 + lane;
-        cur[k] = 0u;
-        if (row < tiles_y && tx < tiles_x) {
+    if (row < tiles_y) {
+        for (int tx = lane; tx < tiles_x; tx += 64) {
             const uint64_t b = base[((int64_t)row * tiles_x + tx) * nchunks + chunk];
-            cur[k] = b < (uint64_t)cap ? (uint32_t)b : cap;
+            s_cur[w][tx] = b < (uint64_t)cap ? (uint32_t)b : cap;
         }
     }
     __syncthreads();
     if (row >= tiles_y) return;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;   // lanes under this one
+    // 1. the covering Gaussians in depth order and the prefix of their widths
+    int G = 0;
+    uint32_t P = 0;
     for (int eb = 0; eb < m; eb += 64) {
         const int e = eb + lane;
-        bool covers = false;
+        uint32_t wd = 0u;
         if (e < m) {
             const uint2 r = s_rect[e];
-            covers = (int)(r.x >> 16) <= row && row <= (int)(r.y >> 16);
+            if ((int)(r.x >> 16) <= row && row <= (int)(r.y >> 16)) wd = (r.y & 0xFFFFu) - (r.x & 0xFFFFu) + 1u;
         }
-        uint64_t mask = __ballot(covers);
-        while (mask) {
-            const int j = __ffsll((unsigned long long)mask) - 1;
-            mask &= mask - 1;
-            const uint2 r = s_rect[eb + j];
-            const int tx0 = (int)(r.x & 0xFFFF), tx1 = (int)(r.y & 0xFFFF);
-            const uint32_t idj = s_id[eb + j];
-            // slot of this Gaussian's first tile of this row in its own pair range
-            const uint32_t k0 = s_goff[eb + j] + (uint32_t)((row - (int)(r.x >> 16)) * (tx1 - tx0 + 1));
-#pragma unroll
-            for (int k = 0; k < kBinColSlots; k++) {
-                const int tx = k * 64 + lane;
-                if (tx < tx0 || tx > tx1) continue;
-                const uint32_t pos = cur[k]++;
-                if (pos < cap) {
-                    vals[pos] = idj;
-                    const uint32_t kk = k0 + (uint32_t)(tx - tx0);
-                    if (gpos && kk < cap) gpos[kk] = pos;
-                }
+        const uint64_t cov = __ballot(wd != 0u);
+        uint32_t x = wd;   // inclusive scan of the widths
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (wd) {
+            const int k = G + __popcll(cov & below);
+            s_gl[w][k] = (uint16_t)e;
+            s_wp[w][k] = P + x - wd;
+        }
+        G += __popcll(cov);
+        P += __shfl(x, 63, 64);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // 2. the row's P pairs, 64 per round
+    for (uint32_t q0 = 0; q0 < P; q0 += 64) {
+        const uint32_t q = q0 + (uint32_t)lane;
+        const bool valid = q < P;
+        uint32_t tx = 0xFFFFFFFFu, id = 0u, kk = 0u;
+        if (valid) {
+            int lo = 0, hi = G - 1;   // last g with s_wp[g] <= q
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_wp[w][mid] <= q) lo = mid; else hi = mid - 1;
             }
+            const int e = s_gl[w][lo];
+            const uint2 r = s_rect[e];
+            const uint32_t tx0 = r.x & 0xFFFFu, tx1 = r.y & 0xFFFFu;
+            const uint32_t d = q - s_wp[w][lo];
+            tx = tx0 + d;
+            id = s_id[e];
+            // slot of this pair in its Gaussian's own pair range
+            kk = s_goff[e] + (uint32_t)(row - (int)(r.x >> 16)) * (tx1 - tx0 + 1u) + d;
         }
+        // lanes of this round with the same tile column
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; bit++) {
+            const bool set = (tx >> bit) & 1u;
+            const uint64_t bal = __ballot(set);
+            peers &= set ? bal : ~bal;
+        }
+        if (valid) {
+            const uint32_t pos = s_cur[w][tx] + (uint32_t)__popcll(peers & below);
+            if (pos < cap) {
+                vals[pos] = id;
+                if (gpos && kk < cap) gpos[kk] = pos;
+            }
+            if ((peers >> lane) >> 1 == 0ull) s_cur[w][tx] = pos + 1u;   // the column's last lane this round
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
