@@ -30,15 +30,30 @@ __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x, int lane) {
     return x;
 }
 
+// A thread's kItems consecutive inputs: two 16-byte loads when they are all
+// in range and the array is 16-byte aligned, else one by one.
+__device__ __forceinline__ void load8(const uint32_t* __restrict__ in, int64_t base, int64_t n, uint32_t v[kItems]) {
+    if (base + kItems <= n && ((reinterpret_cast<uintptr_t>(in) & 15u) == 0)) {
+        const uint4 a = *reinterpret_cast<const uint4*>(in + base);
+        const uint4 b = *reinterpret_cast<const uint4*>(in + base + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kItems; k++) v[k] = base + k < n ? in[base + k] : 0u;
+    }
+}
+
 template <typename Tin>
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const Tin* __restrict__ in, int64_t n,
                                                           uint64_t* __restrict__ bsum) {
     __shared__ uint64_t s_w[kThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
+    uint32_t v[kItems];
+    load8(in, base, n, v);
     uint64_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; k++)
-        if (base + k < n) s += (uint64_t)in[base + k];
+    for (int k = 0; k < kItems; k++) s += (uint64_t)v[k];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -79,23 +94,37 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const Tin* __restrict__ 
     __shared__ uint64_t s_w[kThreads / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
-    uint64_t v[kItems];
+    uint32_t v[kItems];
+    load8(in, base, n, v);
     uint64_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; k++) {
-        v[k] = base + k < n ? (uint64_t)in[base + k] : 0;
-        s += v[k];
-    }
+    for (int k = 0; k < kItems; k++) s += (uint64_t)v[k];
     uint64_t x = wave_incl_scan(s, lane);
     if (lane == 63) s_w[w] = x;
     __syncthreads();
     uint64_t pre = bpre[blockIdx.x];
     for (int k = 0; k < w; k++) pre += s_w[k];
     uint64_t run = pre + x - s;
+    Tout o[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; k++) {
-        if (base + k < n) out[base + k] = (Tout)run;
+        o[k] = (Tout)run;
         run += v[k];
+    }
+    if (base + kItems <= n && ((reinterpret_cast<uintptr_t>(out) & 15u) == 0)) {
+        // 16-byte stores of the thread's consecutive outputs
+        constexpr int kPer = 16 / (int)sizeof(Tout);
+#pragma unroll
+        for (int k = 0; k < kItems; k += kPer) {
+            if constexpr (sizeof(Tout) == 8)
+                *reinterpret_cast<ulonglong2*>(out + base + k) = make_ulonglong2(o[k], o[k + 1]);
+            else
+                *reinterpret_cast<uint4*>(out + base + k) = make_uint4(o[k], o[k + 1], o[k + 2], o[k + 3]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kItems; k++)
+            if (base + k < n) out[base + k] = o[k];
     }
 }
 
