@@ -662,8 +662,17 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ 
     if (k >= len) return;
     const int b0 = blockIdx.y * kPartSlice;
     const int b1 = min(b0 + kPartSlice, nparts);
+    // eight loads in flight, summed in order
     float s = 0.f;
-    for (int b = b0; b < b1; b++) s += part[(int64_t)b * len + k];
+    int b = b0;
+    for (; b + 8 <= b1; b += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = part[(int64_t)(b + u) * len + k];
+#pragma unroll
+        for (int u = 0; u < 8; u++) s += v[u];
+    }
+    for (; b < b1; b++) s += part[(int64_t)b * len + k];
     atomicAdd(dst + k, s);
 }
 

@@ -241,3 +241,31 @@ def test_morton_reorder_is_a_sorted_permutation_and_keeps_the_image():
     if len(np.unique(keys)) == len(keys):      # distinct depths: same compositing order
         assert torch.equal(a, b)
     ctx.close()
+
+
+def test_profiler_counts_launches_and_filters_by_kernel():
+    """HIP-event profiling: every launch is counted while on; restricted to
+    one kernel, only that kernel's launches are timed; off, nothing is."""
+    g, cam, _, _ = _scene("small-2k-64px", 3, False)
+    ctx = make_ctx(g.n, cam)
+    gg = _gs3().GaussiansGPU.from_host(g)
+    ctx.render(gg, cam)
+    ctx.profile(True)
+    ctx.profile_reset()
+    for _ in range(3):
+        ctx.render(gg, cam)
+    for k in ("preprocess_fwd", "blend_fwd"):
+        ms, cnt = ctx.profile_query(k)
+        assert cnt == 3 and ms > 0.0, (k, ms, cnt)
+    ctx.profile_only("blend_fwd")
+    ctx.profile_reset()
+    for _ in range(2):
+        ctx.render(gg, cam)
+    assert ctx.profile_query("blend_fwd")[1] == 2
+    assert ctx.profile_query("preprocess_fwd")[1] == 0
+    ctx.profile(False)
+    ctx.profile_only(None)
+    ctx.profile_reset()
+    ctx.render(gg, cam)
+    assert ctx.profile_query("blend_fwd")[1] == 0
+    ctx.close()
