@@ -24,22 +24,31 @@ struct EventProfiler : Profiler {
     std::vector<Rec> pending;
     std::vector<Rec> open;
     std::map<std::string, std::pair<double, int64_t>> totals;
+    // profiling is best effort: a launch whose events cannot be created or
+    // recorded is simply not timed
     hipEvent_t take() {
         hipEvent_t e = nullptr;
         if (!pool.empty()) {
             e = pool.back();
             pool.pop_back();
-        } else {
-            hipEventCreate(&e);
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
         }
         return e;
+    }
+    void give(hipEvent_t e) {
+        if (e) pool.push_back(e);
     }
     void begin(const char* name, hipStream_t st) override {
         Rec r{name, nullptr, nullptr};
         if (only.empty() || only == name) {
             r.a = take();
             r.b = take();
-            hipEventRecord(r.a, st);
+            if (!r.a || !r.b || hipEventRecord(r.a, st) != hipSuccess) {
+                give(r.a);
+                give(r.b);
+                r.a = r.b = nullptr;
+            }
         }
         open.push_back(r);
     }
@@ -48,25 +57,29 @@ struct EventProfiler : Profiler {
         Rec r = open.back();
         open.pop_back();
         if (!r.a) return;
-        hipEventRecord(r.b, st);
+        if (hipEventRecord(r.b, st) != hipSuccess) {
+            give(r.a);
+            give(r.b);
+            return;
+        }
         pending.push_back(r);
     }
     void collect() {
         for (auto& r : pending) {
-            hipEventSynchronize(r.b);
             float ms = 0.f;
-            hipEventElapsedTime(&ms, r.a, r.b);
-            auto& t = totals[r.name];
-            t.first += ms;
-            t.second += 1;
-            pool.push_back(r.a);
-            pool.push_back(r.b);
+            if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                auto& t = totals[r.name];
+                t.first += ms;
+                t.second += 1;
+            }
+            give(r.a);
+            give(r.b);
         }
         pending.clear();
     }
     ~EventProfiler() override {
         collect();
-        for (auto e : pool) hipEventDestroy(e);
+        for (auto e : pool) (void)hipEventDestroy(e);
     }
 };
 
@@ -253,7 +266,13 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
         }
         c->n_table_floats = off * 2;
         c->n_params = c->n_table_floats + ntc_mlp_params();
-        c->max_parts = 512;   // one workgroup per CU pair: the backward loops over its point batches
+        // one NTC-backward workgroup per CU (its registers allow one per CU);
+        // each loops over its share of the point batches in a single round
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        c->max_parts = cus;
         ok = c->alloc(&c->p, c->n_params) && c->alloc(&c->g, c->n_params) && c->alloc(&c->m, c->n_params) &&
              c->alloc(&c->v, c->n_params) && c->alloc((float**)&c->work, c->n_params) &&
              c->alloc(&c->g_part, (int64_t)c->max_parts * ntc_mlp_params()) && c->alloc(&c->warm_bsum, (N + 255) / 256);
@@ -280,9 +299,10 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
 
 void gs3_destroy(gs3_ctx* ctx) {
     if (!ctx) return;
-    hipDeviceSynchronize();
-    for (void* p : ctx->allocs) hipFree(p);
-    for (void* p : ctx->csr_allocs) hipFree(p);
+    // teardown has no caller to report to: errors here are dropped
+    (void)hipStreamSynchronize(ctx->st);
+    for (void* p : ctx->allocs) (void)hipFree(p);
+    for (void* p : ctx->csr_allocs) (void)hipFree(p);
     delete ctx;
 }
 
@@ -394,8 +414,8 @@ gs3_status gs3_ntc_prepare(gs3_ctx* c, const float* means, int64_t n) {
     c->csr_n = -1;
     const int64_t m = n * 128;
     if (n > c->csr_cap) {
-        hipDeviceSynchronize();
-        for (void* p : c->csr_allocs) hipFree(p);
+        if (hipStreamSynchronize(c->st) != hipSuccess) return c->fail(GS3_EHIP, "ntc_prepare: sync failed");
+        for (void* p : c->csr_allocs) (void)hipFree(p);
         c->csr_bytes = 0;
         c->csr_allocs.clear();
         auto get = [&](void** out, size_t bytes) {
@@ -413,7 +433,7 @@ gs3_status gs3_ntc_prepare(gs3_ctx* c, const float* means, int64_t n) {
                   get((void**)&c->csr.rows, entries * 8) && get((void**)&c->csr.pw, m * 8) &&
                   get((void**)&c->csr.denc, n * 32 * 4);
         if (!ok) {
-            for (void* p : c->csr_allocs) hipFree(p);
+            for (void* p : c->csr_allocs) (void)hipFree(p);
             c->csr_allocs.clear();
             c->csr_cap = 0;
             return c->fail(GS3_ENOMEM, "ntc_prepare: allocation failed");
@@ -515,7 +535,8 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
     if (c->cfg.sort_mode == GS3_SORT_DEPTH_FIRST) {
         sl.cur = 0;
         if (n > 0) {
-            hipMemcpyAsync(c->dkeys[0], sl.key, (size_t)n * 4, hipMemcpyDeviceToDevice, c->st);
+            if (hipMemcpyAsync(c->dkeys[0], sl.key, (size_t)n * 4, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+                return c->fail(GS3_EHIP, "render: copying the depth keys failed");
             iota_u32(L, c->dvals[0], n);
             const int r = radix_sort_u32(L, c->dkeys, c->dvals, n, 32, c->radix_hist, c->scan_tmp);
             const uint32_t* order = c->dvals[r];

@@ -124,7 +124,6 @@ __global__ __launch_bounds__(256) void k_ranges_from_keys(const uint64_t* __rest
 #endif
 constexpr int kBinRowsPerBlock = GS3_BIN_ROWS;   // one wave per tile row
 constexpr int kBinThreads = 64 * kBinRowsPerBlock;
-constexpr int kBinColSlots = kMaxTilesX / 64;   // register cursors per lane
 
 __global__ __launch_bounds__(256) void k_bin_gather(const uint32_t* __restrict__ order, int64_t n,
                                                     const uint2* __restrict__ rect, const uint32_t* __restrict__ count,
