@@ -531,7 +531,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
     __shared__ float4 s_w1[NT];
     __shared__ float4 s_w2[NT];   // blend_stage_w2 form
     __shared__ uint32_t s_id[NT];
-    __shared__ float s_g[NW][9][NT];   // per-wave sums, [wave][term][entry]
+    __shared__ float s_g[NW][9][NT + 1];   // per-wave sums, [wave][term][entry] (padded: term rows on distinct banks)
     const int tile = order ? order[blockIdx.x] : tile_of_block(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const uint32_t maxlast = tile_walk[tile];
@@ -648,23 +648,37 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
             if (kOpacity && lane == 8) s_g[wv][5][j] = redop;
         }
         __syncthreads();
-        if ((int)threadIdx.x < cnt) {
-            const uint32_t widx = woff + (uint32_t)jb + threadIdx.x;   // compact index of this walked entry
-            const bool fits = kRecords && widx < grec_cap;
+        if (kRecords) {
+            if ((int)threadIdx.x < cnt) {
+                const uint32_t widx = woff + (uint32_t)jb + threadIdx.x;   // compact index of this walked entry
+                const bool fits = widx < grec_cap;
 #pragma unroll
-            for (int k = 0; k < 9; k++) {
-                if (!kOpacity && k == 5) {
-                    if (fits) grec[(int64_t)k * grec_cap + widx] = 0.f;
-                    continue;
+                for (int k = 0; k < 9; k++) {
+                    if (!kOpacity && k == 5) {
+                        if (fits) grec[(int64_t)k * grec_cap + widx] = 0.f;
+                        continue;
+                    }
+                    float v = s_g[0][k][threadIdx.x];
+#pragma unroll
+                    for (int w = 1; w < NW; w++) v += s_g[w][k][threadIdx.x];
+                    v *= kConicScale[k];
+                    if (fits)
+                        grec[(int64_t)k * grec_cap + widx] = v;
+                    else if (v != 0.f)
+                        atomicAdd(accum + 9 * (int64_t)s_id[threadIdx.x] + k, v);
                 }
-                float v = s_g[0][k][threadIdx.x];
+            }
+        } else {
+            // lane = (entry, term): the atomics of one entry's terms are
+            // adjacent lanes on adjacent addresses (one or two cache lines)
+            for (int q = threadIdx.x; q < 9 * cnt; q += NT) {
+                const int e = q / 9, k = q - 9 * e;
+                if (!kOpacity && k == 5) continue;
+                float v = s_g[0][k][e];
 #pragma unroll
-                for (int w = 1; w < NW; w++) v += s_g[w][k][threadIdx.x];
+                for (int w = 1; w < NW; w++) v += s_g[w][k][e];
                 v *= kConicScale[k];
-                if (fits)
-                    grec[(int64_t)k * grec_cap + widx] = v;
-                else if (v != 0.f)
-                    atomicAdd(accum + 9 * (int64_t)s_id[threadIdx.x] + k, v);
+                if (v != 0.f) atomicAdd(accum + 9 * (int64_t)s_id[e] + k, v);
             }
         }
         __syncthreads();
