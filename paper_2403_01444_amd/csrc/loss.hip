@@ -167,9 +167,11 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, c
             const float sxx = exx[o] - mx[o] * mx[o], syy = eyy[o] - my[o] * my[o], sxy = exy[o] - mx[o] * my[o];
             const float a1 = 2.f * mx[o] * my[o] + kC1, a2 = 2.f * sxy + kC2;
             const float b1 = mx[o] * mx[o] + my[o] * my[o] + kC1, b2 = sxx + syy + kC2;
-            const float ib = 1.0f / (b1 * b2);
+            // hardware reciprocal (1 ulp; b1 b2 >= C1 C2 is a normal number);
+            // 1 / b1 = b2 ib and 1 / b2 = b1 ib
+            const float ib = __builtin_amdgcn_rcpf(b1 * b2);
             const float S = a1 * a2 * ib;
-            const float dS_da1 = a2 * ib, dS_da2 = a1 * ib, dS_db1 = -S / b1, dS_db2 = -S / b2;
+            const float dS_da1 = a2 * ib, dS_da2 = a1 * ib, dS_db1 = -S * (b2 * ib), dS_db2 = -S * (b1 * ib);
             const float d_mx = 2.f * my[o] * (dS_da1 - dS_da2) + 2.f * mx[o] * (dS_db1 - dS_db2);
             const int64_t p = ch * P + (int64_t)gy * W + gx;
             maps[p] = d_mx;
