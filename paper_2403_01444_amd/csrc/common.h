@@ -390,29 +390,17 @@ __device__ __forceinline__ void blend_dx_terms(float dx, const float4& w0, float
     bdx = w0.w * dx;
 }
 
-// Branch-free form for the blend loops: the exponent and whether it passes
-// the cheap part of the test (0 = reject, 1 = accept, 2 = needs the exact
-// test near the threshold).
+// The exponent in the decision procedure's order; the blend loops compare
+// it with 0 and with the band edges pthr -/+ 1e-4 themselves.
 __device__ __forceinline__ float blend_power(float adx2, float bdx, float dy, float C) {
 #pragma clang fp contract(off)
     return -0.5f * (adx2 + C * dy * dy) - bdx * dy;
 }
 
+// the exact opacity test, for exponents inside the band
 __device__ __forceinline__ bool blend_exact_test(float power, float opacity) {
 #pragma clang fp contract(off)
     return opacity * spec_exp(power) >= 1.0f / 255.0f;
-}
-
-__device__ __forceinline__ bool blend_alpha_dy(float adx2, float bdx, float dy, const float4& w1, float pthr,
-                                               float& G, float& raw, float& alpha) {
-#pragma clang fp contract(off)
-    const float power = -0.5f * (adx2 + w1.x * dy * dy) - bdx * dy;
-    if (power > 0.0f || power < pthr - 1e-4f) return false;
-    if (power < pthr + 1e-4f && !(w1.y * spec_exp(power) >= 1.0f / 255.0f)) return false;
-    G = __expf(power);
-    raw = w1.y * G;
-    alpha = fminf(0.99f, raw);
-    return true;
 }
 
 // bits lo..hi of a 16-bit span, clipped to 0..15 (0 when empty)
@@ -437,10 +425,6 @@ __device__ __forceinline__ float4 blend_stage_w2(const float4& w2, int tx0p, int
 }
 
 // wave64 helpers
-__device__ __forceinline__ float wave_sum(float v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 template <int kCtrl, int kRowMask>
 __device__ __forceinline__ float dpp_add(float x) {
