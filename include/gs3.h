@@ -189,7 +189,9 @@ gs3_status gs3_ntc_forward(gs3_ctx* ctx, const float* means, int64_t n, float* d
 
 /* Accumulate into the context's float32 gradient buffers the gradient of
  * <d_dmu, dmu> + <d_dq, dq> for the same means (adjoint of Eq. 5: MLP
- * backward, then the hash-table scatter-add). */
+ * backward, then the hash-table scatter-add).  On the means of the last
+ * gs3_ntc_prepare, the encoding that the last gs3_ntc_forward on them
+ * computed is reused when no gs3_ntc_step or gs3_ntc_load came in between. */
 gs3_status gs3_ntc_backward(gs3_ctx* ctx, const float* means, int64_t n,
                             const float* d_dmu, const float* d_dq);
 
@@ -201,7 +203,7 @@ gs3_status gs3_ntc_backward(gs3_ctx* ctx, const float* means, int64_t n,
  * (no atomics, fixed order).  The caller guarantees that the contents of
  * `means` do not change until the next gs3_ntc_prepare; a call with another
  * pointer or n uses the atomic scatter.  Allocates device memory on first
- * use or growth (about 3.2 KB per mean) and synchronises. */
+ * use or growth (about 3.3 KB per mean) and synchronises. */
 gs3_status gs3_ntc_prepare(gs3_ctx* ctx, const float* means, int64_t n);
 
 /* One Adam step on the NTC parameters with the accumulated gradients,

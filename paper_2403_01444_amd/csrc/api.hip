@@ -146,6 +146,8 @@ struct gs3_ctx {
     int max_parts = 0;
     double* warm_bsum = nullptr;
     // per-frame contribution lists of the table gradient
+    void* enc_cache = nullptr;   // encoding of the prepared means from the last forward (n x 32)
+    bool enc_valid = false;      // it matches the current parameters
     NtcCsr csr;
     const float* csr_means = nullptr;
     int64_t csr_n = -1, csr_cap = 0;
@@ -359,6 +361,7 @@ gs3_status gs3_ntc_load(gs3_ctx* c, const float* host_params, int64_t n) {
     fill_f32(L, c->v, 0.f, n);
     ntc_refresh_work(L, c->cfg.ntc.precision, c->p, c->work, n);
     c->step = 0;
+    c->enc_valid = false;
     if (hipStreamSynchronize(c->st) != hipSuccess) return c->fail(GS3_EHIP, "ntc_load: sync failed");
     return c->check_launch("ntc_load");
 }
@@ -389,7 +392,11 @@ gs3_status gs3_ntc_forward(gs3_ctx* c, const float* means, int64_t n, float* dmu
     if (n < 0 || (n > 0 && (!means || !dmu || !dq))) return c->fail(GS3_EINVAL, "ntc_forward: bad arguments");
     const void *table, *mlp;
     ntc_ptrs(c, &table, &mlp);
-    ntc_forward(c->L(), c->cfg.ntc.precision, c->nd, table, mlp, means, n, dmu, dq);
+    // on the prepared means the forward keeps the encoding for the backward
+    const bool prepared = n > 0 && means == c->csr_means && n == c->csr_n;
+    ntc_forward(c->L(), c->cfg.ntc.precision, c->nd, table, mlp, means, n, dmu, dq,
+                prepared ? c->enc_cache : nullptr);
+    if (prepared) c->enc_valid = true;
     return c->check_launch("ntc_forward");
 }
 
@@ -401,7 +408,8 @@ gs3_status gs3_ntc_backward(gs3_ctx* c, const float* means, int64_t n, const flo
     ntc_ptrs(c, &table, &mlp);
     const bool prepared = means == c->csr_means && n == c->csr_n;
     ntc_backward(c->L(), c->cfg.ntc.precision, c->nd, table, mlp, means, n, d_dmu, d_dq, c->g,
-                 c->g + c->n_table_floats, c->g_part, c->max_parts, prepared ? &c->csr : nullptr);
+                 c->g + c->n_table_floats, c->g_part, c->max_parts, prepared ? &c->csr : nullptr,
+                 prepared && c->enc_valid ? c->enc_cache : nullptr);
     return c->check_launch("ntc_backward");
 }
 
@@ -412,6 +420,7 @@ gs3_status gs3_ntc_prepare(gs3_ctx* c, const float* means, int64_t n) {
         return c->fail(GS3_EINVAL, "ntc_prepare: bad arguments");
     c->csr_means = nullptr;
     c->csr_n = -1;
+    c->enc_valid = false;
     const int64_t m = n * 128;
     if (n > c->csr_cap) {
         if (hipStreamSynchronize(c->st) != hipSuccess) return c->fail(GS3_EHIP, "ntc_prepare: sync failed");
@@ -431,7 +440,7 @@ gs3_status gs3_ntc_prepare(gs3_ctx* c, const float* means, int64_t n) {
                   get((void**)&c->csr_hist, radix_hist_words(m) * 4) &&
                   get((void**)&c->csr_tmp, (scan_tmp_words(radix_hist_words(m)) + 4) * 8) &&
                   get((void**)&c->csr.rows, entries * 8) && get((void**)&c->csr.pw, m * 8) &&
-                  get((void**)&c->csr.denc, n * 32 * 4);
+                  get((void**)&c->csr.denc, n * 32 * 4) && get(&c->enc_cache, n * 32 * 4);
         if (!ok) {
             for (void* p : c->csr_allocs) (void)hipFree(p);
             c->csr_allocs.clear();
@@ -454,6 +463,7 @@ gs3_status gs3_ntc_step(gs3_ctx* c, float lr, float beta1, float beta2, float ep
     if (!c) return GS3_EINVAL;
     if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
     c->step += 1;
+    c->enc_valid = false;
     const float bc1 = (float)(1.0 - pow((double)beta1, (double)c->step));
     const float bc2 = (float)(1.0 - pow((double)beta2, (double)c->step));
     ntc_adam(c->L(), c->cfg.ntc.precision, c->p, c->g, c->m, c->v, c->work, c->n_params, lr, beta1, beta2, eps, bc1,

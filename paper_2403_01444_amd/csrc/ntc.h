@@ -27,12 +27,16 @@ int ntc_mlp_params();
 // keys/vals: two ping-pong buffers of n * 128 u32 each; hist: radix_hist_words(n * 128)
 void ntc_csr_build(const Launch& L, const NtcDev& nd, const float* means, int64_t n, NtcCsr& csr, uint32_t* keys[2],
                    uint32_t* vals[2], uint32_t* hist, uint64_t* tmp);
+// enc_out (optional, n x 32 values of the working precision): the forward
+// also stores each point's encoding there
 void ntc_forward(const Launch& L, int precision, const NtcDev& nd, const void* table, const void* mlp,
-                 const float* means, int64_t n, float* dmu, float* dq);
-// g_part holds max_parts x ntc_mlp_params() floats
+                 const float* means, int64_t n, float* dmu, float* dq, void* enc_out);
+// g_part holds max_parts x ntc_mlp_params() floats; enc_in (optional): the
+// encoding a forward with the same parameters and means stored, used instead
+// of recomputing it
 void ntc_backward(const Launch& L, int precision, const NtcDev& nd, const void* table, const void* mlp,
                   const float* means, int64_t n, const float* d_dmu, const float* d_dq, float* g_table, float* g_mlp,
-                  float* g_part, int max_parts, const NtcCsr* csr);
+                  float* g_part, int max_parts, const NtcCsr* csr, const void* enc_in);
 void ntc_adam(const Launch& L, int precision, float* p, float* g, float* m, float* v, void* work, int64_t n, float lr,
               float b1, float b2, float eps, float bc1, float bc2);
 void ntc_refresh_work(const Launch& L, int precision, const float* p, void* work, int64_t n);

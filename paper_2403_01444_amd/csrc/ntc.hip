@@ -227,10 +227,24 @@ __device__ __forceinline__ void encode_lane(const NtcDev& nd, const typename P::
     }
 }
 
+// A lane's eight encoding values (levels 4 g .. 4 g + 3) of point pt:
+// LDS row X[p] <-> the cached encoding enc[pt][8 g .. 8 g + 7].
+template <class P>
+__device__ __forceinline__ void enc_to_cache(const typename P::S* X, int p, int g, typename P::S* enc, int64_t pt) {
+#pragma unroll
+    for (int j = 0; j < 8; j++) enc[pt * 32 + 8 * g + j] = X[p * LD32 + 8 * g + j];
+}
+template <class P>
+__device__ __forceinline__ void enc_from_cache(typename P::S* X, int p, int g, const typename P::S* enc, int64_t pt) {
+#pragma unroll
+    for (int j = 0; j < 8; j++) X[p * LD32 + 8 * g + j] = enc[pt * 32 + 8 * g + j];
+}
+
 template <class P>
 __global__ __launch_bounds__(256) void k_ntc_fwd(NtcDev nd, const typename P::S* __restrict__ table,
                                                  const typename P::S* __restrict__ mlp, const float* __restrict__ means,
-                                                 int64_t n, float* __restrict__ dmu, float* __restrict__ dq) {
+                                                 int64_t n, float* __restrict__ dmu, float* __restrict__ dq,
+                                                 typename P::S* __restrict__ enc_out) {
     using S = typename P::S;
     __shared__ S sW1[64 * LD32], sW2[64 * LD64], sW3[16 * LD64];
     __shared__ S sX[kWaves][kPts * LD32], sH1[kWaves][kPts * LD64], sH2[kWaves][kPts * LD64];
@@ -258,6 +272,7 @@ __global__ __launch_bounds__(256) void k_ntc_fwd(NtcDev nd, const typename P::S*
             for (int j = 0; j < 8; j++) X[p * LD32 + 8 * g + j] = P::cvt(0.f);
         }
         wave_sync();
+        if (enc_out && valid) enc_to_cache<P>(X, p, g, enc_out, pt);   // kept for the backward
 #pragma unroll
         for (int mt = 0; mt < 4; mt++) {
             const f4v a = layer_tile<P, 32>(sW1, LD32, mt * 16, X, LD32, lane);
@@ -312,7 +327,8 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
                                                  const typename P::S* __restrict__ mlp, const float* __restrict__ means,
                                                  int64_t n, const float* __restrict__ d_dmu,
                                                  const float* __restrict__ d_dq, float* __restrict__ g_table,
-                                                 float* __restrict__ g_part, float* __restrict__ denc) {
+                                                 float* __restrict__ g_part, float* __restrict__ denc,
+                                                 const typename P::S* __restrict__ enc_in) {
     using S = typename P::S;
     constexpr int kWElems = 64 * LD32 + 64 * LD64 + 32 * LD64 + 64 * LD64 + 64 * LD16;
     constexpr int kWBytes = (int)sizeof(S) * kWElems > kMlpParams * 4 ? (int)sizeof(S) * kWElems : kMlpParams * 4;
@@ -358,8 +374,10 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
             in = ntc_normalise(nd, mu, x);
         }
         wave_sync();
-        // 1. encoding
-        if (in) {
+        // 1. encoding: the forward's, when it kept it, else recomputed
+        if (enc_in && valid) {
+            enc_from_cache<P>(X, p, g, enc_in, pt);
+        } else if (in) {
             encode_lane<P>(nd, table, x, g, X, p);
         } else {
             for (int j = 0; j < 8; j++) X[p * LD32 + 8 * g + j] = P::cvt(0.f);
@@ -764,29 +782,31 @@ inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per
 
 template <class P>
 void fwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* mlp, const float* means, int64_t n,
-              float* dmu, float* dq) {
+              float* dmu, float* dq, void* enc_out) {
     const int64_t nb = (n + kPts - 1) / kPts;
     const unsigned grid = (unsigned)std::min<int64_t>((nb + kWaves - 1) / kWaves, 2048);
     hipLaunchKernelGGL((k_ntc_fwd<P>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
-                       (const typename P::S*)mlp, means, n, dmu, dq);
+                       (const typename P::S*)mlp, means, n, dmu, dq, (typename P::S*)enc_out);
 }
 
 template <class P>
 void bwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* mlp, const float* means, int64_t n,
               const float* d_dmu, const float* d_dq, float* g_table, float* g_mlp, float* g_part, int max_parts,
-              const NtcCsr* csr) {
+              const NtcCsr* csr, const void* enc_in) {
     const int64_t nb = (n + kPts - 1) / kPts;
     const unsigned grid = (unsigned)std::min<int64_t>((nb + kWaves - 1) / kWaves, max_parts);
     if (csr) {
         hipLaunchKernelGGL((k_ntc_bwd<P, true>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
-                           (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, csr->denc);
+                           (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, csr->denc,
+                           (const typename P::S*)enc_in);
         if (L.prof) L.prof->end(L.st);
         if (L.prof) L.prof->begin("ntc_scatter", L.st);
         hipLaunchKernelGGL(k_csr_gather, dim3(nblk(csr->entries * kGatherLanes, 256)), dim3(256), 0, L.st, csr->rows, csr->pw,
                            csr->denc, n, csr->entries, g_table);
     } else {
         hipLaunchKernelGGL((k_ntc_bwd<P, false>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
-                           (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, (float*)nullptr);
+                           (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, (float*)nullptr,
+                           (const typename P::S*)enc_in);
     }
     hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(kMlpParams, 256), (grid + kPartSlice - 1) / kPartSlice), dim3(256), 0,
                        L.st, g_part, (int)grid, kMlpParams, g_mlp);
@@ -797,29 +817,29 @@ void bwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* 
 int ntc_mlp_params() { return kMlpParams; }
 
 void ntc_forward(const Launch& L, int precision, const NtcDev& nd, const void* table, const void* mlp,
-                 const float* means, int64_t n, float* dmu, float* dq) {
+                 const float* means, int64_t n, float* dmu, float* dq, void* enc_out) {
     if (n <= 0) return;
     if (L.prof) L.prof->begin("ntc_fwd", L.st);
     if (precision == 1)
-        fwd_impl<PF16>(L, nd, table, mlp, means, n, dmu, dq);
+        fwd_impl<PF16>(L, nd, table, mlp, means, n, dmu, dq, enc_out);
     else if (precision == 2)
-        fwd_impl<PBF16>(L, nd, table, mlp, means, n, dmu, dq);
+        fwd_impl<PBF16>(L, nd, table, mlp, means, n, dmu, dq, enc_out);
     else
-        fwd_impl<PF32>(L, nd, table, mlp, means, n, dmu, dq);
+        fwd_impl<PF32>(L, nd, table, mlp, means, n, dmu, dq, enc_out);
     if (L.prof) L.prof->end(L.st);
 }
 
 void ntc_backward(const Launch& L, int precision, const NtcDev& nd, const void* table, const void* mlp,
                   const float* means, int64_t n, const float* d_dmu, const float* d_dq, float* g_table, float* g_mlp,
-                  float* g_part, int max_parts, const NtcCsr* csr) {
+                  float* g_part, int max_parts, const NtcCsr* csr, const void* enc_in) {
     if (n <= 0) return;
     if (L.prof) L.prof->begin("ntc_bwd", L.st);
     if (precision == 1)
-        bwd_impl<PF16>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts, csr);
+        bwd_impl<PF16>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts, csr, enc_in);
     else if (precision == 2)
-        bwd_impl<PBF16>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts, csr);
+        bwd_impl<PBF16>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts, csr, enc_in);
     else
-        bwd_impl<PF32>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts, csr);
+        bwd_impl<PF32>(L, nd, table, mlp, means, n, d_dmu, d_dq, g_table, g_mlp, g_part, max_parts, csr, enc_in);
     if (L.prof) L.prof->end(L.st);
 }
 

@@ -164,3 +164,29 @@ def test_prepared_backward_is_deterministic_and_accumulates():
     c = ctx.ntc_grads().cpu().numpy()
     assert rel_err(c, 2 * b.astype(np.float64)) < 1e-5
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16", "bf16"])
+def test_backward_reuses_the_forward_encoding(precision):
+    """On prepared means the backward takes the encoding the forward kept;
+    after ntc_load (same parameters) it recomputes it: same gradients, the
+    table part bit for bit (fixed summation order)."""
+    cfg = synth.NTCConfig()
+    params, spec = trained_like_params(cfg, 6)
+    n = 30000
+    rng = np.random.default_rng(11)
+    means = cuda(rng.uniform(-1.3, 1.3, size=(n, 3)).astype(np.float32))
+    gm, gq = cuda(rng.normal(size=(n, 3)).astype(np.float32)), cuda(rng.normal(size=(n, 4)).astype(np.float32))
+    ctx = ntc_ctx(cfg, n, precision)
+    ctx.ntc_load(params)
+    ctx.ntc_prepare(means)
+    ctx.ntc_forward(means)
+    ctx.ntc_backward(means, gm, gq)          # encoding from the forward
+    a = ctx.ntc_grads().cpu().numpy()
+    ctx.ntc_load(params)                     # same parameters; the kept encoding is dropped
+    ctx.ntc_backward(means, gm, gq)          # encoding recomputed
+    b = ctx.ntc_grads().cpu().numpy()
+    t = spec.n_table
+    assert np.array_equal(a[:t], b[:t])
+    assert rel_err(a[t:], b[t:].astype(np.float64)) < 1e-5
+    ctx.close()
