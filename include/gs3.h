@@ -184,7 +184,9 @@ gs3_status gs3_ntc_load(gs3_ctx* ctx, const float* host_params, int64_t n);
 gs3_status gs3_ntc_save(gs3_ctx* ctx, float* host_params, int64_t cap);
 
 /* (dmu, dq) = MLP(h(mu)) for n means (n x 3) -> dmu (n x 3), dq (n x 4).
- * Means outside the AABB get the identity (0, (1,0,0,0)) (Suppl. Sec. A). */
+ * Means outside the AABB get the identity (0, (1,0,0,0)) (Suppl. Sec. A).
+ * On the means of the last gs3_ntc_prepare the context also keeps each
+ * point's encoding h(mu) for the next gs3_ntc_backward on them. */
 gs3_status gs3_ntc_forward(gs3_ctx* ctx, const float* means, int64_t n, float* dmu, float* dq);
 
 /* Accumulate into the context's float32 gradient buffers the gradient of
