@@ -40,21 +40,63 @@ def _signature(g, cam, dmu, dq):
     return pre["visible"].tobytes() + pre["box"].tobytes() + r["n_contrib"].tobytes(), r
 
 
-def test_adjoint_matches_central_differences():
-    g, cam, dmu, dq = fd_scene()
-    rng = np.random.default_rng(1)
+def clamp_scene(n=24, size=32, seed=0, sh_degree=3, frac=0.5):
+    """Scene whose first frac * n Gaussians sit beyond 1.3 x the half-FOV
+    tangent in x or y (camera space), where the EWA Jacobian takes the
+    clamped coordinate (reading C4), and are large enough that their pixel
+    boxes still reach into the image."""
+    rng = np.random.default_rng(seed)
+    g = synth.make_gaussians(n, sh_degree, seed)
+    cam = synth.look_at_camera(size, size, bg=(0.1, 0.2, 0.3))
+    W = np.asarray(cam.world_to_cam, np.float64)
+    R, t = W[:, :3], W[:, 3]
+    lim = 0.5 * size / cam.fx
+    z = rng.uniform(2.6, 3.4, size=n)
+    xy = rng.uniform(-0.5, 0.5, size=(n, 2)) * lim * z[:, None]
+    k = int(round(frac * n))
+    ax = np.arange(k) % 2                        # every (axis, side) case appears
+    sg = np.where((np.arange(k) // 2) % 2, 1.0, -1.0)
+    off = rng.uniform(1.35, 1.6, size=k) * lim
+    for i in range(k):
+        xy[i, ax[i]] = sg[i] * off[i] * z[i]
+    tc = np.concatenate([xy, z[:, None]], 1)
+    g.means[:] = ((tc - t) @ R).astype(np.float32)
+    ls = rng.normal(-2.2, 0.2, size=(n, 3))
+    ls[:k] = rng.normal(-1.0, 0.15, size=(k, 3))
+    g.log_scales[:] = ls.astype(np.float32)
+    g.opacity_logits[:] = rng.uniform(-1.0, 1.5, size=n).astype(np.float32)
+    dc = rng.uniform(0.25, 0.75, size=(n, 3))
+    g.sh[:, 0, :] = ((dc - 0.5) / (0.5 / math.sqrt(math.pi))).astype(np.float32)
+    dmu = (rng.normal(size=(n, 3)) * 0.02).astype(np.float32)
+    dq = (np.array([1, 0, 0, 0]) + rng.normal(size=(n, 4)) * 0.2).astype(np.float32)
+    return g, cam, dmu, dq
+
+
+def clamped_mask(g, cam, dmu):
+    """Gaussians whose camera-space x/z or y/z lies beyond 1.3 x the half-FOV
+    tangent and that are visible (their box reaches the image)."""
+    W = np.asarray(cam.world_to_cam, np.float64)
+    tc = (g.means.astype(np.float64) + dmu) @ W[:, :3].T + W[:, 3]
+    clx = np.abs(tc[:, 0] / tc[:, 2]) > 1.3 * 0.5 * cam.width / cam.fx
+    cly = np.abs(tc[:, 1] / tc[:, 2]) > 1.3 * 0.5 * cam.height / cam.fy
+    return (clx | cly) & orc.preprocess(g, cam, dmu, None)["visible"].astype(bool)
+
+
+def _check_central_differences(g, cam, dmu, dq, seed, per_key=60, min_checked=300, only=None):
+    rng = np.random.default_rng(seed)
     w = rng.normal(size=(3, cam.height, cam.width))
     grads = orc.render_backward(g, cam, w, dmu, dq)
     sig0, _ = _signature(g, cam, dmu, dq)
     h = 1e-4
     checked = 0
-    worst = 0.0
     for key in GRAD_KEYS:
         arr = _arrays(g, dmu, dq)[key]
         flat = arr.reshape(-1)
         gflat = grads["d_" + key].reshape(-1)
         scale = np.abs(gflat).max() + 1e-30
-        for j in rng.choice(flat.size, size=min(flat.size, 60), replace=False):
+        rows = np.arange(flat.size) // (flat.size // g.n)
+        pool = np.arange(flat.size) if only is None else np.nonzero(only[rows])[0]
+        for j in rng.choice(pool, size=min(pool.size, per_key), replace=False):
             x0 = flat[j]
             flat[j] = np.float32(x0 + h)
             sp, rp = _signature(g, cam, dmu, dq)
@@ -67,10 +109,24 @@ def test_adjoint_matches_central_differences():
                 continue   # a discrete decision moved: no derivative there
             fd = float(np.sum(w * (rp["image"] - rm["image"]))) / (xp - xm)
             err = abs(fd - gflat[j]) / scale
-            worst = max(worst, err)
             assert err < 1e-5, (key, j, fd, gflat[j])
             checked += 1
-    assert checked > 300, checked
+    assert checked > min_checked, checked
+
+
+def test_adjoint_matches_central_differences():
+    g, cam, dmu, dq = fd_scene()
+    _check_central_differences(g, cam, dmu, dq, 1)
+
+
+def test_adjoint_matches_central_differences_with_clamped_jacobian():
+    """Half the Gaussians beyond the J clamp (reading C4): the forward takes
+    the clamped coordinate and the adjoint has no term through it.  The
+    components checked belong to the clamped Gaussians only."""
+    g, cam, dmu, dq = clamp_scene(seed=3)
+    cl = clamped_mask(g, cam, dmu)
+    assert cl.sum() >= g.n // 3, cl.sum()
+    _check_central_differences(g, cam, dmu, dq, 4, only=cl, min_checked=250)
 
 
 # ---------------------------------------------------------------------------
@@ -181,3 +237,27 @@ def test_adjoint_matches_torch_autograd():
         a = t[k].grad.numpy()
         b = grads["d_" + k]
         np.testing.assert_allclose(b, a, atol=1e-10 * (1 + np.abs(a).max()), err_msg=k)
+
+
+def test_adjoint_matches_torch_autograd_with_clamped_jacobian():
+    """The independent renderer clamps x/z and y/z with torch.clamp, whose
+    gradient through a clamped coordinate is zero: the oracle's image and
+    adjoint agree on a scene where a third or more of the Gaussians are
+    clamped (a dropped clamp moves both)."""
+    g, cam, dmu, dq = clamp_scene(n=12, size=24, seed=8)
+    cl = clamped_mask(g, cam, dmu)
+    assert cl.sum() >= g.n // 3, cl.sum()
+    pre = orc.preprocess(g, cam, dmu, dq)
+    t = {k: torch.tensor(np.asarray(a, np.float64), requires_grad=True) for k, a in _arrays(g, dmu, dq).items()}
+    img = torch_render(t, cam, pre)
+    ref = orc.render(g, cam, dmu, dq)
+    np.testing.assert_allclose(img.detach().numpy(), ref["image"], atol=1e-12)
+    w = np.random.default_rng(3).normal(size=img.shape)
+    (img * torch.tensor(w)).sum().backward()
+    grads = orc.render_backward(g, cam, w, dmu, dq)
+    for k in GRAD_KEYS:
+        a = t[k].grad.numpy()
+        b = grads["d_" + k]
+        np.testing.assert_allclose(b, a, atol=1e-10 * (1 + np.abs(a).max()), err_msg=k)
+        # the clamped Gaussians carry real gradient (they are not just culled)
+        assert np.abs(a[cl]).max() > 1e-6, k

@@ -47,6 +47,82 @@ def test_hash_vertex_reproduction_and_partition_of_unity(spec):
         assert rows[l].min() >= spec.offsets[l] and rows[l].max() < spec.offsets[l + 1]
 
 
+# Hashed-level indices worked by hand (instant-NGP spatial hash, T = 2^15):
+#   (1, 2, 3): 2 * 2654435761 = 5308871522 -> mod 2^32 = 1013904226;
+#              3 * 805459861 = 2416379583; 1 ^ 1013904226 ^ 2416379583 =
+#              2892625372; 2892625372 mod 32768 = 30172.
+#   (36, 0, 0): 36 (the x prime is 1).
+#   (0, 36, 0): 36 * 2654435761 mod 2^32 = 1070406884 -> 7396.
+#   (0, 0, 36): 36 * 805459861 mod 2^32 = 3226751220 -> 20724.
+HAND_HASH = {(1, 2, 3): 30172, (36, 0, 0): 36, (0, 36, 0): 7396, (0, 0, 36): 20724}
+
+
+def _hash_low_bits(v, T):
+    """The hash of a vertex mod a power-of-two T computed another way: XOR
+    and the 32-bit mask act bit by bit, so only the low log2(T) bits of each
+    product matter (Python integers, primes reduced mod T first)."""
+    return (v[0] ^ (v[1] * (2654435761 % T)) ^ (v[2] * (805459861 % T))) % T
+
+
+def _point_on_vertex(spec, level, v):
+    """A float32 mean whose lattice coordinate at `level` is the vertex v."""
+    N = spec.res[level]
+    x = (np.asarray(v, np.float64) / N) / spec.inv_ext.astype(np.float64) + spec.aabb_min
+    return x.astype(np.float32)
+
+
+@pytest.mark.parametrize("level", [3, 9, 15])
+def test_hashed_level_index_on_chosen_vertices(spec, level):
+    """Points on chosen vertices of hashed levels: the corner that carries the
+    whole weight has the hand-worked index (or, for the other vertices, the
+    low-bit form of the hash), and all 8 corners of each cell agree with the
+    low-bit form."""
+    N, T = spec.res[level], spec.T
+    assert (N + 1) ** 3 > T                      # the level is hashed
+    verts = [(1, 2, 3), (N // 2, 3, N - 1), (N - 2, N // 3, 7), (5, N - 1, N // 4)]
+    if N >= 36:
+        verts += [(36, 1, 1), (1, 36, 1), (1, 1, 36)]
+    pts = np.stack([_point_on_vertex(spec, level, v) for v in verts])
+    inside, rows, wts = ontc.corners(spec, pts)
+    assert inside.all()
+    for k, v in enumerate(verts):
+        w = wts[level][k]
+        c = int(np.argmax(w))
+        assert w[c] > 1 - 1e-3
+        got = int(rows[level][k, c] - spec.offsets[level])
+        want = HAND_HASH.get(tuple(v), _hash_low_bits(v, T))
+        assert got == want, (level, v, got, want)
+        # every corner of the cell around the point
+        p = (pts[k].astype(np.float32) - spec.aabb_min) * spec.inv_ext
+        i0 = np.minimum(np.floor(p * np.float32(N)).astype(np.int64), N - 1)
+        for cc in range(8):
+            vv = tuple(int(i0[a] + ((cc >> a) & 1)) for a in range(3))
+            assert int(rows[level][k, cc] - spec.offsets[level]) == _hash_low_bits(vv, T)
+    # the hand-worked values themselves follow from the low-bit form
+    for v, want in HAND_HASH.items():
+        assert _hash_low_bits(v, T) == want
+
+
+def test_hashed_level_collision_spread(spec):
+    """Every cell of hashed level 3 (36^3 = 46,656 lower vertices into 32,768
+    slots): the spatial hash spreads them over about two thirds of the slots
+    with bucket loads of at most 8 (measured 66.9% / 8).  A dropped y or z
+    prime piles them up (under 8% of the slots, loads of 36 and more); an
+    XOR-to-addition slip or swapped primes spread as well, and the
+    hand-worked indices above catch those."""
+    level = 3
+    N, T = spec.res[level], spec.T
+    g = np.stack(np.meshgrid(*[np.arange(N)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    # through corners(): a point at a cell centre has the cell's lower vertex as corner 0
+    pts = ((g + 0.5) / N) / spec.inv_ext.astype(np.float64) + spec.aabb_min
+    inside, rows, wts = ontc.corners(spec, pts.astype(np.float32))
+    idx = rows[level][:, 0] - spec.offsets[level]
+    assert [int(i) for i in idx[::97]] == [_hash_low_bits(tuple(int(a) for a in v), T) for v in g[::97]]
+    load = np.bincount(idx, minlength=T)
+    assert 0.6 < (load > 0).mean() < 0.75, (load > 0).mean()
+    assert load.max() <= 10, load.max()
+
+
 def test_dense_index_injective(spec):
     N = spec.res[2]
     g = np.stack(np.meshgrid(*[np.arange(N + 1)] * 3, indexing="ij"), -1).reshape(-1, 3)
