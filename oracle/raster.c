@@ -633,19 +633,25 @@ typedef struct { int64_t id; double alpha, raw, G, T, dx, dy; } contrib_t;
 /* Walk the candidates of pixel (x, y) (Eq. 4).  Returns the number of
  * contributors; fills list[] when list != NULL (capacity cap).  Which
  * Gaussians contribute is decided in single precision (spec_contributes);
- * their weights are double.  Sets *ambig when one of the two decisions that
- * still depend on single-precision values could go the other way: the 0.99
- * clamp of alpha, and the transmittance cut-off.  The margins follow from the
- * difference between the single- and double-precision exponents (which moves
- * alpha by the same relative amount), the error of a hardware exponential
- * (taken as 2e-6 relative) and rounding of the transmittance product. */
+ * their weights are double.  Two decisions still depend on values each side
+ * computes in its own precision; *ambig gets bit 0 when the 0.99 clamp of
+ * alpha is within reach of going the other way, bit 1 when the
+ * transmittance cut-off is, and bit 2 when a second cut-off decision of the
+ * same walk is.  The margins follow from the difference between the single-
+ * and double-precision exponents (which moves alpha by the same relative
+ * amount), the error of a hardware exponential (taken as 2e-6 relative) and
+ * rounding of the transmittance product.  *stop_k receives the candidate
+ * position of the first cut-off decision within reach (-1 if none); the
+ * walk takes the other outcome of the cut-off at candidate position flip_k
+ * (-1: none), which gives the pixel's alternative value. */
 static int64_t walk_pixel(const scene_t* s, int x, int y, double* T_out, double col[3],
-                          contrib_t* list, int64_t cap, int* ambig) {
+                          contrib_t* list, int64_t cap, int* ambig, int64_t flip_k, int64_t* stop_k) {
     double T = 1.0;
     double relT = 0.0;   /* bound on the relative error of a single-precision T */
     col[0] = col[1] = col[2] = 0;
     int64_t n = 0;
     *ambig = 0;
+    if (stop_k) *stop_k = -1;
     for (int64_t k = s->row_start[y]; k < s->row_start[y + 1]; k++) {
         int64_t id = s->row_ids[k];
         const spec_t* p = &s->sp[id];
@@ -659,11 +665,17 @@ static int64_t walk_pixel(const scene_t* s, int x, int y, double* T_out, double 
         double raw = q->opacity * G;
         double alpha = raw < 0.99 ? raw : 0.99;
         double e = fabs((double)power32 - power) + fabs((double)p->opacity - q->opacity) / q->opacity + 2e-6;
-        if (fabs(raw - 0.99) < 2.0 * e * 0.99) *ambig = 1;
+        if (fabs(raw - 0.99) < 2.0 * e * 0.99) *ambig |= 1;
         double Tn = T * (1.0 - alpha);
         relT += (raw < 0.99 ? alpha / (1.0 - alpha) : 0.0) * e + 3.0e-7;
-        if (fabs(Tn - 1e-4) < 2.0 * relT * 1e-4 + 1e-9) *ambig = 1;
-        if (Tn < 1e-4) break;
+        if (fabs(Tn - 1e-4) < 2.0 * relT * 1e-4 + 1e-9) {
+            if (*ambig & 2) *ambig |= 4;
+            *ambig |= 2;
+            if (stop_k && *stop_k < 0) *stop_k = k;
+        }
+        int stop = Tn < 1e-4;
+        if (k == flip_k) stop = !stop;
+        if (stop) break;
         for (int ch = 0; ch < 3; ch++) col[ch] += alpha * T * q->rgb[ch];
         if (list && n < cap) {
             list[n].id = id; list[n].alpha = alpha; list[n].raw = raw; list[n].G = G;
@@ -766,9 +778,14 @@ int64_t orc_sorted_pairs(const orc_gaussians* g, const orc_camera* c, int tile,
 }
 
 /* Forward render: image 3 x H x W (planar), final transmittance H x W,
- * contributor count H x W, ambiguity flag H x W.  Any output may be NULL. */
+ * contributor count H x W, ambiguity flags H x W (bits as in walk_pixel).
+ * image_alt / T_alt hold, where the transmittance cut-off is within reach of
+ * going the other way (bit 1), the pixel rendered with the other outcome of
+ * that decision, and the primary value elsewhere; when the alternative walk
+ * meets a further cut-off decision within reach, bit 2 is set (the two
+ * values do not cover every outcome).  Any output may be NULL. */
 int orc_render(const orc_gaussians* g, const orc_camera* c, double* image, double* T_final,
-               int32_t* n_contrib, uint8_t* ambiguous) {
+               int32_t* n_contrib, uint8_t* ambiguous, double* image_alt, double* T_alt) {
     if (!g || !c || c->width <= 0 || c->height <= 0) return -1;
     scene_t s;
     int rc = scene_build(g, c, &s);
@@ -780,11 +797,21 @@ int orc_render(const orc_gaussians* g, const orc_camera* c, double* image, doubl
         for (int x = 0; x < Wd; x++) {
             double T, col[3];
             int amb;
-            int64_t n = walk_pixel(&s, x, y, &T, col, NULL, 0, &amb);
+            int64_t stop_k;
+            int64_t n = walk_pixel(&s, x, y, &T, col, NULL, 0, &amb, -1, &stop_k);
             int64_t p = (int64_t)y * Wd + x;
-            for (int ch = 0; ch < 3; ch++)
+            double Ta = T, cola[3] = {col[0], col[1], col[2]};
+            if ((amb & 2) && (image_alt || T_alt)) {
+                int amb2;
+                walk_pixel(&s, x, y, &Ta, cola, NULL, 0, &amb2, stop_k, NULL);
+                if (amb2 & 4) amb |= 4;
+            }
+            for (int ch = 0; ch < 3; ch++) {
                 if (image) image[ch * P + p] = col[ch] + T * (double)c->bg[ch];
+                if (image_alt) image_alt[ch * P + p] = cola[ch] + Ta * (double)c->bg[ch];
+            }
             if (T_final) T_final[p] = T;
+            if (T_alt) T_alt[p] = Ta;
             if (n_contrib) n_contrib[p] = (int32_t)n;
             if (ambiguous) ambiguous[p] = (uint8_t)amb;
         }
@@ -825,12 +852,12 @@ int orc_render_backward(const orc_gaussians* g, const orc_camera* c, const doubl
             for (int x = 0; x < Wd; x++) {
                 double T, col[3];
                 int amb;
-                int64_t cnt = walk_pixel(&s, x, y, &T, col, list, cap, &amb);
+                int64_t cnt = walk_pixel(&s, x, y, &T, col, list, cap, &amb, -1, NULL);
                 if (cnt > cap) {
                     free(list);
                     cap = cnt;
                     list = malloc((size_t)cap * sizeof(contrib_t));
-                    walk_pixel(&s, x, y, &T, col, list, cap, &amb);
+                    walk_pixel(&s, x, y, &T, col, list, cap, &amb, -1, NULL);
                 }
                 int64_t p = (int64_t)y * Wd + x;
                 double gc[3] = {dl_dimg[p], dl_dimg[P + p], dl_dimg[2 * P + p]};

@@ -109,16 +109,43 @@ def sorted_pairs(g, cam, dmu=None, dq=None, tile: int = 16):
 
 
 def render(g, cam, dmu=None, dq=None) -> dict:
+    """Eq. 4 per pixel.  `ambiguous` bits: 1 the 0.99 clamp of alpha, 2 the
+    transmittance cut-off, 4 a second cut-off decision, within single-
+    precision reach of going the other way.  `image_alt` / `T_alt` are the
+    pixel with the other outcome of the cut-off decision where bit 2 is set,
+    and equal `image` / `T_final` elsewhere."""
     H, W = cam.height, cam.width
     out = dict(image=np.zeros((3, H, W)), T_final=np.zeros((H, W)), n_contrib=np.zeros((H, W), np.int32),
-               ambiguous=np.zeros((H, W), np.uint8))
+               ambiguous=np.zeros((H, W), np.uint8), image_alt=np.zeros((3, H, W)), T_alt=np.zeros((H, W)))
     p = _Pinned(g, dmu, dq)
     c = _cam(cam)
     rc = lib().orc_render(C.byref(p.s), C.byref(c), C.c_void_p(_ptr(out["image"])),
                           C.c_void_p(_ptr(out["T_final"])), C.c_void_p(_ptr(out["n_contrib"])),
-                          C.c_void_p(_ptr(out["ambiguous"])))
+                          C.c_void_p(_ptr(out["ambiguous"])), C.c_void_p(_ptr(out["image_alt"])),
+                          C.c_void_p(_ptr(out["T_alt"])))
     assert rc == 0, rc
     return out
+
+
+def image_error(img, ref: dict, T=None):
+    """Distance of a rendered image (3 x H x W) and, if given, its final
+    transmittance (H x W) from the oracle's render `ref`, per pixel, taking
+    for each pixel whichever of the two outcomes of the cut-off decision
+    (primary or alternative) fits both quantities better.  Returns
+    (image error = max over channels (H x W), transmittance error (H x W) or
+    None, mask of pixels that took the alternative, mask of pixels whose
+    outcomes the two values do not cover)."""
+    img = np.asarray(img, np.float64)
+    d0 = np.abs(img - ref["image"]).max(axis=0)
+    d1 = np.abs(img - ref["image_alt"]).max(axis=0)
+    s0, s1 = d0, d1
+    if T is not None:
+        T = np.asarray(T, np.float64)
+        t0, t1 = np.abs(T - ref["T_final"]), np.abs(T - ref["T_alt"])
+        s0, s1 = np.maximum(d0, t0), np.maximum(d1, t1)
+    use_alt = s1 < s0
+    terr = None if T is None else np.where(use_alt, t1, t0)
+    return np.where(use_alt, d1, d0), terr, use_alt, (ref["ambiguous"] & 4) != 0
 
 
 def render_backward(g, cam, dl_dimg, dmu=None, dq=None) -> dict:

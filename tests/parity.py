@@ -1,0 +1,49 @@
+"""Shared parity checks of the GPU tests against the oracle."""
+import numpy as np
+
+from oracle import raster as orc
+
+
+def check_image(img, T, ref, label, tol=1e-4):
+    """Image and final transmittance against the oracle's render, every
+    pixel: each pixel takes whichever of the oracle's two outcomes of the
+    transmittance cut-off fits it (the decision single precision can take
+    either way; elsewhere the two are equal).  Image error <= tol x the
+    largest image value, transmittance error <= tol.  Prints the measured
+    share of pixels whose cut-off was within reach, and how many took the
+    alternative; returns them."""
+    img = img.detach().cpu().numpy() if hasattr(img, "detach") else img
+    T = T.detach().cpu().numpy() if hasattr(T, "detach") else T
+    err, terr, alt, unres = orc.image_error(img, ref, T)
+    amb = (ref["ambiguous"] & 2) > 0
+    P = amb.size
+    scale = np.abs(ref["image"]).max()
+    ok = ~unres
+    e = float(err[ok].max() / scale) if ok.any() else 0.0
+    te = float(terr[ok].max()) if (ok.any() and terr is not None) else 0.0
+    print(f"[parity] {label}: cut-off within reach at {int(amb.sum())} of {P} pixels ({amb.mean():.2e}), "
+          f"{int(alt.sum())} matched the alternative, {int(unres.sum())} unresolved; "
+          f"image error {e:.2e} (bar {tol:g}), transmittance error {te:.2e}", flush=True)
+    assert not (alt & ~amb).any()
+    assert unres.sum() <= 1e-5 * P, int(unres.sum())
+    assert e <= tol, e
+    assert te <= tol, te
+    return float(amb.mean()), int(alt.sum())
+
+
+def check_grads(grads, ref, label, tol=1e-3, keys=None):
+    """Max-norm relative gradient error per tensor over every Gaussian, and
+    over the Gaussians that reach no pixel with a decision within reach;
+    the bar applies to the latter.  Prints both and the share set aside."""
+    touched = ref["touched_ambiguous"].astype(bool)
+    keep = ~touched
+    for k in keys or grads.keys():
+        v = grads[k]
+        a = v.detach().cpu().numpy().astype(np.float64) if hasattr(v, "detach") else np.asarray(v, np.float64)
+        b = ref[k]
+        s_all = max(np.abs(b).max(), 1e-30)
+        e_all = float(np.abs(a - b).max() / s_all)
+        e_keep = float(np.abs(a[keep] - b[keep]).max() / max(np.abs(b[keep]).max(), 1e-30)) if keep.any() else 0.0
+        print(f"[parity] {label} {k}: error {e_keep:.2e} over {keep.mean():.4f} of the Gaussians, "
+              f"{e_all:.2e} over all (bar {tol:g})", flush=True)
+        assert e_keep < tol, (k, e_keep)

@@ -183,3 +183,40 @@ def test_sorted_pairs_complete_and_ordered():
         s, e = ranges[t]
         assert np.all((keys[s:e] >> np.uint64(32)) == t)
     assert ranges[:, 1].max() == len(keys)
+
+
+def test_cutoff_decision_alternative_closed_form():
+    """Four layers of alpha = 0.9 on the principal point of a 33 x 33 view:
+    the transmittance after the fourth is (1 - 0.9)^4 = 1e-4, so the cut-off
+    before a Gaussian that would bring T below 1e-4 (reading C7) sits on its
+    threshold and is flagged.  The oracle's two values at that pixel are the
+    textbook sums with three and with four layers (Eq. 4), in either order."""
+    cam = synth.look_at_camera(33, 33, bg=(0.25, 0.5, 0.75))
+    cols = [(0.2, 0.5, 0.8), (0.4, 0.5, 0.7), (0.6, 0.5, 0.6), (0.8, 0.5, 0.5)]
+    gs = [single_gaussian((0.05, 0.05, 0.05), math.log(9.0), c, mean=(0, 0, -0.4 + 0.25 * i))
+          for i, c in enumerate(cols)]
+    g = synth.make_gaussians(4, 0, 0)
+    for k in ("means", "quats", "log_scales", "opacity_logits", "sh"):
+        getattr(g, k)[:] = np.concatenate([getattr(x, k) for x in gs])
+    pre = orc.preprocess(g, cam)
+    assert np.abs(pre["uv"] - [cam.cx, cam.cy]).max() < 1e-5     # centred on the pixel
+    out = orc.render(g, cam)
+    y = x = 16
+    assert out["ambiguous"][y, x] & 2 and not out["ambiguous"][y, x] & 4
+    o = np.array([1 / (1 + math.exp(-float(v))) for v in g.opacity_logits])
+    order = np.argsort(pre["depth"])                  # front to back
+    a = o[order]
+    c = np.array(cols)[order]
+    T = np.concatenate([[1.0], np.cumprod(1 - a)])
+    bg = np.asarray(cam.bg, np.float64)
+    three = sum(a[i] * T[i] * c[i] for i in range(3)) + T[3] * bg
+    four = sum(a[i] * T[i] * c[i] for i in range(4)) + T[4] * bg
+    # colours pass through float32 SH coefficients: agreement to 1e-7
+    p0, p1 = out["image"][:, y, x], out["image_alt"][:, y, x]
+    t0, t1 = out["T_final"][y, x], out["T_alt"][y, x]
+    close = lambda u, v: np.abs(np.asarray(u) - v).max() < 1e-7
+    assert (close(p0, three) and close(p1, four) and close(t0, T[3]) and close(t1, T[4])) or \
+           (close(p0, four) and close(p1, three) and close(t0, T[4]) and close(t1, T[3])), (p0, p1, three, four)
+    assert not close(three, four)
+    # a pixel away from the threshold has one value
+    assert out["ambiguous"][0, 0] == 0 and np.array_equal(out["image"][:, 0, 0], out["image_alt"][:, 0, 0])
