@@ -219,23 +219,40 @@ def stream(args):
 
 
 # Per-unit algorithmic work of each kernel.  The blend kernels are bound by
-# vector ALU work per (pixel, tile-list entry up to that pixel's last
-# contributor): operations counted from the forward and adjoint formulas of
-# Eq. 4 (add, mul, compare, min and the hardware exp each 1; a fused
-# multiply-add 2); the backward includes the 9 adds that sum each pixel's
-# contribution into the Gaussian's gradient terms.
+# vector ALU work.  The reported count is about 25 operations per evaluated
+# (pixel, tile-list entry) pair, where a tile evaluates 256 x its longest
+# walk (the 16 x 16 pixels of a tile run in lockstep up to the last
+# contributor of any of them): evaluated pairs = 256 x sum over tiles of the
+# longest walk.  The build's own per-operation counts of the two kernels'
+# formulas (29 forward, 71 backward per pixel's own walked entries: Eq. 4 and
+# its adjoint, add / mul / compare / min / exp 1, fused multiply-add 2, the
+# backward with the 9 adds into the Gaussian's gradient terms) are reported
+# beside it, never as the roofline.
+OPS_PER_EVALUATED_PAIR = 25
 BLEND_FWD_FLOP = 29
 BLEND_BWD_FLOP = 71
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+# Algorithmic HBM bytes of the rasterizer (preprocess, prefix sum, keys, sort,
+# ranges, both blends, preprocess backward) per unit: per Gaussian the
+# preprocess reads 72 + 4S and writes 52 bytes, the scan moves 8, the
+# accumulators are zeroed (36) and the preprocess backward reads 36 + 72 + 4S
+# and writes 28; per pair 52 bytes (emit 12, one sort read and write 24,
+# ranges 8, one list read in each blend 4 + 4); per pixel 20 written by the
+# forward and 20 read by the backward.  (S: SH floats per Gaussian.)
+RASTER_KERNELS = ("preprocess_fwd", "radix_pass", "bin_gather", "bin_count", "scan", "bin_scatter", "tile_ranges",
+                  "tile_order", "blend_fwd", "blend_bwd", "preprocess_bwd")
+
+
+def raster_bytes(n, K, P, S):
+    return n * (72 + 4 * S + 52 + 8 + 36 + 36 + 72 + 4 * S + 28) + K * 52 + P * (20 + 20)
 
 
 def algorithmic_work(name, st):
     """(bound, amount per launch, unit) of the work the method itself needs."""
     n, P, S = st["n"], st["pixels"], st["sh_floats"]
-    if name == "blend_fwd":
-        return "alu", st["evals"] * BLEND_FWD_FLOP, "flop"
-    if name == "blend_bwd":
-        return "alu", st["evals"] * BLEND_BWD_FLOP, "flop"
+    if name in ("blend_fwd", "blend_bwd"):
+        return "alu", 256 * st["walked"] * OPS_PER_EVALUATED_PAIR, "flop"
     if name == "preprocess_fwd":
         # read mean, quat, log-scale, opacity, SH, dmu, dq; write 48-byte record, key, rect, count
         return "hbm", n * (12 + 16 + 12 + 4 + 4 * S + 12 + 16 + 48 + 4 + 8 + 4), "byte"
@@ -425,6 +442,9 @@ def main():
         ms, cnt = ctx.profile_query(dom)
         dom_ms = ms / cnt
     iters_per_s = args.steps / elapsed
+    free_b, total_b = torch.cuda.mem_get_info()
+    mem = {"context_workspace_bytes": ctx.workspace_bytes(), "device_in_use_bytes": int(total_b - free_b),
+           "torch_peak_allocated_bytes": int(torch.cuda.max_memory_allocated())}
 
     # pairs, walked list entries and per-pixel evaluations, averaged over the
     # training views with the final transform
@@ -432,15 +452,32 @@ def main():
     Ks, walks, evals = [], [], []
     for cam in cams:
         ctx.render(gg, cam, dmu_f, dq_f)
-        T, last = ctx.debug_pixels(cam)
-        lastn = last.cpu().numpy().astype(np.int64)
-        th, tw = (cam.height + 15) // 16, (cam.width + 15) // 16
-        pad = np.zeros((th * 16, tw * 16), np.int64)
-        pad[:lastn.shape[0], :lastn.shape[1]] = lastn
-        walks.append(int(pad.reshape(th, 16, tw, 16).max(axis=(1, 3)).sum()))
-        evals.append(int(lastn.sum()))
+        sc, wk = ctx.debug_sums()          # sum of n_contrib; sum over tiles of the longest walk
+        walks.append(wk)
+        evals.append(sc)
         Ks.append(ctx.debug_counts()[0])
     K0, walked, n_evals = int(np.mean(Ks)), int(np.mean(walks)), int(np.mean(evals))
+
+    # s/frame: per-frame setup (Morton order of the frozen Gaussians, NTC
+    # contribution lists) + 150 iterations from the warm-up parameters, the
+    # median of 5 frames after one warm-up frame
+    frame_s = []
+    g_in = gs3.GaussiansGPU.from_host(g)
+    for rep in range(6):
+        ctx.ntc_load(params_warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g_f, _ = ctx.reorder(g_in, cfg.aabb_min, cfg.inv_extent())
+        st_f = train.Stage1NTC(ctx, g_f, cams, targets, lam=0.2)
+        for _ in range(150):
+            st_f.step()
+        torch.cuda.synchronize()
+        if rep:
+            frame_s.append(time.perf_counter() - t0)
+        del st_f, g_f
+    ctx.check_flags()
+    ctx.ntc_load(params_warm)
+    s_per_frame = float(np.median(frame_s))
 
     # render FPS on the held-out view: NTC query + transform + raster (and raster alone)
     hc = held[0]
@@ -518,6 +555,18 @@ def main():
                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     "algorithmic_per_launch": int(amount),
                     "algorithmic_unit": unit, "ms_per_launch": round(dom_ms, 5)}
+    if roof is not None and dom in ("blend_fwd", "blend_bwd"):
+        per = BLEND_FWD_FLOP if dom == "blend_fwd" else BLEND_BWD_FLOP
+        roof["count"] = (f"{OPS_PER_EVALUATED_PAIR} ops x 256 x {walked} (sum over tiles of the longest walk) "
+                         f"evaluated pairs")
+        roof["builder_op_count"] = {"ops_per_pixel_entry": per, "pixel_entries": n_evals,
+                                    "tflops": round(per * n_evals / (dom_ms * 1e-3) / 1e12, 3),
+                                    "frac": round(per * n_evals / (dom_ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4)}
+    r_ms = sum(kernels[k]["ms_per_launch"] * kernels[k]["launches_per_step"] for k in RASTER_KERNELS if k in kernels)
+    r_bytes = raster_bytes(g.n, K0, cams[0].width * cams[0].height, 3 * (g.sh_degree + 1) ** 2)
+    raster_hbm = {"kernels": list(RASTER_KERNELS), "ms_per_step": round(r_ms, 4), "algorithmic_bytes": int(r_bytes),
+                  "achieved_gbs": round(r_bytes / (r_ms * 1e-3) / 1e9, 1),
+                  "frac_of_8tbs": round(r_bytes / (r_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     all_roof = {}
     for k, v in kernels.items():
         w = algorithmic_work(k, st)
@@ -547,15 +596,20 @@ def main():
         "config": {"workload": args.workload, "gaussians": g.n, "sh_degree": g.sh_degree,
                    "width": cams[0].width, "height": cams[0].height, "views": len(cams),
                    "ntc_precision": args.precision, "sort_mode": args.sort_mode},
-        "s_per_frame_150_iters": round(150.0 / iters_per_s, 4),
+        "s_per_frame_150_iters": round(s_per_frame, 4),
+        "s_per_frame_runs": [round(x, 4) for x in frame_s],
+        "s_per_frame_note": "per-frame setup (Morton order + NTC contribution lists) + 150 iterations, "
+                            "median of 5 frames after 1 warm-up frame",
         "render_fps_with_ntc": round(fps, 2), "render_fps_without_ntc": round(fps_plain, 2),
         "direct_f32_iters_per_s": None if direct is None else round(direct, 3),
         "iters_per_s_by_ntc_precision": by_precision, "multi_view_batch": multi_view,
-        "pairs_per_view": int(K0), "walked_entries": walked, "pixel_evals": n_evals,
+        "pairs_per_view": int(K0), "sum_n_contrib": n_evals, "walked_entries": walked,
+        "evaluated_pairs": 256 * walked, "pixel_evals": n_evals,
+        "device_memory": mem,
         "heldout_psnr_after_steps": round(psnr_ntc, 3),
         "warmup_s": round(t_warm, 3), "warmup_iters": args.warmup_iters, "frame_setup_s": round(t_prepare + t_reorder, 4),
         "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in kernels.items()},
-        "roofline": roof, "roofline_frac_by_kernel": all_roof, "cpu_baseline": base,
+        "roofline": roof, "roofline_frac_by_kernel": all_roof, "rasterizer_hbm": raster_hbm, "cpu_baseline": base,
         "equal_psnr": qual,
     }
     print(json.dumps(res))

@@ -183,30 +183,60 @@ gs3_status gs3_ntc_load(gs3_ctx* ctx, const float* host_params, int64_t n);
  * Synchronises. */
 gs3_status gs3_ntc_save(gs3_ctx* ctx, float* host_params, int64_t cap);
 
+/* Initialise the NTC parameters on the device (Suppl. Sec. A gives the
+ * architecture, not the initialisation; the instant-NGP encoding it follows
+ * starts its table near zero): table entries U(-1e-4, 1e-4), each weight
+ * matrix Kaiming-uniform U(-sqrt(6 / fan_in), +sqrt(6 / fan_in)) (fan-in 32
+ * for W1, 64 for W2 and W3).  Parameter i is b * (2u - 1), u = (top 24 bits
+ * of output i of SplitMix64 seeded with `seed`) / 2^24, where output i is
+ * the SplitMix64 mixing function applied to seed + (i + 1) *
+ * 0x9E3779B97F4A7C15 (Steele, Lea and Flood 2014); float32 arithmetic, one
+ * rounding.  Resets the gradients, Adam moments and step counter like
+ * gs3_ntc_load.  Synchronises. */
+gs3_status gs3_ntc_init(gs3_ctx* ctx, uint64_t seed);
+
+/* Checkpoint of the whole NTC training state: a fixed header (magic
+ * "GS3NTC1", parameter count, Adam step, NTC shape and AABB), then the
+ * float32 parameters and the first and second Adam moments (num_params
+ * each), all in HOST memory.  gs3_ntc_state_bytes gives the size;
+ * gs3_ntc_save_state writes it (cap >= that size, *used = the size, may be
+ * NULL); gs3_ntc_load_state restores parameters, moments and step (the
+ * gradients are zeroed) and returns GS3_EINVAL when n or the saved shape or
+ * AABB differ from this context's.  The storage precision may differ (the
+ * working copy is rebuilt from the float32 parameters).  Both synchronise. */
+gs3_status gs3_ntc_state_bytes(const gs3_ctx* ctx, size_t* bytes);
+gs3_status gs3_ntc_save_state(gs3_ctx* ctx, void* host, size_t cap, size_t* used);
+gs3_status gs3_ntc_load_state(gs3_ctx* ctx, const void* host, size_t n);
+
 /* (dmu, dq) = MLP(h(mu)) for n means (n x 3) -> dmu (n x 3), dq (n x 4).
  * Means outside the AABB get the identity (0, (1,0,0,0)) (Suppl. Sec. A).
- * On the means of the last gs3_ntc_prepare the context also keeps each
- * point's encoding h(mu) for the next gs3_ntc_backward on them. */
-gs3_status gs3_ntc_forward(gs3_ctx* ctx, const float* means, int64_t n, float* dmu, float* dq);
+ * token: 0, or the token of the last gs3_ntc_prepare, whose means and n
+ * these must be (GS3_ESTATE for a stale token, GS3_EINVAL for other means).
+ * With a token the context also keeps each point's encoding h(mu) for the
+ * next gs3_ntc_backward with that token. */
+gs3_status gs3_ntc_forward(gs3_ctx* ctx, const float* means, int64_t n, uint64_t token, float* dmu, float* dq);
 
 /* Accumulate into the context's float32 gradient buffers the gradient of
  * <d_dmu, dmu> + <d_dq, dq> for the same means (adjoint of Eq. 5: MLP
- * backward, then the hash-table scatter-add).  On the means of the last
- * gs3_ntc_prepare, the encoding that the last gs3_ntc_forward on them
- * computed is reused when no gs3_ntc_step or gs3_ntc_load came in between. */
-gs3_status gs3_ntc_backward(gs3_ctx* ctx, const float* means, int64_t n,
+ * backward, then the hash-table scatter-add).  token as for
+ * gs3_ntc_forward: with a token the table gradient is the per-entry sum over
+ * the prepared contribution lists (no atomics, fixed order) and the encoding
+ * of the last forward with that token is reused when no gs3_ntc_step,
+ * gs3_ntc_init or load came in between; with 0 the table gradient is
+ * scattered with atomics. */
+gs3_status gs3_ntc_backward(gs3_ctx* ctx, const float* means, int64_t n, uint64_t token,
                             const float* d_dmu, const float* d_dq);
 
 /* Per-frame setup for gs3_ntc_backward on frozen means (Stage 1 keeps the
  * previous frame's Gaussians frozen, Sec. 4.1): for every (mean, level,
  * corner) the table entry and trilinear weight are computed once and the
- * contributions are sorted by entry.  Afterwards gs3_ntc_backward calls with
- * the SAME `means` pointer and n add the table gradient by a per-entry sum
- * (no atomics, fixed order).  The caller guarantees that the contents of
- * `means` do not change until the next gs3_ntc_prepare; a call with another
- * pointer or n uses the atomic scatter.  Allocates device memory on first
- * use or growth (about 3.3 KB per mean) and synchronises. */
-gs3_status gs3_ntc_prepare(gs3_ctx* ctx, const float* means, int64_t n);
+ * contributions are sorted by entry.  *token receives a new nonzero token
+ * that names this preparation; forward and backward calls pass it to use
+ * the prepared lists.  The caller guarantees that the contents of `means`
+ * do not change while the token is in use; a later gs3_ntc_prepare makes
+ * the previous token stale.  Allocates device memory on first use or growth
+ * (about 3.3 KB per mean) and synchronises. */
+gs3_status gs3_ntc_prepare(gs3_ctx* ctx, const float* means, int64_t n, uint64_t* token);
 
 /* One Adam step on the NTC parameters with the accumulated gradients,
  * then zero the gradients and refresh the FP16/BF16 working copy. */
@@ -293,10 +323,15 @@ gs3_status gs3_zero(gs3_ctx* ctx, float* dev, int64_t n);
 
 /* ---- Inspection (parity tests, benchmarks) ------------------------------- */
 
-/* Number of (Gaussian, tile) pairs of the slot's last render and its overflow
- * flag; sums the contributors walked.  Synchronises.  Returns GS3_ECAPACITY
- * when the pair list overflowed. */
-gs3_status gs3_debug_counts(gs3_ctx* ctx, int32_t slot, int64_t* num_pairs, int32_t* overflow);
+/* Counts of the slot's last render (any pointer may be NULL): the number of
+ * (Gaussian, tile) pairs K, the sum over pixels of n_contrib (the tile-list
+ * entries each pixel walked up to its last contributor of Eq. 4), the sum
+ * over tiles of the longest such walk in the tile (the entries the blend
+ * kernels evaluate for the whole tile), and the overflow flag.  The sums
+ * are -1 when the slot holds no render.  Synchronises.  Returns
+ * GS3_ECAPACITY when the pair list overflowed. */
+gs3_status gs3_debug_counts(gs3_ctx* ctx, int32_t slot, int64_t* num_pairs, int64_t* sum_contrib,
+                            int64_t* walked, int32_t* overflow);
 
 /* Sorted pairs of the slot's last render into DEVICE buffers: keys
  * (tile << 32 | float bits of view-space z) and Gaussian indices; cap >=

@@ -1,0 +1,66 @@
+"""Stage-1 training loops on the oracle (test infrastructure only).
+
+Sec. 4.1: each iteration queries the NTC at every frozen mean (Eq. 5),
+transforms the Gaussians, renders one training view (Eq. 1-4), takes the
+loss of Eq. 6 against that view's target, back-propagates through the
+renderer and the NTC, and steps Adam on the NTC parameters (lr 0.002,
+Suppl. Sec. A; betas and epsilon of reading B7).  All arithmetic is
+float64; the parameters are rounded to float32 after every step, since the
+GPU keeps float32 master parameters.  The training views come as a list
+(reading C10: the same schedule is handed to the GPU loop).
+
+psnr() is reading C12: 10 log10(1 / MSE) on images clamped to [0, 1].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import loss as oloss
+from . import ntc as ontc
+from . import optim as oopt
+from . import raster as orc
+
+
+def psnr(img, target) -> float:
+    d = np.clip(np.asarray(img, np.float64), 0, 1) - np.clip(np.asarray(target, np.float64), 0, 1)
+    mse = float(np.mean(d * d))
+    return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
+
+
+def ntc_stage1(spec, params0, g, cams, targets, views, lam=0.2, lr=0.002, betas=(0.9, 0.99), eps=1e-15,
+               held_cam=None, held_target=None, log_every=10, keep_params=0):
+    """Run len(views) iterations from the float32 parameters params0.
+
+    Returns a dict: loss per iteration; (iteration, held-out PSNR) every
+    `log_every` iterations and at 0 when a held-out view is given; the
+    float32 parameters after, and the gradients of, each of the first
+    `keep_params` iterations.
+    """
+    p = np.asarray(params0, np.float32).astype(np.float64)
+    m, v = np.zeros_like(p), np.zeros_like(p)
+    losses, log, kept, grads = [], [], [], []
+
+    def held_psnr():
+        dmu, dq, _ = ontc.forward(spec, p, g.means)
+        img = orc.render(g, held_cam, dmu.astype(np.float32), dq.astype(np.float32))["image"]
+        return psnr(img, held_target)
+
+    if held_cam is not None:
+        log.append((0, held_psnr()))
+    for t, view in enumerate(views, start=1):
+        dmu, dq, cache = ontc.forward(spec, p, g.means)
+        dmu32, dq32 = dmu.astype(np.float32), dq.astype(np.float32)     # the GPU hands float32 to the renderer
+        cam = cams[view]
+        img = orc.render(g, cam, dmu32, dq32)["image"]
+        L, dL = oloss.stage1_loss(img, np.asarray(targets[view], np.float64), lam)
+        gr = orc.render_backward(g, cam, dL, dmu32, dq32)
+        grad = ontc.backward(spec, p, cache, gr["d_dmu"], gr["d_dq"])
+        p, m, v = oopt.adam(p, grad, m, v, t, lr, betas[0], betas[1], eps)
+        p = p.astype(np.float32).astype(np.float64)
+        losses.append(L)
+        if t <= keep_params:
+            kept.append(p.astype(np.float32))
+            grads.append(grad)
+        if held_cam is not None and t % log_every == 0:
+            log.append((t, held_psnr()))
+    return {"loss": losses, "psnr": log, "params": kept, "grads": grads}

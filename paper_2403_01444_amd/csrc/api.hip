@@ -134,6 +134,7 @@ struct gs3_ctx {
     float* grec = nullptr;
     int64_t grec_cap = 0;
     int* flags = nullptr;   // [0] pair overflow, [1] non-finite loss
+    uint64_t* sums = nullptr;        // two u64 sums of the inspection calls
     float* loss_maps = nullptr;
     double* loss_bsum = nullptr;
     // NTC
@@ -151,6 +152,8 @@ struct gs3_ctx {
     NtcCsr csr;
     const float* csr_means = nullptr;
     int64_t csr_n = -1, csr_cap = 0;
+    uint64_t csr_token = 0;          // token of the current preparation (0: none)
+    uint64_t last_token = 0;         // last token handed out
     std::vector<void*> csr_allocs;
     uint32_t* csr_keys[2] = {nullptr, nullptr};
     uint32_t* csr_vals[2] = {nullptr, nullptr};
@@ -205,11 +208,15 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
     if (tiles_of(cfg->max_width, cfg->max_height) > GS3_MAX_TILES) return GS3_EINVAL;
     if ((cfg->max_width + 15) / 16 > kMaxTilesX) return GS3_EINVAL;
     if ((cfg->max_width + kTile - 1) / kTile > 2048) return GS3_EINVAL;
+    // the binning passes launch bin_chunks(N) x ceil(tile rows / 8) workgroups
+    // of 512 threads on a 1-D grid: keep that below 2^32 work-items
+    if (bin_chunks(cfg->max_gaussians) * (((cfg->max_height + kTile - 1) / kTile + 7) / 8) * 512 >= ((int64_t)1 << 32))
+        return GS3_EINVAL;
     gs3_ctx* c = new gs3_ctx();
     c->cfg = *cfg;
     c->max_tiles = tiles_of(cfg->max_width, cfg->max_height);
     const int64_t N = cfg->max_gaussians, PK = cfg->max_pairs, PX = (int64_t)cfg->max_width * cfg->max_height;
-    const int64_t nchunks = (N + kBinChunk - 1) / kBinChunk;
+    const int64_t nchunks = bin_chunks(N);
     bool ok = true;
     c->slots.resize(cfg->num_slots);
     for (auto& s : c->slots) {
@@ -228,7 +235,7 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
     ok = ok && c->alloc(&c->dkeys[0], N) && c->alloc(&c->dkeys[1], N) && c->alloc(&c->dvals[0], N) &&
          c->alloc(&c->dvals[1], N) && c->alloc(&c->radix_hist, hist_words) &&
          c->alloc(&c->scan_tmp, scan_tmp_words(scan_items) + 4) && c->alloc(&c->accum, 9 * N) &&
-         c->alloc(&c->flags, 4) && c->alloc(&c->loss_maps, loss_map_floats(cfg->max_height, cfg->max_width)) &&
+         c->alloc(&c->flags, 4) && c->alloc(&c->sums, 2) && c->alloc(&c->loss_maps, loss_map_floats(cfg->max_height, cfg->max_width)) &&
          c->alloc(&c->walk_off, c->max_tiles) && c->alloc(&c->walk_total, 1) && c->alloc(&c->goff_total, 1) &&
          c->alloc(&c->sel_flag, N) && c->alloc(&c->sel_pos, N) && c->alloc(&c->sel_total, 1) &&
          c->alloc(&c->loss_bsum, 2 * (int64_t)loss_blocks(cfg->max_height, cfg->max_width));
@@ -376,6 +383,102 @@ gs3_status gs3_ntc_save(gs3_ctx* c, float* host_params, int64_t cap) {
     return GS3_OK;
 }
 
+// Reset everything that follows the parameters: gradients, Adam moments,
+// step counter, the working copy and the kept encoding.
+static void ntc_reset_state(gs3_ctx* c, bool keep_moments) {
+    Launch L = c->L();
+    fill_f32(L, c->g, 0.f, c->n_params);
+    if (!keep_moments) {
+        fill_f32(L, c->m, 0.f, c->n_params);
+        fill_f32(L, c->v, 0.f, c->n_params);
+        c->step = 0;
+    }
+    ntc_refresh_work(L, c->cfg.ntc.precision, c->p, c->work, c->n_params);
+    c->enc_valid = false;
+}
+
+gs3_status gs3_ntc_init(gs3_ctx* c, uint64_t seed) {
+    if (!c) return GS3_EINVAL;
+    if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
+    ntc_init(c->L(), c->p, c->n_params, c->n_table_floats, seed);
+    ntc_reset_state(c, false);
+    if (hipStreamSynchronize(c->st) != hipSuccess) return c->fail(GS3_EHIP, "ntc_init: sync failed");
+    return c->check_launch("ntc_init");
+}
+
+namespace {
+// Fixed-layout header of a saved NTC state, followed by the float32
+// parameters, first and second Adam moments (n_params each).
+struct NtcStateHeader {
+    char magic[8];
+    int64_t n_params;
+    int64_t step;
+    int32_t levels, feats, log2_T, hidden, precision, reserved;
+    int32_t res[16];
+    float aabb_min[3], inv_extent[3];
+};
+const char kStateMagic[8] = {'G', 'S', '3', 'N', 'T', 'C', '1', '\0'};
+}  // namespace
+
+gs3_status gs3_ntc_state_bytes(const gs3_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return GS3_EINVAL;
+    if (!c->n_params) return GS3_ESTATE;
+    *bytes = sizeof(NtcStateHeader) + 3 * (size_t)c->n_params * 4;
+    return GS3_OK;
+}
+
+gs3_status gs3_ntc_save_state(gs3_ctx* c, void* host, size_t cap, size_t* used) {
+    if (!c || !host) return GS3_EINVAL;
+    if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
+    size_t need = 0;
+    gs3_ntc_state_bytes(c, &need);
+    if (used) *used = need;
+    if (cap < need) return c->fail(GS3_EINVAL, "ntc_save_state: buffer too small");
+    NtcStateHeader h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, kStateMagic, 8);
+    const gs3_ntc_config& nc = c->cfg.ntc;
+    h.n_params = c->n_params; h.step = c->step;
+    h.levels = nc.levels; h.feats = nc.feats; h.log2_T = nc.log2_T; h.hidden = nc.hidden; h.precision = nc.precision;
+    for (int l = 0; l < 16; l++) h.res[l] = nc.res[l];
+    for (int k = 0; k < 3; k++) { h.aabb_min[k] = nc.aabb_min[k]; h.inv_extent[k] = nc.inv_extent[k]; }
+    memcpy(host, &h, sizeof(h));
+    char* dst = (char*)host + sizeof(h);
+    const size_t b = (size_t)c->n_params * 4;
+    if (hipMemcpyAsync(dst, c->p, b, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipMemcpyAsync(dst + b, c->m, b, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipMemcpyAsync(dst + 2 * b, c->v, b, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "ntc_save_state: copy failed");
+    return GS3_OK;
+}
+
+gs3_status gs3_ntc_load_state(gs3_ctx* c, const void* host, size_t n) {
+    if (!c || !host) return GS3_EINVAL;
+    if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
+    size_t need = 0;
+    gs3_ntc_state_bytes(c, &need);
+    if (n != need) return c->fail(GS3_EINVAL, "ntc_load_state: size does not match this context's NTC");
+    NtcStateHeader h;
+    memcpy(&h, host, sizeof(h));
+    const gs3_ntc_config& nc = c->cfg.ntc;
+    bool same = memcmp(h.magic, kStateMagic, 8) == 0 && h.n_params == c->n_params && h.step >= 0 &&
+                h.levels == nc.levels && h.feats == nc.feats && h.log2_T == nc.log2_T && h.hidden == nc.hidden;
+    for (int l = 0; l < 16 && same; l++) same = h.res[l] == nc.res[l];
+    for (int k = 0; k < 3 && same; k++) same = h.aabb_min[k] == nc.aabb_min[k] && h.inv_extent[k] == nc.inv_extent[k];
+    if (!same) return c->fail(GS3_EINVAL, "ntc_load_state: the saved NTC has another shape or AABB");
+    const char* src = (const char*)host + sizeof(h);
+    const size_t b = (size_t)c->n_params * 4;
+    if (hipMemcpyAsync(c->p, src, b, hipMemcpyHostToDevice, c->st) != hipSuccess ||
+        hipMemcpyAsync(c->m, src + b, b, hipMemcpyHostToDevice, c->st) != hipSuccess ||
+        hipMemcpyAsync(c->v, src + 2 * b, b, hipMemcpyHostToDevice, c->st) != hipSuccess)
+        return c->fail(GS3_EHIP, "ntc_load_state: copy failed");
+    c->step = (int)h.step;
+    ntc_reset_state(c, true);
+    if (hipStreamSynchronize(c->st) != hipSuccess) return c->fail(GS3_EHIP, "ntc_load_state: sync failed");
+    return c->check_launch("ntc_load_state");
+}
+
 static void ntc_ptrs(gs3_ctx* c, const void** table, const void** mlp) {
     if (c->cfg.ntc.precision == GS3_F32) {
         *table = c->p;
@@ -386,40 +489,60 @@ static void ntc_ptrs(gs3_ctx* c, const void** table, const void** mlp) {
     }
 }
 
-gs3_status gs3_ntc_forward(gs3_ctx* c, const float* means, int64_t n, float* dmu, float* dq) {
+// A nonzero token must be the one the last gs3_ntc_prepare returned, for
+// the same means and n.
+static gs3_status check_token(gs3_ctx* c, const float* means, int64_t n, uint64_t token, const char* what) {
+    if (token == 0) return GS3_OK;
+    if (token != c->csr_token || c->csr_token == 0)
+        return c->fail(GS3_ESTATE, std::string(what) + ": the token is not the last ntc_prepare's");
+    if (means != c->csr_means || n != c->csr_n)
+        return c->fail(GS3_EINVAL, std::string(what) + ": means or n differ from the prepared ones");
+    return GS3_OK;
+}
+
+gs3_status gs3_ntc_forward(gs3_ctx* c, const float* means, int64_t n, uint64_t token, float* dmu, float* dq) {
     if (!c) return GS3_EINVAL;
     if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
-    if (n < 0 || (n > 0 && (!means || !dmu || !dq))) return c->fail(GS3_EINVAL, "ntc_forward: bad arguments");
+    if (n < 0 || n > c->cfg.max_gaussians || (n > 0 && (!means || !dmu || !dq)))
+        return c->fail(GS3_EINVAL, "ntc_forward: bad arguments");
+    gs3_status s = check_token(c, means, n, token, "ntc_forward");
+    if (s != GS3_OK) return s;
     const void *table, *mlp;
     ntc_ptrs(c, &table, &mlp);
     // on the prepared means the forward keeps the encoding for the backward
-    const bool prepared = n > 0 && means == c->csr_means && n == c->csr_n;
+    const bool prepared = token != 0 && n > 0;
     ntc_forward(c->L(), c->cfg.ntc.precision, c->nd, table, mlp, means, n, dmu, dq,
                 prepared ? c->enc_cache : nullptr);
     if (prepared) c->enc_valid = true;
     return c->check_launch("ntc_forward");
 }
 
-gs3_status gs3_ntc_backward(gs3_ctx* c, const float* means, int64_t n, const float* d_dmu, const float* d_dq) {
+gs3_status gs3_ntc_backward(gs3_ctx* c, const float* means, int64_t n, uint64_t token, const float* d_dmu,
+                            const float* d_dq) {
     if (!c) return GS3_EINVAL;
     if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
-    if (n < 0 || (n > 0 && (!means || !d_dmu || !d_dq))) return c->fail(GS3_EINVAL, "ntc_backward: bad arguments");
+    if (n < 0 || n > c->cfg.max_gaussians || (n > 0 && (!means || !d_dmu || !d_dq)))
+        return c->fail(GS3_EINVAL, "ntc_backward: bad arguments");
+    gs3_status s = check_token(c, means, n, token, "ntc_backward");
+    if (s != GS3_OK) return s;
     const void *table, *mlp;
     ntc_ptrs(c, &table, &mlp);
-    const bool prepared = means == c->csr_means && n == c->csr_n;
+    const bool prepared = token != 0;
     ntc_backward(c->L(), c->cfg.ntc.precision, c->nd, table, mlp, means, n, d_dmu, d_dq, c->g,
                  c->g + c->n_table_floats, c->g_part, c->max_parts, prepared ? &c->csr : nullptr,
                  prepared && c->enc_valid ? c->enc_cache : nullptr);
     return c->check_launch("ntc_backward");
 }
 
-gs3_status gs3_ntc_prepare(gs3_ctx* c, const float* means, int64_t n) {
+gs3_status gs3_ntc_prepare(gs3_ctx* c, const float* means, int64_t n, uint64_t* token) {
     if (!c) return GS3_EINVAL;
+    if (token) *token = 0;
     if (!c->n_params) return c->fail(GS3_ESTATE, "context created without an NTC");
     if (n < 1 || n > c->cfg.max_gaussians || n >= ((int64_t)1 << 25) || !means)
         return c->fail(GS3_EINVAL, "ntc_prepare: bad arguments");
     c->csr_means = nullptr;
     c->csr_n = -1;
+    c->csr_token = 0;
     c->enc_valid = false;
     const int64_t m = n * 128;
     if (n > c->csr_cap) {
@@ -456,6 +579,8 @@ gs3_status gs3_ntc_prepare(gs3_ctx* c, const float* means, int64_t n) {
     if (s != GS3_OK) return s;
     c->csr_means = means;
     c->csr_n = n;
+    c->csr_token = ++c->last_token;
+    if (token) *token = c->csr_token;
     return GS3_OK;
 }
 
@@ -550,7 +675,7 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
             iota_u32(L, c->dvals[0], n);
             const int r = radix_sort_u32(L, c->dkeys, c->dvals, n, 32, c->radix_hist, c->scan_tmp);
             const uint32_t* order = c->dvals[r];
-            const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
+            const int64_t nchunks = bin_chunks(n);
             const bool rec_mode = c->grec_cap > 0;
             // first pair slot of each Gaussian: only the record mode's
             // gradient gather needs it
@@ -712,17 +837,25 @@ gs3_status gs3_zero(gs3_ctx* c, float* dev, int64_t n) {
 
 /* ---- inspection ----------------------------------------------------------- */
 
-gs3_status gs3_debug_counts(gs3_ctx* c, int32_t slot, int64_t* num_pairs, int32_t* overflow) {
+gs3_status gs3_debug_counts(gs3_ctx* c, int32_t slot, int64_t* num_pairs, int64_t* sum_contrib,
+                            int64_t* walked, int32_t* overflow) {
     if (!c) return GS3_EINVAL;
     if (slot < 0 || slot >= (int)c->slots.size()) return c->fail(GS3_EINVAL, "bad slot");
     Slot& sl = c->slots[slot];
-    uint64_t K = 0;
-    int flags[4] = {0, 0, 0, 0};
+    uint64_t K = 0, sums[2] = {0, 0};
+    const bool need_sums = sl.valid && (sum_contrib || walked);
+    if (need_sums) {
+        Launch L = c->L();
+        sum_u32(L, sl.last, (int64_t)sl.cam.W * sl.cam.H, c->sums);
+        sum_u32(L, sl.tile_walk, (int64_t)sl.cam.tiles_x * sl.cam.tiles_y, c->sums + 1);
+    }
     if (hipMemcpyAsync(&K, sl.total, 8, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
-        hipMemcpyAsync(flags, c->flags, 16, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        (need_sums && hipMemcpyAsync(sums, c->sums, 16, hipMemcpyDeviceToHost, c->st) != hipSuccess) ||
         hipStreamSynchronize(c->st) != hipSuccess)
         return c->fail(GS3_EHIP, "debug_counts: copy failed");
     if (num_pairs) *num_pairs = (int64_t)K;
+    if (sum_contrib) *sum_contrib = sl.valid ? (int64_t)sums[0] : -1;
+    if (walked) *walked = sl.valid ? (int64_t)sums[1] : -1;
     const int ov = K > (uint64_t)c->cfg.max_pairs;
     if (overflow) *overflow = ov;
     return ov ? c->fail(GS3_ECAPACITY, "pair list overflowed") : GS3_OK;
@@ -735,7 +868,7 @@ gs3_status gs3_debug_pairs(gs3_ctx* c, int32_t slot, uint64_t* keys, uint32_t* v
     if (!sl.valid) return c->fail(GS3_ESTATE, "no render on this slot");
     int64_t K = 0;
     int32_t ov = 0;
-    gs3_status s = gs3_debug_counts(c, slot, &K, &ov);
+    gs3_status s = gs3_debug_counts(c, slot, &K, nullptr, nullptr, &ov);
     if (s != GS3_OK) return s;
     if (cap < K) return c->fail(GS3_EINVAL, "debug_pairs: buffer too small");
     if (K == 0) return GS3_OK;

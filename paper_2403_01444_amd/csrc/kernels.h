@@ -43,6 +43,8 @@ void gather_rows(const Launch& L, const float* src, const uint32_t* perm, int64_
 void fill_u32(const Launch& L, uint32_t* p, uint32_t v, int64_t n);
 void fill_f32(const Launch& L, float* p, float v, int64_t n);
 void iota_u32(const Launch& L, uint32_t* p, int64_t n);
+// *out (one u64, device) = sum of the n values
+void sum_u32(const Launch& L, const uint32_t* a, int64_t n, uint64_t* out);
 
 // ---- rasterizer (raster.hip) -------------------------------------------------
 void preprocess(const Launch& L, const GaussDev& g, const CamDev& cam, float4* rec, uint32_t* key, uint2* rect,
@@ -58,6 +60,9 @@ void ranges_from_keys(const Launch& L, const uint64_t* keys, int64_t K, int ntil
 #endif
 constexpr int kBinChunk = GS3_BIN_CHUNK;
 constexpr int kMaxTilesX = 256;   // widest image: 4096 pixels
+// chunks of kBinChunk depth-ordered Gaussians for n Gaussians, rounded up to
+// a multiple of 8 (the passes give each XCD an eighth; padding chunks are empty)
+int64_t bin_chunks(int64_t n);
 // tile rectangles (empty for culled Gaussians) and, when sgoff is set, the
 // first pair slots goff, gathered into depth order
 void bin_gather(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,

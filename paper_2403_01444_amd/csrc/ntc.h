@@ -39,6 +39,9 @@ void ntc_backward(const Launch& L, int precision, const NtcDev& nd, const void* 
                   float* g_part, int max_parts, const NtcCsr* csr, const void* enc_in);
 void ntc_adam(const Launch& L, int precision, float* p, float* g, float* m, float* v, void* work, int64_t n, float lr,
               float b1, float b2, float eps, float bc1, float bc2);
+// float32 master parameters [table | W1 | W2 | W3] from a counter-based
+// generator (SplitMix64) seeded with `seed`
+void ntc_init(const Launch& L, float* p, int64_t n, int64_t n_table, uint64_t seed);
 void ntc_refresh_work(const Launch& L, int precision, const float* p, void* work, int64_t n);
 void warmup_loss(const Launch& L, const float* dmu, const float* dq, int64_t n, float* loss, float* gmu, float* gq,
                  double* bsum);

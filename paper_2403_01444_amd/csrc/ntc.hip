@@ -862,6 +862,41 @@ void ntc_csr_build(const Launch& L, const NtcDev& nd, const float* means, int64_
     if (L.prof) L.prof->end(L.st);
 }
 
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014) used as a counter-based generator: output i of
+// the stream seeded with `seed` is the generator's mixing function applied to
+// seed + (i + 1) * 0x9E3779B97F4A7C15.
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Parameter i = bound * (2u - 1) with u the top 24 bits of output i over
+// 2^24 (exact in float32, so 2u - 1 is exact and the product rounds once).
+// bound: b_table for the table, then b_w1 / b_w2 / b_w3 for the three
+// weight matrices (n_w1, n_w2 entries; the rest W3).
+__global__ __launch_bounds__(256) void k_ntc_init(float* __restrict__ p, int64_t n, int64_t n_table, int64_t n_w1,
+                                                  int64_t n_w2, float b_table, float b_w1, float b_w2, float b_w3,
+                                                  uint64_t seed) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = i - n_table;
+    const float b = j < 0 ? b_table : j < n_w1 ? b_w1 : j < n_w1 + n_w2 ? b_w2 : b_w3;
+    const float u = (float)(uint32_t)(splitmix64_at(seed, (uint64_t)i) >> 40) * 0x1p-24f;
+    p[i] = b * (2.0f * u - 1.0f);
+}
+
+void ntc_init(const Launch& L, float* p, int64_t n, int64_t n_table, uint64_t seed) {
+    // U(-1e-4, 1e-4) for the table (instant-NGP's), Kaiming-uniform
+    // U(-sqrt(6 / fan_in), +sqrt(6 / fan_in)) for W1 (fan-in 32), W2, W3 (64)
+    const float b_table = 1e-4f, b_w1 = (float)sqrt(6.0 / 32.0), b_w2 = (float)sqrt(6.0 / 64.0);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_ntc_init, dim3(nblk(n, 256)), dim3(256), 0, L.st, p, n, n_table, (int64_t)64 * 32,
+                       (int64_t)64 * 64, b_table, b_w1, b_w2, b_w2, seed);
+}
+
 void ntc_adam(const Launch& L, int precision, float* p, float* g, float* m, float* v, void* work, int64_t n, float lr,
               float b1, float b2, float eps, float bc1, float bc2) {
     if (L.prof) L.prof->begin("ntc_adam", L.st);

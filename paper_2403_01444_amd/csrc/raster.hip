@@ -125,6 +125,21 @@ __global__ __launch_bounds__(256) void k_ranges_from_keys(const uint64_t* __rest
 constexpr int kBinRowsPerBlock = GS3_BIN_ROWS;   // one wave per tile row
 constexpr int kBinThreads = 64 * kBinRowsPerBlock;
 
+// Workgroups are dealt round-robin to the eight XCDs (linear id mod 8), each
+// with its own L2.  The binning passes give each XCD a contiguous eighth of
+// the chunks of every row block, so the (tile, chunk) segments that follow
+// each other in a tile's list (about a dozen entries each) are written
+// through the same L2 and merge into whole lines there, instead of eight L2s
+// writing back partial lines of each other's segments.  nchunks is a
+// multiple of 8 (bin_chunks); the padding chunks are empty.
+__device__ __forceinline__ void bin_block(int64_t nchunks, int& rowblock, int64_t& chunk) {
+    const int64_t per = nchunks >> 3;
+    const int64_t b = blockIdx.x;
+    const int64_t k = b >> 3;
+    rowblock = (int)(k / per);
+    chunk = (b & 7) * per + k % per;
+}
+
 __global__ __launch_bounds__(256) void k_bin_gather(const uint32_t* __restrict__ order, int64_t n,
                                                     const uint2* __restrict__ rect, const uint32_t* __restrict__ count,
                                                     const uint64_t* __restrict__ goff, uint32_t cap,
@@ -150,8 +165,10 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const uint2* __restri
     __shared__ uint2 s_rect[kBinChunk];
     __shared__ int s_diff[kBinRowsPerBlock][kMaxTilesX + 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int row = (int)blockIdx.y * kBinRowsPerBlock + w;
-    const int64_t chunk = blockIdx.x;
+    int rowblock;
+    int64_t chunk;
+    bin_block(nchunks, rowblock, chunk);
+    const int row = rowblock * kBinRowsPerBlock + w;
     const int64_t e0 = chunk * kBinChunk;
     const int m = (int)min((int64_t)kBinChunk, n - e0);
     for (int e = threadIdx.x; e < m; e += kBinThreads) s_rect[e] = srect[e0 + e];
@@ -213,8 +230,10 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __rest
     __shared__ uint16_t s_gl[kBinRowsPerBlock][kBinChunk];      // covering Gaussians (chunk positions)
     __shared__ uint32_t s_wp[kBinRowsPerBlock][kBinChunk];      // exclusive prefix of their column counts
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int row = (int)blockIdx.y * kBinRowsPerBlock + w;
-    const int64_t chunk = blockIdx.x;
+    int rowblock;
+    int64_t chunk;
+    bin_block(nchunks, rowblock, chunk);
+    const int row = rowblock * kBinRowsPerBlock + w;
     const int64_t e0 = chunk * kBinChunk;
     const int m = (int)min((int64_t)kBinChunk, n - e0);
     for (int e = threadIdx.x; e < m; e += kBinThreads) {
@@ -939,13 +958,15 @@ void bin_gather(const Launch& L, const uint32_t* order, int64_t n, const uint2* 
     if (L.prof) L.prof->end(L.st);
 }
 
+int64_t bin_chunks(int64_t n) { return (((n + kBinChunk - 1) / kBinChunk) + 7) / 8 * 8; }
+
 static dim3 bin_grid(int64_t nchunks, int tiles_y) {
-    return dim3((unsigned)nchunks, (unsigned)((tiles_y + kBinRowsPerBlock - 1) / kBinRowsPerBlock));
+    return dim3((unsigned)(nchunks * ((tiles_y + kBinRowsPerBlock - 1) / kBinRowsPerBlock)));
 }
 
 void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, int tiles_x, int tiles_y,
                uint32_t* hist) {
-    const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
+    const int64_t nchunks = n > 0 ? bin_chunks(n) : 0;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_count", L.st);
     hipLaunchKernelGGL(k_bin_count, bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, srect, n, tiles_x, tiles_y,
@@ -955,7 +976,7 @@ void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* s
 
 void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, const uint32_t* sgoff,
                  int tiles_x, int tiles_y, const uint64_t* base, uint64_t cap, uint32_t* vals, uint32_t* gpos) {
-    const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
+    const int64_t nchunks = n > 0 ? bin_chunks(n) : 0;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_scatter", L.st);
     hipLaunchKernelGGL(k_bin_rows, bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, order, n, srect, sgoff,

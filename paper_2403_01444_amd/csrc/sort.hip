@@ -305,6 +305,15 @@ __global__ void k_fill_f32(float* p, float v, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
+// Sum of n u32 values into *out (u64, zeroed by the caller): a wave sum per
+// 64 values, one atomic per wave.
+__global__ __launch_bounds__(256) void k_sum_u32(const uint32_t* __restrict__ a, int64_t n,
+                                                 unsigned long long* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    unsigned long long v = i < n ? (unsigned long long)a[i] : 0ull;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
+}
 __global__ void k_iota_u32(uint32_t* p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = (uint32_t)i;
@@ -387,6 +396,12 @@ void fill_u32(const Launch& L, uint32_t* p, uint32_t v, int64_t n) {
 void fill_f32(const Launch& L, float* p, float v, int64_t n) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.st, p, v, n);
+}
+void sum_u32(const Launch& L, const uint32_t* a, int64_t n, uint64_t* out) {
+    fill_u32(L, (uint32_t*)out, 0u, 2);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_sum_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.st, a, n,
+                       (unsigned long long*)out);
 }
 void iota_u32(const Launch& L, uint32_t* p, int64_t n) {
     if (n <= 0) return;

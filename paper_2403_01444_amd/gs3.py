@@ -67,7 +67,8 @@ class GradsC(C.Structure):
 
 EXPORTED = ("gs3_create", "gs3_destroy", "gs3_last_error", "gs3_set_stream", "gs3_morton_order",
             "gs3_gather_rows", "gs3_ntc_num_params",
-            "gs3_ntc_load", "gs3_ntc_save", "gs3_ntc_forward", "gs3_ntc_backward", "gs3_ntc_prepare", "gs3_ntc_step",
+            "gs3_ntc_load", "gs3_ntc_save", "gs3_ntc_init", "gs3_ntc_state_bytes", "gs3_ntc_save_state",
+            "gs3_ntc_load_state", "gs3_ntc_forward", "gs3_ntc_backward", "gs3_ntc_prepare", "gs3_ntc_step",
             "gs3_ntc_grads", "gs3_ntc_zero_grads", "gs3_warmup_loss", "gs3_render", "gs3_render_backward", "gs3_transform_bake", "gs3_select", "gs3_spawn",
             "gs3_loss", "gs3_adam", "gs3_zero", "gs3_debug_counts", "gs3_debug_pairs", "gs3_debug_ranges",
             "gs3_debug_gaussians", "gs3_debug_pixels", "gs3_check_flags", "gs3_workspace_bytes", "gs3_profile_enable",
@@ -95,9 +96,13 @@ def lib():
         "gs3_ntc_num_params": [vp, C.POINTER(i64)],
         "gs3_ntc_load": [vp, vp, i64],
         "gs3_ntc_save": [vp, vp, i64],
-        "gs3_ntc_forward": [vp, vp, i64, vp, vp],
-        "gs3_ntc_backward": [vp, vp, i64, vp, vp],
-        "gs3_ntc_prepare": [vp, vp, i64],
+        "gs3_ntc_init": [vp, C.c_uint64],
+        "gs3_ntc_state_bytes": [vp, C.POINTER(C.c_size_t)],
+        "gs3_ntc_save_state": [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)],
+        "gs3_ntc_load_state": [vp, vp, C.c_size_t],
+        "gs3_ntc_forward": [vp, vp, i64, C.c_uint64, vp, vp],
+        "gs3_ntc_backward": [vp, vp, i64, C.c_uint64, vp, vp],
+        "gs3_ntc_prepare": [vp, vp, i64, C.POINTER(C.c_uint64)],
         "gs3_ntc_step": [vp, f32, f32, f32, f32],
         "gs3_ntc_grads": [vp, vp, i64],
         "gs3_ntc_zero_grads": [vp],
@@ -110,7 +115,7 @@ def lib():
         "gs3_loss": [vp, vp, vp, i32, i32, f32, vp, vp],
         "gs3_adam": [vp, vp, vp, vp, vp, i64, i32, f32, f32, f32, f32],
         "gs3_zero": [vp, vp, i64],
-        "gs3_debug_counts": [vp, i32, C.POINTER(i64), C.POINTER(i32)],
+        "gs3_debug_counts": [vp, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)],
         "gs3_debug_pairs": [vp, i32, vp, vp, i64],
         "gs3_debug_ranges": [vp, i32, vp],
         "gs3_debug_gaussians": [vp, i32, vp, vp, vp],
@@ -257,20 +262,46 @@ def gs3_ntc_save(h, n: int) -> np.ndarray:
     return out
 
 
-def gs3_ntc_forward(h, means, dmu, dq):
-    n = means.shape[0]
-    _check(h, lib().gs3_ntc_forward(h, _ptr(means, numel=3 * n), n, _ptr(dmu, numel=3 * n), _ptr(dq, numel=4 * n)))
+def gs3_ntc_init(h, seed: int):
+    _check(h, lib().gs3_ntc_init(h, C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF)))
 
 
-def gs3_ntc_backward(h, means, d_dmu, d_dq):
+def gs3_ntc_state_bytes(h) -> int:
+    b = C.c_size_t(0)
+    _check(h, lib().gs3_ntc_state_bytes(h, C.byref(b)))
+    return int(b.value)
+
+
+def gs3_ntc_save_state(h) -> bytes:
+    n = gs3_ntc_state_bytes(h)
+    buf = C.create_string_buffer(n)
+    used = C.c_size_t(0)
+    _check(h, lib().gs3_ntc_save_state(h, C.cast(buf, C.c_void_p), n, C.byref(used)))
+    return buf.raw[:used.value]
+
+
+def gs3_ntc_load_state(h, blob: bytes):
+    buf = C.create_string_buffer(bytes(blob), len(blob))
+    _check(h, lib().gs3_ntc_load_state(h, C.cast(buf, C.c_void_p), len(blob)))
+
+
+def gs3_ntc_forward(h, means, dmu, dq, token: int = 0):
     n = means.shape[0]
-    _check(h, lib().gs3_ntc_backward(h, _ptr(means, numel=3 * n), n, _ptr(d_dmu, numel=3 * n),
+    _check(h, lib().gs3_ntc_forward(h, _ptr(means, numel=3 * n), n, C.c_uint64(token), _ptr(dmu, numel=3 * n),
+                                    _ptr(dq, numel=4 * n)))
+
+
+def gs3_ntc_backward(h, means, d_dmu, d_dq, token: int = 0):
+    n = means.shape[0]
+    _check(h, lib().gs3_ntc_backward(h, _ptr(means, numel=3 * n), n, C.c_uint64(token), _ptr(d_dmu, numel=3 * n),
                                      _ptr(d_dq, numel=4 * n)))
 
 
-def gs3_ntc_prepare(h, means):
+def gs3_ntc_prepare(h, means) -> int:
     n = means.shape[0]
-    _check(h, lib().gs3_ntc_prepare(h, _ptr(means, numel=3 * n), n))
+    tok = C.c_uint64(0)
+    _check(h, lib().gs3_ntc_prepare(h, _ptr(means, numel=3 * n), n, C.byref(tok)))
+    return int(tok.value)
 
 
 def gs3_ntc_step(h, lr, beta1, beta2, eps):
@@ -350,11 +381,13 @@ def gs3_zero(h, t):
 
 
 def gs3_debug_counts(h, slot):
-    k, ov = C.c_int64(), C.c_int32()
-    s = lib().gs3_debug_counts(h, slot, C.byref(k), C.byref(ov))
+    """(pairs K, overflow flag, sum over pixels of n_contrib, sum over tiles
+    of the longest walk); the sums are -1 when the slot holds no render."""
+    k, ov, sc, wk = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int64()
+    s = lib().gs3_debug_counts(h, slot, C.byref(k), C.byref(sc), C.byref(wk), C.byref(ov))
     if s not in (GS3_OK, GS3_ECAPACITY):
         _check(h, s)
-    return k.value, ov.value
+    return k.value, ov.value, sc.value, wk.value
 
 
 def gs3_debug_pairs(h, slot, keys, vals):
@@ -506,18 +539,29 @@ class Context:
     def ntc_save(self):
         return gs3_ntc_save(self.h, self.n_params)
 
-    def ntc_forward(self, means, dmu=None, dq=None):
+    def ntc_init(self, seed: int):
+        gs3_ntc_init(self.h, seed)
+
+    def ntc_save_state(self) -> bytes:
+        return gs3_ntc_save_state(self.h)
+
+    def ntc_load_state(self, blob: bytes):
+        gs3_ntc_load_state(self.h, blob)
+
+    def ntc_forward(self, means, dmu=None, dq=None, token: int = 0):
         n = means.shape[0]
         dmu = self.empty(n, 3) if dmu is None else dmu
         dq = self.empty(n, 4) if dq is None else dq
-        gs3_ntc_forward(self.h, means, dmu, dq)
+        gs3_ntc_forward(self.h, means, dmu, dq, token)
         return dmu, dq
 
-    def ntc_backward(self, means, d_dmu, d_dq):
-        gs3_ntc_backward(self.h, means, d_dmu, d_dq)
+    def ntc_backward(self, means, d_dmu, d_dq, token: int = 0):
+        gs3_ntc_backward(self.h, means, d_dmu, d_dq, token)
 
-    def ntc_prepare(self, means):
-        gs3_ntc_prepare(self.h, means)
+    def ntc_prepare(self, means) -> int:
+        """Per-frame contribution lists of frozen means; returns the token
+        that forward and backward calls on these means pass."""
+        return gs3_ntc_prepare(self.h, means)
 
     def ntc_step(self, lr=0.002, beta1=0.9, beta2=0.99, eps=1e-15):
         gs3_ntc_step(self.h, lr, beta1, beta2, eps)
@@ -595,11 +639,16 @@ class Context:
 
     # -- inspection
     def debug_counts(self, slot=0):
-        return gs3_debug_counts(self.h, slot)
+        """(pairs K, overflow flag)."""
+        return gs3_debug_counts(self.h, slot)[:2]
+
+    def debug_sums(self, slot=0):
+        """(sum over pixels of n_contrib, sum over tiles of the longest walk)."""
+        return gs3_debug_counts(self.h, slot)[2:]
 
     def debug_pairs(self, slot=0):
         import torch
-        K, ov = gs3_debug_counts(self.h, slot)
+        K, ov = gs3_debug_counts(self.h, slot)[:2]
         keys = torch.empty(max(K, 1), dtype=torch.int64, device=self.device)
         vals = torch.empty(max(K, 1), dtype=torch.int32, device=self.device)
         gs3_debug_pairs(self.h, slot, keys, vals)

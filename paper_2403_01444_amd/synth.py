@@ -413,6 +413,18 @@ def ntc_init_params(cfg: NTCConfig, seed: int) -> np.ndarray:
     return np.concatenate([table] + ws).astype(np.float32)
 
 
+def view_schedule(count: int, iters: int, seed: int) -> list[int]:
+    """Training views of `iters` iterations: a fresh seeded permutation of
+    the `count` views per epoch (reading C10).  The training loops draw their
+    views in exactly this order, so the list can be handed to another
+    implementation of the same loop."""
+    rng = np.random.default_rng(seed)
+    out: list[int] = []
+    while len(out) < iters:
+        out.extend(int(v) for v in rng.permutation(count))
+    return out[:iters]
+
+
 def warmup_points(means: np.ndarray, cfg: NTCConfig, seed: int, rel_sigma: float = 0.01) -> np.ndarray:
     """Noise-augmented means for the NTC warm-up: mu + N(0, (rel_sigma * extent)^2)."""
     rng = np.random.default_rng(seed)

@@ -49,7 +49,7 @@ class Stage1NTC:
         self.loss = ctx.empty(views_per_step)   # per view of the last step
         self.views = _Views(len(cams), seed)
         # per-frame setup: the means stay frozen for the whole of Stage 1
-        ctx.ntc_prepare(gauss.means)
+        self.token = ctx.ntc_prepare(gauss.means)
 
     def accumulate(self, views, track=None):
         """NTC gradient of the summed loss over `views`: one NTC query, then
@@ -60,7 +60,7 @@ class Stage1NTC:
         unchanged by a constant gradient scale apart from eps, so the sum and
         the mean over the views step alike.)"""
         ctx = self.ctx
-        ctx.ntc_forward(self.g.means, self.dmu, self.dq)
+        ctx.ntc_forward(self.g.means, self.dmu, self.dq, self.token)
         ctx.zero(self.d_dmu, self.d_dq)
         grads = {"d_dmu": self.d_dmu, "d_dq": self.d_dq}
         if track is not None:
@@ -72,7 +72,7 @@ class Stage1NTC:
             ctx.render(self.g, cam, self.dmu, self.dq, image=img)
             ctx.loss(img, self.targets[v], self.lam, loss=self.loss[k:k + 1], d_image=dimg)
             ctx.render_backward(dimg, grads)
-        ctx.ntc_backward(self.g.means, self.d_dmu, self.d_dq)
+        ctx.ntc_backward(self.g.means, self.d_dmu, self.d_dq, self.token)
 
     def step(self, track=None):
         """One iteration over `views_per_step` views of the epoch's
@@ -87,12 +87,15 @@ class Stage1NTC:
     def run(self, iters: int):
         """`iters` iterations; the view-space gradient statistics of the last
         epoch (the iterations that cover the last len(views) views) are
-        returned for Stage 2."""
+        returned for Stage 2.  Raises GS3Error (GS3_ECAPACITY /
+        GS3_ENONFINITE) when a render of the run overflowed its pair list or a
+        loss was not finite: the run's results are then not the method's."""
         n = self.g.n
         vg, vc = self.ctx.zeros(n), self.ctx.zeros(n)
         last = min(iters, -(-len(self.cams) // self.views_per_step))
         for it in range(iters):
             self.step((vg, vc) if it >= iters - last else None)
+        self.ctx.check_flags()
         return vg, vc
 
     def transform(self):
@@ -138,6 +141,13 @@ class Stage1Direct:
 
     def transform(self):
         return self.dmu, self.dq
+
+    def run(self, iters: int):
+        """`iters` iterations, then the device flags are checked (GS3Error on
+        a pair-list overflow or a non-finite loss)."""
+        for _ in range(iters):
+            self.step()
+        self.ctx.check_flags()
 
 
 class Stage2:
@@ -224,6 +234,14 @@ class Stage2:
             self.control()
         return v
 
+    def run(self, iters: int):
+        """`iters` iterations, then the device flags are checked (GS3Error on
+        a pair-list overflow, which Stage 2's growth can cause, or a
+        non-finite loss)."""
+        for _ in range(iters):
+            self.step()
+        self.ctx.check_flags()
+
     def control(self):
         """Quantity control at the end of an epoch: split the additional
         Gaussians above tau_grad, then drop those below opacity tau_alpha."""
@@ -252,11 +270,11 @@ def warmup(ctx: gs3.Context, points, iters: int = 3000, lr: float = 0.002, betas
     dmu, dq = ctx.empty(n, 3), ctx.empty(n, 4)
     loss = ctx.empty(1)
     gmu, gq = ctx.empty(n, 3), ctx.empty(n, 4)
-    ctx.ntc_prepare(points)          # the warm-up points stay fixed
+    tok = ctx.ntc_prepare(points)    # the warm-up points stay fixed
     for _ in range(iters):
-        ctx.ntc_forward(points, dmu, dq)
+        ctx.ntc_forward(points, dmu, dq, tok)
         gs3.gs3_warmup_loss(ctx.h, dmu, dq, loss, gmu, gq)
-        ctx.ntc_backward(points, gmu, gq)
+        ctx.ntc_backward(points, gmu, gq, tok)
         ctx.ntc_step(lr, betas[0], betas[1], eps)
     return loss
 

@@ -69,9 +69,8 @@ def test_ntc_forward_backward(precision, n, prepared):
     assert near.mean() < 0.02, near.mean()
     g_mu[near] = 0.0
     g_q[near] = 0.0
-    if prepared:
-        ctx.ntc_prepare(m)
-    ctx.ntc_backward(m, cuda(g_mu), cuda(g_q))
+    tok = ctx.ntc_prepare(m) if prepared else 0
+    ctx.ntc_backward(m, cuda(g_mu), cuda(g_q), tok)
     grad = ctx.ntc_grads().cpu().numpy()
     ref_g = ontc.backward(spec, params, cache, g_mu, g_q, precision)
     t = spec.n_table
@@ -152,15 +151,15 @@ def test_prepared_backward_is_deterministic_and_accumulates():
     gm, gq = cuda(rng.normal(size=(n, 3)).astype(np.float32)), cuda(rng.normal(size=(n, 4)).astype(np.float32))
     ctx = ntc_ctx(cfg, n, "f16")
     ctx.ntc_load(params)
-    ctx.ntc_prepare(means)
-    ctx.ntc_backward(means, gm, gq)
+    tok = ctx.ntc_prepare(means)
+    ctx.ntc_backward(means, gm, gq, tok)
     a = ctx.ntc_grads().cpu().numpy()
     ctx.ntc_zero_grads()
-    ctx.ntc_backward(means, gm, gq)
+    ctx.ntc_backward(means, gm, gq, tok)
     b = ctx.ntc_grads().cpu().numpy()
     t = spec.n_table
     assert np.array_equal(a[:t], b[:t])          # the table part has a fixed summation order
-    ctx.ntc_backward(means, gm, gq)
+    ctx.ntc_backward(means, gm, gq, tok)
     c = ctx.ntc_grads().cpu().numpy()
     assert rel_err(c, 2 * b.astype(np.float64)) < 1e-5
     ctx.close()
@@ -179,12 +178,12 @@ def test_backward_reuses_the_forward_encoding(precision):
     gm, gq = cuda(rng.normal(size=(n, 3)).astype(np.float32)), cuda(rng.normal(size=(n, 4)).astype(np.float32))
     ctx = ntc_ctx(cfg, n, precision)
     ctx.ntc_load(params)
-    ctx.ntc_prepare(means)
-    ctx.ntc_forward(means)
-    ctx.ntc_backward(means, gm, gq)          # encoding from the forward
+    tok = ctx.ntc_prepare(means)
+    ctx.ntc_forward(means, token=tok)
+    ctx.ntc_backward(means, gm, gq, tok)     # encoding from the forward
     a = ctx.ntc_grads().cpu().numpy()
     ctx.ntc_load(params)                     # same parameters; the kept encoding is dropped
-    ctx.ntc_backward(means, gm, gq)          # encoding recomputed
+    ctx.ntc_backward(means, gm, gq, tok)     # encoding recomputed
     b = ctx.ntc_grads().cpu().numpy()
     t = spec.n_table
     assert np.array_equal(a[:t], b[:t])
