@@ -223,3 +223,152 @@ def relu_ambiguous(spec: NTCSpec, params: np.ndarray, means: np.ndarray, precisi
         x_err = acc_rel * s
     flag &= inside
     return flag
+
+
+# ---------------------------------------------------------------------------
+# Error bounds of a float32-accumulating implementation with the same storage
+# roundings (mixed precision of Suppl. Sec. A: tables, weights and
+# activations stored in FP16 / BF16, products and sums in FP32).
+#
+# Not a step of the method: a numerical-analysis bound the parity tests use.
+# A sum of m float32 terms carries at most gamma_m = m 2^-24 / (1 - m 2^-24)
+# times the sum of the terms' magnitudes of rounding error (any order).  For
+# the long sums over points and table contributions the probabilistic bound
+# of Higham and Mary ("A new approach to probabilistic rounding error
+# analysis", SIAM J. Sci. Comput. 41, 2019) is used instead: lambda sqrt(m) u
+# with lambda = 8, which fails with probability below 2 exp(-32) per sum;
+# for m <= 64 the two coincide (8 sqrt(m) >= m).  A
+# stored value is rounded from the float32 result; it can differ from the
+# emulation's rounding of the exact value only when a rounding midpoint of
+# the storage type lies within that error, and then by the spacing there.
+# The bounds propagate these through the layers with the emulation's ReLU
+# masks (points whose masks could differ are set aside by relu_ambiguous).
+# ---------------------------------------------------------------------------
+
+def _gamma(m) -> float:
+    """Relative rounding-error bound of a float32 sum of m terms: m u for
+    m <= 64, 8 sqrt(m) u beyond (u = 2^-24), with second-order slack."""
+    u = 2.0 ** -24
+    m = np.asarray(m, np.float64)
+    return np.minimum(m, 8.0 * np.sqrt(m)) * u * (1.0 + 1e-3)
+
+
+def _neighbours(r, precision: str):
+    """Representable neighbours below and above the stored values r."""
+    r = np.asarray(r, np.float64)
+    if precision == "f16":
+        h = r.astype(np.float16)
+        dn = np.nextafter(h, np.float16(-np.inf)).astype(np.float64)
+        up = np.nextafter(h, np.float16(np.inf)).astype(np.float64)
+        return dn, up
+    # bfloat16: the upper 16 bits of a float32; step the 16-bit pattern
+    f = r.astype(np.float32).view(np.uint32) >> 16
+    neg = (f & 0x8000) != 0
+    mag = f & 0x7FFF
+    toward_inf = np.where(neg, np.where(mag == 0, 0x0001 | 0x8000, f - 1), f + 1)
+    toward_minf = np.where(neg, f + 1, np.where(mag == 0, 0x8001, f - 1))
+    cv = lambda b: (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return cv(toward_minf), cv(toward_inf)
+
+
+def _stored_error(exact, err, precision: str):
+    """Bound on |rs(exact + d) - rs(exact)| for |d| <= err (elementwise)."""
+    if precision == "f32":
+        return np.asarray(err, np.float64)
+    exact = np.asarray(exact, np.float64)
+    r = round_storage(exact, precision)
+    dn, up = _neighbours(r, precision)
+    gap = np.maximum(up - r, r - dn)
+    # nearest midpoint between r and a neighbour
+    dist = np.minimum(np.abs(exact - 0.5 * (r + up)), np.abs(exact - 0.5 * (r + dn)))
+    reach = dist <= err
+    return np.where(reach, np.where(err < gap, gap, err + gap), 0.0)
+
+
+def mixed_precision_bounds(spec: NTCSpec, params: np.ndarray, means: np.ndarray, d_dmu, d_dq,
+                           precision: str = "f32"):
+    """Bounds (per output (n, 7), per parameter (num_params,)) on the
+    difference between a float32-accumulating forward / backward with the
+    storage roundings of `precision` and forward() / backward() here."""
+    table, W1, W2, W3 = spec.split(params)
+    rs = lambda a: round_storage(a, precision)
+    inside, rows, wts = corners(spec, means)
+    tab = rs(table)
+    n = means.shape[0]
+    F = spec.F
+    # encoding: 8 weighted corners per level; weights are products of three
+    # float32 fractions (2 roundings), so 11 roundings per term in all
+    enc = np.zeros((n, spec.in_dim))
+    mag = np.zeros((n, spec.in_dim))
+    for l in range(spec.L):
+        for c in range(8):
+            t = wts[l][:, c:c + 1] * tab[rows[l][:, c]]
+            enc[:, F * l:F * (l + 1)] += t
+            mag[:, F * l:F * (l + 1)] += np.abs(t)
+    B_enc = _stored_error(enc, _gamma(11) * mag, precision)
+    enc_s = rs(enc)
+    W1s, W2s, W3s = rs(W1), rs(W2), rs(W3)
+    # forward layers
+    z1 = enc_s @ W1s.T
+    B_z1 = B_enc @ np.abs(W1s).T + _gamma(spec.in_dim) * (np.abs(enc_s) @ np.abs(W1s).T)
+    m1 = z1 > 0
+    h1 = np.maximum(z1, 0.0)
+    B_h1 = _stored_error(h1, np.where(m1, B_z1, 0.0), precision)
+    h1s = rs(h1)
+    z2 = h1s @ W2s.T
+    B_z2 = B_h1 @ np.abs(W2s).T + _gamma(spec.hidden) * (np.abs(h1s) @ np.abs(W2s).T)
+    m2 = z2 > 0
+    h2 = np.maximum(z2, 0.0)
+    B_h2 = _stored_error(h2, np.where(m2, B_z2, 0.0), precision)
+    h2s = rs(h2)
+    B_out = B_h2 @ np.abs(W3s).T + _gamma(spec.hidden) * (np.abs(h2s) @ np.abs(W3s).T)
+    B_out[~inside] = 0.0
+    # backward: the output gradient is the caller's float32 value, rounded to
+    # the storage significand identically on both sides
+    rg = lambda a: round_significand(a, precision)
+    dout = np.concatenate([np.asarray(d_dmu, np.float64), np.asarray(d_dq, np.float64)], axis=1)
+    dout[~inside] = 0.0
+    dout = rg(dout)
+    a_out = np.abs(dout)
+    dW3 = a_out.T @ B_h2 + _gamma(n) * (a_out.T @ np.abs(h2s))
+    e2 = (a_out @ np.abs(W3s)) * _gamma(spec.out_dim)
+    dh2 = (dout @ W3s) * m2
+    B_dh2 = _significand_error(dh2, e2 * m2, precision)
+    dh2s = rg(dh2)
+    dW2 = np.abs(dh2s).T @ B_h1 + B_dh2.T @ np.abs(h1s) + _gamma(n) * (np.abs(dh2s).T @ np.abs(h1s))
+    e1 = (B_dh2 @ np.abs(W2s) + _gamma(spec.hidden) * (np.abs(dh2s) @ np.abs(W2s))) * m1
+    dh1 = (dh2s @ W2s) * m1
+    B_dh1 = _significand_error(dh1, e1, precision)
+    dh1s = rg(dh1)
+    dW1 = np.abs(dh1s).T @ B_enc + B_dh1.T @ np.abs(enc_s) + _gamma(n) * (np.abs(dh1s).T @ np.abs(enc_s))
+    B_denc = B_dh1 @ np.abs(W1s) + _gamma(spec.hidden) * (np.abs(dh1s) @ np.abs(W1s))
+    denc = dh1s @ W1s
+    # table entries: sum over their contributions in float32 (at most n 8 terms)
+    B_tab = np.zeros((int(spec.offsets[-1]), F))
+    mag_t = np.zeros((int(spec.offsets[-1]), F))
+    cnt = np.zeros(int(spec.offsets[-1]))
+    for l in range(spec.L):
+        for c in range(8):
+            w = wts[l][:, c:c + 1]
+            np.add.at(B_tab, rows[l][:, c], w * B_denc[:, F * l:F * (l + 1)])
+            np.add.at(mag_t, rows[l][:, c], np.abs(w * denc[:, F * l:F * (l + 1)]))
+            np.add.at(cnt, rows[l][:, c], inside.astype(np.float64))
+    B_tab += _gamma(cnt + 3)[:, None] * mag_t
+    B_grad = np.concatenate([B_tab.reshape(-1), dW1.reshape(-1), dW2.reshape(-1), dW3.reshape(-1)])
+    return B_out, B_grad
+
+
+def _significand_error(exact, err, precision: str):
+    """As _stored_error for round_significand (significand width of the
+    storage type, unbounded exponent)."""
+    exact = np.asarray(exact, np.float64)
+    err = np.asarray(err, np.float64)
+    if precision == "f32":
+        return err
+    bits = {"f16": 11, "bf16": 8}[precision]
+    m, e = np.frexp(exact)
+    ulp = np.ldexp(1.0, e - bits)            # spacing of the rounded significand at |exact|
+    r = round_significand(exact, precision)
+    dist = np.abs(np.abs(exact - r) - 0.5 * ulp)
+    reach = (dist <= err) & (exact != 0)
+    return np.where(reach, np.where(err < ulp, ulp, err + ulp), np.where(exact == 0, err, 0.0))

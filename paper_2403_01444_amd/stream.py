@@ -79,6 +79,7 @@ class StreamTrainer:
         t1 = time.perf_counter()
         st2 = train.Stage2(ctx, baked, self.cams, targets, vg, vc, max_add=self.max_add, seed=self.seed + f)
         st2.run(self.s2)
+        self.last_stage2 = st2
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         p1 = float(np.mean([train.psnr(ctx.render(baked, c), t) for c, t in zip(self.novel, novel_targets)]))

@@ -33,17 +33,42 @@ def scene():
     ctx.close()
 
 
-def test_fullsize_pairs_and_ranges_bit_exact(scene):
+@pytest.fixture(scope="module")
+def oracle_pairs(scene):
+    ctx, g, gg, cams, dmu, dq = scene
+    return orc.sorted_pairs(g, cams[7], dmu, dq)
+
+
+def test_fullsize_pairs_and_ranges_bit_exact(scene, oracle_pairs):
     ctx, g, gg, cams, dmu, dq = scene
     cam = cams[7]
     ctx.render(gg, cam, cuda(dmu), cuda(dq))
     keys, vals = ctx.debug_pairs()
     ranges = ctx.debug_ranges(cam)
-    rk, rv, rr = orc.sorted_pairs(g, cam, dmu, dq)
+    rk, rv, rr = oracle_pairs
     assert keys.shape[0] == rk.shape[0] and rk.shape[0] > 10_000_000
     assert np.array_equal(ranges.cpu().numpy().view(np.uint32), rr)
     assert np.array_equal(vals.cpu().numpy().view(np.uint32), rv)
     assert np.array_equal(keys.cpu().numpy().view(np.uint64), rk)
+
+
+def test_fullsize_radix64_pairs_bit_exact(scene, oracle_pairs):
+    """The 64-bit (tile | depth) LSD radix sort of every pair at full size
+    (34M pairs, 45-bit keys, the large-input code path of the sort): keys,
+    Gaussian indices and tile ranges bit-exact."""
+    from paper_2403_01444_amd import gs3
+    _, g, gg, cams, dmu, dq = scene
+    cam = cams[7]
+    ctx = gs3.Context(g.n, 40_000_000, 1352, 1014, num_slots=1, sort_mode="radix64")
+    ctx.render(gg, cam, cuda(dmu), cuda(dq))
+    keys, vals = ctx.debug_pairs()
+    ranges = ctx.debug_ranges(cam)
+    rk, rv, rr = oracle_pairs
+    assert keys.shape[0] == rk.shape[0] and rk.shape[0] > 10_000_000
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), rk)
+    assert np.array_equal(vals.cpu().numpy().view(np.uint32), rv)
+    assert np.array_equal(ranges.cpu().numpy().view(np.uint32), rr)
+    ctx.close()
 
 
 def test_fullsize_image(scene):

@@ -273,3 +273,94 @@ def test_warmup_fixed_point_and_gradient():
     assert abs(L - Lt.item()) < 1e-13
     np.testing.assert_allclose(gm, a.grad.numpy(), atol=1e-15)
     np.testing.assert_allclose(gq, b.grad.numpy(), atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# error bounds of mixed precision (FP16 / BF16 storage, FP32 arithmetic)
+# ---------------------------------------------------------------------------
+
+def _f32_simulation(spec, params, means, g_mu, g_q, precision):
+    """The NTC forward and backward in float32 numpy arithmetic (another
+    summation order than the float64 emulation) with the same storage
+    roundings: an independent instance of what the bounds must cover."""
+    f = np.float32
+    rs = lambda a: ontc.round_storage(a, precision).astype(f)
+    rg = lambda a: ontc.round_significand(np.asarray(a, np.float64), precision).astype(f)
+    table, W1, W2, W3 = spec.split(params)
+    inside, rows, wts = ontc.corners(spec, means)
+    xn = (np.asarray(means, f) - spec.aabb_min) * spec.inv_ext
+    tab = rs(table)
+    n = means.shape[0]
+    enc = np.zeros((n, spec.in_dim), f)
+    for l, N in enumerate(spec.res):
+        p = xn * f(N)
+        fr = (p - np.minimum(np.floor(p), f(N - 1))).astype(f)
+        for c in reversed(range(8)):
+            w = np.ones(n, f)
+            for k in range(3):
+                w = (w * (fr[:, k] if (c >> k) & 1 else f(1) - fr[:, k])).astype(f)
+            enc[:, 2 * l:2 * l + 2] += (w[:, None] * tab[rows[l][:, c]]).astype(f)
+    encs = rs(enc)
+    W1s, W2s, W3s = rs(W1), rs(W2), rs(W3)
+    h1 = rs(np.maximum(encs @ W1s.T, f(0)))
+    h2 = rs(np.maximum(h1 @ W2s.T, f(0)))
+    out = h2 @ W3s.T
+    out[~inside] = 0
+    dout = np.concatenate([g_mu, g_q], 1).astype(f)
+    dout[~inside] = 0
+    dout = rg(dout)
+    dW3 = dout.T @ h2
+    dh2 = rg((dout @ W3s) * (h2 > 0))
+    dW2 = dh2.T @ h1
+    dh1 = rg((dh2 @ W2s) * (h1 > 0))
+    dW1 = dh1.T @ encs
+    denc = dh1 @ W1s
+    dt = np.zeros((int(spec.offsets[-1]), 2), f)
+    for l in reversed(range(spec.L)):
+        for c in range(8):
+            np.add.at(dt, rows[l][:, c], (wts[l][:, c:c + 1].astype(f) * denc[:, 2 * l:2 * l + 2]).astype(f))
+    return out, np.concatenate([dt.reshape(-1), dW1.reshape(-1), dW2.reshape(-1), dW3.reshape(-1)])
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16", "bf16"])
+def test_mixed_precision_bounds_cover_a_float32_computation(spec, precision):
+    """A float32 computation with the same storage roundings stays within
+    the bounds at every output and every parameter gradient, and the bounds
+    are tight enough to matter: one storage step planted in a stored value
+    where no rounding flip was reachable exceeds them."""
+    cfg = synth.NTCConfig()
+    rng = np.random.default_rng(7)
+    params = synth.ntc_init_params(cfg, 1).astype(np.float64)
+    params[:spec.n_table] = rng.normal(scale=0.05, size=spec.n_table)
+    params = params.astype(np.float32)
+    n = 3000
+    means = rng.uniform(-1.3, 1.3, size=(n, 3)).astype(np.float32)
+    g_mu = (rng.normal(size=(n, 3)) * 1e-3).astype(np.float32)
+    g_q = (rng.normal(size=(n, 4)) * 1e-3).astype(np.float32)
+    near = ontc.relu_ambiguous(spec, params, means, precision)
+    g_mu[near] = 0
+    g_q[near] = 0
+    dmu, dq, cache = ontc.forward(spec, params, means, precision)
+    ref = np.concatenate([dmu, dq], 1)
+    ref[~cache["inside"]] = 0
+    ref_g = ontc.backward(spec, params, cache, g_mu, g_q, precision)
+    B_out, B_g = ontc.mixed_precision_bounds(spec, params, means, g_mu, g_q, precision)
+    out, grad = _f32_simulation(spec, params, means, g_mu, g_q, precision)
+    ok = ~near
+    e_out = np.abs(out.astype(np.float64) - ref)
+    assert np.all(e_out[ok] <= B_out[ok] + 2.0 ** -24 * np.abs(ref[ok])), (e_out[ok] / (B_out[ok] + 1e-30)).max()
+    e_g = np.abs(grad.astype(np.float64) - ref_g)
+    assert np.all(e_g <= B_g + 2.0 ** -24 * np.abs(ref_g)), (e_g / (B_g + 1e-30)).max()
+    if precision != "f32":
+        # a planted one-step error in h2 of a point whose outputs carry no
+        # flip allowance shows up beyond the bound
+        tight = np.nonzero(ok & cache["inside"] & np.all(B_out < 1e-5 * np.abs(ref).max(), axis=1))[0]
+        assert tight.size > 0
+        i = int(tight[0])
+        _, _, _, W3 = spec.split(params)
+        W3s = ontc.round_storage(W3, precision)
+        j = int(np.argmax(np.abs(W3s[0]) * (cache["h2"][i] > 0)))
+        h = cache["h2"][i, j]
+        dn, up = ontc._neighbours(np.array([h]), precision)
+        planted = ref[i, 0] + (up[0] - h) * W3s[0, j]
+        assert abs(planted - ref[i, 0]) > B_out[i, 0]
