@@ -190,7 +190,11 @@ def relu_ambiguous(spec: NTCSpec, params: np.ndarray, means: np.ndarray, precisi
     an input x_k (encoding or h1) is also at risk when its float32 value,
     uncertain by acc_rel x sum |terms| as well, straddles a rounding boundary
     of the storage type; the point is flagged when replacing x_k by the other
-    rounding would change the sign of some z_j.  Returns a boolean mask.
+    rounding would change the sign of some z_j.  Several inputs of one point
+    can take their other rounding together, so the point is also flagged when
+    |z_j| is within the bound of _forward_bounds (every reachable storage step
+    of the layer's inputs plus the accumulation error).  Returns a boolean
+    mask.
     """
     table, W1, W2, W3 = spec.split(params)
     rs = lambda a: round_storage(a, precision)
@@ -221,6 +225,9 @@ def relu_ambiguous(spec: NTCSpec, params: np.ndarray, means: np.ndarray, precisi
                     flag[ii[np.any(np.sign(zz) != np.sign(z[ii]), axis=1)]] = True
         x_val = np.maximum(z, 0.0)
         x_err = acc_rel * s
+    fb = _forward_bounds(spec, params, means, precision)
+    flag |= np.any(np.abs(fb["z1"]) <= fb["B_z1"], axis=1)
+    flag |= np.any(np.abs(fb["z2"]) <= fb["B_z2"], axis=1)
     flag &= inside
     return flag
 
@@ -285,11 +292,12 @@ def _stored_error(exact, err, precision: str):
     return np.where(reach, np.where(err < gap, gap, err + gap), 0.0)
 
 
-def mixed_precision_bounds(spec: NTCSpec, params: np.ndarray, means: np.ndarray, d_dmu, d_dq,
-                           precision: str = "f32"):
-    """Bounds (per output (n, 7), per parameter (num_params,)) on the
-    difference between a float32-accumulating forward / backward with the
-    storage roundings of `precision` and forward() / backward() here."""
+def _forward_bounds(spec: NTCSpec, params: np.ndarray, means: np.ndarray, precision: str):
+    """The forward of a float32-accumulating implementation with the storage
+    roundings of `precision`, next to the bounds on how far its values can
+    sit from the emulation's: encoding (B_enc), pre-activations of both
+    hidden layers (B_z1, B_z2, with the emulation's ReLU masks for h1),
+    stored activations (B_h1, B_h2) and outputs (B_out)."""
     table, W1, W2, W3 = spec.split(params)
     rs = lambda a: round_storage(a, precision)
     inside, rows, wts = corners(spec, means)
@@ -308,7 +316,6 @@ def mixed_precision_bounds(spec: NTCSpec, params: np.ndarray, means: np.ndarray,
     B_enc = _stored_error(enc, _gamma(11) * mag, precision)
     enc_s = rs(enc)
     W1s, W2s, W3s = rs(W1), rs(W2), rs(W3)
-    # forward layers
     z1 = enc_s @ W1s.T
     B_z1 = B_enc @ np.abs(W1s).T + _gamma(spec.in_dim) * (np.abs(enc_s) @ np.abs(W1s).T)
     m1 = z1 > 0
@@ -323,6 +330,23 @@ def mixed_precision_bounds(spec: NTCSpec, params: np.ndarray, means: np.ndarray,
     h2s = rs(h2)
     B_out = B_h2 @ np.abs(W3s).T + _gamma(spec.hidden) * (np.abs(h2s) @ np.abs(W3s).T)
     B_out[~inside] = 0.0
+    return dict(inside=inside, rows=rows, wts=wts, enc_s=enc_s, B_enc=B_enc, W=(W1s, W2s, W3s), z1=z1, B_z1=B_z1,
+                m1=m1, h1s=h1s, B_h1=B_h1, z2=z2, B_z2=B_z2, m2=m2, h2s=h2s, B_h2=B_h2, B_out=B_out)
+
+
+def mixed_precision_bounds(spec: NTCSpec, params: np.ndarray, means: np.ndarray, d_dmu, d_dq,
+                           precision: str = "f32"):
+    """Bounds (per output (n, 7), per parameter (num_params,)) on the
+    difference between a float32-accumulating forward / backward with the
+    storage roundings of `precision` and forward() / backward() here."""
+    fb = _forward_bounds(spec, params, means, precision)
+    inside, rows, wts = fb["inside"], fb["rows"], fb["wts"]
+    enc_s, B_enc = fb["enc_s"], fb["B_enc"]
+    W1s, W2s, W3s = fb["W"]
+    m1, h1s, B_h1, m2, h2s, B_h2 = fb["m1"], fb["h1s"], fb["B_h1"], fb["m2"], fb["h2s"], fb["B_h2"]
+    B_out = fb["B_out"]
+    n = means.shape[0]
+    F = spec.F
     # backward: the output gradient is the caller's float32 value, rounded to
     # the storage significand identically on both sides
     rg = lambda a: round_significand(a, precision)

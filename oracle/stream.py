@@ -64,11 +64,13 @@ def _vspace(g, cam, d_uv):
     return np.where(vis, stage2.vspace_grad(d_uv, cam.width, cam.height), 0.0), vis.astype(np.float64)
 
 
-def stage1_tracked(spec, params0, g, cams, targets, views, lam=0.2, lr=0.002, betas=(0.9, 0.99), eps=1e-15):
-    """Stage 1 (as stage1.ntc_stage1) with the view-space gradient summed
-    over the final min(iterations, views) iterations.  Returns the final
-    float32 parameters, the per-iteration (parameters, gradient), and
-    (total, count)."""
+def stage1_tracked(spec, params0, g, cams, targets, views, lam=0.2, lr=0.002, betas=(0.9, 0.99), eps=1e-15,
+                   perturb=None):
+    """Stage 1 (as stage1.ntc_stage1, including its `perturb`) with the
+    view-space gradient summed over the final min(iterations, views)
+    iterations.  Returns the final float32 parameters, the per-iteration
+    (parameters, gradient), and (total, count)."""
+    pert = stage1._perturber(perturb)
     p = np.asarray(params0, np.float32).astype(np.float64)
     m, v = np.zeros_like(p), np.zeros_like(p)
     vg, vc = np.zeros(g.n), np.zeros(g.n)
@@ -78,14 +80,14 @@ def stage1_tracked(spec, params0, g, cams, targets, views, lam=0.2, lr=0.002, be
         dmu, dq, cache = ontc.forward(spec, p, g.means)
         dmu32, dq32 = dmu.astype(np.float32), dq.astype(np.float32)
         cam = cams[view]
-        img = orc.render(g, cam, dmu32, dq32)["image"]
+        img = pert(orc.render(g, cam, dmu32, dq32)["image"])
         L, dL = oloss.stage1_loss(img, np.asarray(targets[view], np.float64), lam)
         gr = orc.render_backward(g, cam, dL, dmu32, dq32)
         if t > len(views) - last:
             a, b = _vspace_transformed(g, cam, gr["d_uv"], dmu32, dq32)
             vg += a
             vc += b
-        grad = ontc.backward(spec, p, cache, gr["d_dmu"], gr["d_dq"])
+        grad = pert(ontc.backward(spec, p, cache, gr["d_dmu"], gr["d_dq"]))
         p, m, v = oopt.adam(p, grad, m, v, t, lr, betas[0], betas[1], eps)
         p = p.astype(np.float32).astype(np.float64)
         kept.append((p.astype(np.float32), grad))
@@ -158,11 +160,12 @@ def stage2_run(base: Gaussians, cams, targets, vg, vc, iters, views, rng, lam=0.
     return add, spawned, decisions
 
 
-def frame(spec, warm_params, g: Gaussians, cams, targets, views1, views2, rng, s2_iters, **kw):
+def frame(spec, warm_params, g: Gaussians, cams, targets, views1, views2, rng, s2_iters, perturb=None, **kw):
     """Stage 1, bake, Stage 2 of one frame.  Returns a dict with the Stage-1
     parameters (per iteration), the baked Gaussians carried to the next frame,
-    the additional Gaussians and the Stage-2 decisions."""
-    p, kept, (vg, vc) = stage1_tracked(spec, warm_params, g, cams, targets, views1)
+    the additional Gaussians and the Stage-2 decisions.  `perturb` perturbs
+    Stage 1 as in stage1.ntc_stage1."""
+    p, kept, (vg, vc) = stage1_tracked(spec, warm_params, g, cams, targets, views1, perturb=perturb)
     dmu, dq, _ = ontc.forward(spec, p.astype(np.float64), g.means)
     mu, q, sh = shrot.bake(g, dmu.astype(np.float32), dq.astype(np.float32))
     baked = Gaussians(_f32(mu), _f32(q), _f32(g.log_scales), _f32(g.opacity_logits), _f32(sh), g.sh_degree)

@@ -47,3 +47,32 @@ def check_grads(grads, ref, label, tol=1e-3, keys=None):
         print(f"[parity] {label} {k}: error {e_keep:.2e} over {keep.mean():.4f} of the Gaussians, "
               f"{e_all:.2e} over all (bar {tol:g})", flush=True)
         assert e_keep < tol, (k, e_keep)
+
+
+def adam_determined(m_prev, v_prev, step, g, lr, b1, b2, eps, delta, tol):
+    """Parameters whose Adam step (Kingma and Ba, bias-corrected; moments
+    m_prev, v_prev before step number `step`) moves by at most `tol` when
+    their gradient g moves by up to `delta` (probed at g +- delta and
+    g +- delta / 2).  Adam normalises each step to about lr, so a parameter
+    whose gradient is within reach of zero, or whose first moment nearly
+    cancels, can step either way on a gradient error of that size; the
+    parameter comparisons of the trajectory tests are made where it cannot."""
+    def update(gg):
+        m = b1 * m_prev + (1 - b1) * gg
+        v = b2 * v_prev + (1 - b2) * gg * gg
+        return lr * (m / (1 - b1 ** step)) / (np.sqrt(v / (1 - b2 ** step)) + eps)
+    u0 = update(g)
+    dev = np.zeros_like(u0)
+    for f in (-1.0, -0.5, 0.5, 1.0):
+        dev = np.maximum(dev, np.abs(update(g + f * delta) - u0))
+    return dev <= tol
+
+
+def curve_bars(ref, members, margin=0.1):
+    """Per logged iteration, the allowed distance from the oracle's PSNR:
+    `margin` plus the spread (largest minus smallest) of the oracle's curve
+    and its float32-perturbed copies there.  Where the loop is well
+    conditioned the spread is far below the margin; where rounding alone
+    moves it (Adam oscillating near the optimum) the bar widens with it."""
+    allc = np.vstack([np.asarray(ref, np.float64)] + [np.asarray(m, np.float64) for m in members])
+    return margin + allc.max(axis=0) - allc.min(axis=0)

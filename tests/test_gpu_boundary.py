@@ -7,6 +7,7 @@ import math
 import numpy as np
 import pytest
 
+from oracle import ntc as ontc
 from oracle import raster as orc
 from paper_2403_01444_amd import synth
 
@@ -196,8 +197,11 @@ def test_stage1_loop_reports_pair_overflow():
 
 def test_autograd_wrappers_give_the_explicit_calls_gradient():
     """NTCQuery -> Render -> Loss with loss.backward() accumulates the same
-    NTC gradient as the explicit calls, bit for bit (deterministic gradient
-    records in the renderer, prepared NTC backward), and the same loss."""
+    NTC gradient as the explicit calls and the same loss.  The table gradient
+    is bit for bit the same (deterministic gradient records in the renderer,
+    per-entry sums over the prepared contribution lists); the MLP weight
+    gradient sums per-workgroup partials with float atomics, whose order
+    varies, so it agrees to float32 summation order (1e-6 of its largest)."""
     from paper_2403_01444_amd import autograd as ag
     from paper_2403_01444_amd import gs3
     g, cams, _, nxt = synth.workload("small-2k-64px", seed=4)
@@ -226,6 +230,8 @@ def test_autograd_wrappers_give_the_explicit_calls_gradient():
     loss.backward()
     got = ctx.ntc_grads().cpu().numpy()
     assert loss.item() == ref_loss
-    assert np.array_equal(got, ref)
-    assert np.abs(ref).max() > 0
+    t = ontc.NTCSpec(cfg).n_table
+    assert np.array_equal(got[:t], ref[:t])
+    assert np.abs(got[t:] - ref[t:]).max() <= 1e-6 * np.abs(ref[t:]).max()
+    assert np.abs(ref[:t]).max() > 0 and np.abs(ref[t:]).max() > 0
     ctx.close()
