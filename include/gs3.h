@@ -311,6 +311,22 @@ gs3_status gs3_spawn(gs3_ctx* ctx, const gs3_gaussians* src, const uint32_t* idx
 gs3_status gs3_loss(gs3_ctx* ctx, const float* image, const float* target, int32_t height,
                     int32_t width, float lambda_dssim, float* loss_dev, float* d_image);
 
+/* gs3_loss for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * context, no allocation of any kind.  The kernels' scratch (SSIM partial
+ * maps, per-block partial sums) lives in a static device array of the
+ * library, about 76 MB, that every GPU the library runs on holds until the
+ * process ends.  Same arguments and results as gs3_loss, launched on
+ * `hip_stream` (a hipStream_t; NULL = the default stream) on the current
+ * device.  Limits: 1 <= height, width <= 4096 and height x width <=
+ * 2,097,152 (1920 x 1080 fits); larger images, NULL pointers or lambda
+ * outside [0, 1] return GS3_EINVAL, a failed HIP call GS3_EHIP.  All calls
+ * on one GPU share the array: calls that overlap on one GPU (other streams,
+ * other host threads) race and must be serialised by the caller.  A
+ * non-finite loss is written as computed; no flag is raised. */
+gs3_status gs3_loss_noalloc(const float* image, const float* target, int32_t height, int32_t width,
+                            float lambda_dssim, float* loss_dev, float* d_image, void* hip_stream);
+
 /* In-place Adam on n float32 parameters (bias correction with `step` >= 1);
  * used by the direct per-Gaussian optimisation comparator. */
 gs3_status gs3_adam(gs3_ctx* ctx, float* param, const float* grad, float* m, float* v, int64_t n,

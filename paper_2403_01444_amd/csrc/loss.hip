@@ -10,6 +10,9 @@
 // filtered mean, E[x^2] and E[xy] at each pixel.  Backward: the adjoint of a
 // zero-padded correlation with a symmetric window is the same correlation,
 // so the three partial maps are filtered again and combined with x and y.
+#include <mutex>
+
+#include "../../include/gs3.h"
 #include "kernels.h"
 
 namespace gs3 {
@@ -318,3 +321,58 @@ void loss_forward_backward(const Launch& L, const float* x, const float* y, int 
 }
 
 }  // namespace gs3
+
+// ---- Eq. 6 without allocation ---------------------------------------------
+// gs3_loss_noalloc runs the kernels of gs3_loss with their scratch (the SSIM
+// partial maps, the per-block partial sums and a flag word) in `scratch`, a
+// file-scope device array: every GPU the library runs on holds its own copy
+// until the process ends, and every call on that GPU shares it.  Host code
+// never passes the array's name to a kernel (on the host it only stands for
+// the symbol): the device address comes from hipGetSymbolAddress, taken once
+// per device with that device current.
+namespace gs3 {
+namespace {
+constexpr int64_t kNaMaxPixels = int64_t(1) << 21;   // 2,097,152: 1920 x 1080 fits
+constexpr int kNaMaxSide = 4096;
+constexpr int64_t kNaMapFloats = 9 * kNaMaxPixels;   // loss_map_floats at the largest size
+// loss_blocks(H, W) <= max(3 ceil(W/32) ceil(H/32), ceil(3 H W / 256)); with
+// H W <= 2^21 and both sides <= 4096 the second term dominates: 24,576
+constexpr int64_t kNaMaxBlocks = 3 * kNaMaxPixels / 256;
+constexpr int64_t kNaFloats = kNaMapFloats + 2 * (2 * kNaMaxBlocks) + 64;
+constexpr int kNaMaxDevices = 64;
+
+static __device__ __align__(256) float scratch[kNaFloats];
+
+std::once_flag g_na_once[kNaMaxDevices];
+float* g_na_ptr[kNaMaxDevices];
+hipError_t g_na_err[kNaMaxDevices];
+}  // namespace
+}  // namespace gs3
+
+extern "C" gs3_status gs3_loss_noalloc(const float* image, const float* target, int32_t height, int32_t width,
+                                       float lambda_dssim, float* loss_dev, float* d_image, void* hip_stream) {
+    using namespace gs3;
+    if (!image || !target || !loss_dev || !d_image) return GS3_EINVAL;
+    if (height < 1 || width < 1 || height > kNaMaxSide || width > kNaMaxSide ||
+        (int64_t)height * width > kNaMaxPixels)
+        return GS3_EINVAL;
+    if (!(lambda_dssim >= 0.f && lambda_dssim <= 1.f)) return GS3_EINVAL;
+    if ((int64_t)loss_blocks(height, width) > kNaMaxBlocks) return GS3_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNaMaxDevices) return GS3_EHIP;
+    std::call_once(g_na_once[dev], [dev] {
+        void* ptr = nullptr;
+        g_na_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_na_ptr[dev] = g_na_err[dev] == hipSuccess ? static_cast<float*>(ptr) : nullptr;
+    });
+    if (g_na_err[dev] != hipSuccess || !g_na_ptr[dev]) return GS3_EHIP;
+    float* base = g_na_ptr[dev];
+    // every word the kernels read is written earlier in the same call (maps
+    // by the forward SSIM pass, block sums by each block), so nothing needs
+    // clearing; the flag word is only ever set and is not reported here
+    LossWork w{base, reinterpret_cast<double*>(base + kNaMapFloats), (int)kNaMaxBlocks};
+    int* flag = reinterpret_cast<int*>(base + kNaMapFloats + 4 * kNaMaxBlocks);
+    Launch L{static_cast<hipStream_t>(hip_stream), nullptr};
+    loss_forward_backward(L, image, target, height, width, lambda_dssim, w, loss_dev, d_image, flag);
+    return hipGetLastError() == hipSuccess ? GS3_OK : GS3_EHIP;
+}

@@ -70,7 +70,7 @@ EXPORTED = ("gs3_create", "gs3_destroy", "gs3_last_error", "gs3_set_stream", "gs
             "gs3_ntc_load", "gs3_ntc_save", "gs3_ntc_init", "gs3_ntc_state_bytes", "gs3_ntc_save_state",
             "gs3_ntc_load_state", "gs3_ntc_forward", "gs3_ntc_backward", "gs3_ntc_prepare", "gs3_ntc_step",
             "gs3_ntc_grads", "gs3_ntc_zero_grads", "gs3_warmup_loss", "gs3_render", "gs3_render_backward", "gs3_transform_bake", "gs3_select", "gs3_spawn",
-            "gs3_loss", "gs3_adam", "gs3_zero", "gs3_debug_counts", "gs3_debug_pairs", "gs3_debug_ranges",
+            "gs3_loss", "gs3_loss_noalloc", "gs3_adam", "gs3_zero", "gs3_debug_counts", "gs3_debug_pairs", "gs3_debug_ranges",
             "gs3_debug_gaussians", "gs3_debug_pixels", "gs3_check_flags", "gs3_workspace_bytes", "gs3_profile_enable",
             "gs3_profile_only", "gs3_profile_reset", "gs3_profile_query")
 
@@ -113,6 +113,7 @@ def lib():
         "gs3_select": [vp, vp, vp, i64, C.c_float, vp, C.POINTER(C.c_int64)],
         "gs3_spawn": [vp, C.POINTER(GaussiansC), vp, i64, vp, i32, vp, vp, vp, vp, vp],
         "gs3_loss": [vp, vp, vp, i32, i32, f32, vp, vp],
+        "gs3_loss_noalloc": [vp, vp, i32, i32, f32, vp, vp, vp],
         "gs3_adam": [vp, vp, vp, vp, vp, i64, i32, f32, f32, f32, f32],
         "gs3_zero": [vp, vp, i64],
         "gs3_debug_counts": [vp, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)],
@@ -368,6 +369,16 @@ def gs3_loss(h, image, target, height, width, lam, loss, d_image):
     N = 3 * height * width
     _check(h, lib().gs3_loss(h, _ptr(image, numel=N), _ptr(target, numel=N), height, width, lam, _ptr(loss),
                              _ptr(d_image, numel=N)))
+
+
+def gs3_loss_noalloc(image, target, height, width, lam, loss, d_image, stream_ptr: int = 0):
+    """gs3_loss without a context: scratch in the library's per-GPU static
+    array (no device allocation); launches on the given HIP stream."""
+    N = 3 * height * width
+    st = lib().gs3_loss_noalloc(_ptr(image, numel=N), _ptr(target, numel=N), height, width, lam, _ptr(loss),
+                                _ptr(d_image, numel=N), C.c_void_p(stream_ptr) if stream_ptr else None)
+    if st != GS3_OK:
+        raise GS3Error(st, "gs3_loss_noalloc failed")
 
 
 def gs3_adam(h, param, grad, m, v, step, lr, beta1, beta2, eps):
