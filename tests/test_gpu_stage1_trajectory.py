@@ -3,24 +3,35 @@
 256 x 256 views), float32 NTC from seeded parameters, 150 iterations in
 the seeded view order of reading C10.
 
-* The first three iterations, parameter by parameter: |p_gpu - p_oracle| <=
-  1e-3 x lr for every parameter whose oracle gradient stood clear of
-  rounding noise (>= 1e-3 of its tensor's largest) in each of those
-  iterations (Adam's early steps are nearly lr x sign(g), so an entry with a
-  noise-level gradient may step either way).
-* The held-out PSNR every 10 iterations within 0.1 dB of the oracle's curve
-  (tests/golden/stage1_ring-50k-256px.json, written by the script beside it
-  from the oracle alone).
+* Iterations 1-3, each from the oracle's state before it (parameters, Adam
+  moments and step loaded through gs3_ntc_load_state): the NTC gradient
+  within 1e-4 of its largest element (table and MLP separately), and the
+  parameters after the step within 1e-3 x lr wherever the oracle's Adam
+  step is determined to 0.5e-3 x lr by its gradient to that precision
+  (tests/parity.py: adam_determined).  Adam normalises every step to about
+  lr, so a parameter whose gradient is a near-cancelling sum can step
+  either way on a rounding-sized difference; those are reported, not
+  compared.
+* The held-out PSNR every 10 iterations of a 150-iteration run: within
+  0.1 dB of the oracle's curve plus the spread of the oracle's curve and
+  eight copies of its loop perturbed by float32-sized relative noise (1e-6
+  on the image and gradient of every iteration), all in
+  tests/golden/stage1_ring-50k-256px.json, written by the script beside it
+  from the oracle alone.  The first 50 iterations are conditioned (spread
+  a few hundredths of a dB); later the loop overfits its four views and
+  rounding alone moves it by tenths of a dB.
 """
 import importlib.util
 import json
 import os
+import struct
 
 import numpy as np
 import pytest
 
 from oracle import ntc as ontc
 from oracle import stage1 as ostage1
+from parity import adam_determined, curve_bars
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +49,15 @@ def _golden():
         return mod, json.load(f)
 
 
+def state_blob(header: bytes, step: int, p, m, v) -> bytes:
+    """A gs3_ntc_save_state blob: the context's own header with the Adam step
+    replaced (int64 after the 8-byte magic and the int64 parameter count),
+    then the float32 parameters and moments."""
+    h = bytearray(header)
+    struct.pack_into("<q", h, 16, int(step))
+    return bytes(h) + b"".join(np.ascontiguousarray(a, np.float32).tobytes() for a in (p, m, v))
+
+
 def test_ring50k_fp32_ntc_trajectory_tracks_the_oracle():
     from paper_2403_01444_amd import gs3, synth, train
     mod, gold = _golden()
@@ -45,8 +65,9 @@ def test_ring50k_fp32_ntc_trajectory_tracks_the_oracle():
     views = gold["views"]
     assert views == synth.view_schedule(len(cams), gold["iters"], gold["view_seed"])
     spec = ontc.NTCSpec(cfg)
-    # the oracle's first three iterations, live
-    first = ostage1.ntc_stage1(spec, p0, g, cams, targets, views[:3], keep_params=3)
+    lr, (b1, b2), eps = gold["lr"], gold["betas"], gold["eps"]
+    first = ostage1.ntc_stage1(spec, p0, g, cams, targets, views[:3], lam=gold["lambda"], lr=lr, betas=(b1, b2),
+                               eps=eps, keep_params=3)
     assert np.allclose(first["loss"], gold["loss"][:3], rtol=1e-12)
 
     ctx = gs3.Context(g.n, 1 << 24, 256, 256, ntc=cfg, precision="f32")
@@ -54,34 +75,58 @@ def test_ring50k_fp32_ntc_trajectory_tracks_the_oracle():
     gg = gs3.GaussiansGPU.from_host(g)
     tt = [torch.from_numpy(t).cuda() for t in targets]
     ht = torch.from_numpy(held_t).cuda()
-    st = train.Stage1NTC(ctx, gg, cams, tt, lam=gold["lambda"], lr=gold["lr"], betas=tuple(gold["betas"]),
-                         eps=gold["eps"], seed=gold["view_seed"])
+    st = train.Stage1NTC(ctx, gg, cams, tt, lam=gold["lambda"], lr=lr, betas=(b1, b2), eps=eps,
+                         seed=gold["view_seed"])
+    blob0 = ctx.ntc_save_state()
+    header = blob0[:len(blob0) - 12 * p0.size]
     t_split = spec.n_table
-    lr = gold["lr"]
-    measurable = np.ones(p0.size, bool)
+    parts = ((0, t_split, "table"), (t_split, p0.size, "MLP"))
+    zeros = np.zeros(p0.size)
+    for k in range(1, 4):
+        p_prev = p0.astype(np.float64) if k == 1 else first["params"][k - 2].astype(np.float64)
+        m_prev, v_prev = (zeros, zeros) if k == 1 else first["moments"][k - 2]
+        ctx.ntc_load_state(state_blob(header, k - 1, p_prev, m_prev, v_prev))
+        st.accumulate([views[k - 1]])
+        got_g = ctx.ntc_grads().cpu().numpy().astype(np.float64)
+        ctx.ntc_step(lr, b1, b2, eps)
+        got_p = ctx.ntc_save().astype(np.float64)
+        ref_g, ref_p = first["grads"][k - 1], first["params"][k - 1].astype(np.float64)
+        det = np.zeros(p0.size, bool)
+        for a, b, name in parts:
+            scale = np.abs(ref_g[a:b]).max()
+            ge = np.abs(got_g[a:b] - ref_g[a:b]).max() / scale
+            print(f"[trajectory] iteration {k} {name} gradient error {ge:.2e} of its largest (bar 1e-4)", flush=True)
+            assert ge <= 1e-4, (k, name, ge)
+            det[a:b] = adam_determined(m_prev[a:b], v_prev[a:b], k, ref_g[a:b], lr, b1, b2, eps,
+                                       1e-4 * scale, 0.5e-3 * lr)
+        err = np.abs(got_p - ref_p)
+        lim = 1e-3 * lr + np.spacing(np.abs(ref_p).astype(np.float32)).astype(np.float64)
+        print(f"[trajectory] iteration {k}: step determined for {det.mean():.4f} of the parameters, error there "
+              f"{err[det].max() / lr:.2e} x lr; {int((err[~det] > 1e-3 * lr).sum())} undetermined steps differ",
+              flush=True)
+        assert det.mean() > 0.05
+        assert np.all(err[det] <= lim[det]), float((err[det] / lr).max())
+
+    # the 150-iteration curve from the initial parameters
+    ctx.ntc_load(p0)
+    st = train.Stage1NTC(ctx, gg, cams, tt, lam=gold["lambda"], lr=lr, betas=(b1, b2), eps=eps,
+                         seed=gold["view_seed"])
     curve = {0: train.psnr(ctx.render(gg, held, *st.transform()), ht)}
     losses = []
     for it in range(1, gold["iters"] + 1):
         v = st.step()
         assert v == views[it - 1]
         losses.append(st.loss.item())
-        if it <= 3:
-            gr = first["grads"][it - 1]
-            for a, b in ((0, t_split), (t_split, p0.size)):
-                measurable[a:b] &= np.abs(gr[a:b]) >= 1e-3 * np.abs(gr[a:b]).max()
-            got = ctx.ntc_save()
-            ref = first["params"][it - 1]
-            err = np.abs(got.astype(np.float64) - ref)[measurable].max() / lr
-            print(f"[trajectory] iteration {it}: parameter error {err:.2e} x lr over {measurable.mean():.4f} "
-                  f"of the parameters; {int((np.abs(got - ref) > 0).sum())} differ at all", flush=True)
-            assert err <= 1e-3, (it, err)
         if it % 10 == 0:
             curve[it] = train.psnr(ctx.render(gg, held, *st.transform()), ht)
-    ref_curve = {int(i): p for i, p in gold["psnr"]}
-    diffs = {i: curve[i] - ref_curve[i] for i in ref_curve}
-    print("[trajectory] held-out PSNR (gpu, oracle): " +
-          ", ".join(f"{i}: {curve[i]:.3f}/{ref_curve[i]:.3f}" for i in sorted(ref_curve)), flush=True)
+    ctx.check_flags()
+    its = [int(i) for i, _ in gold["psnr"]]
+    ref = np.array([p for _, p in gold["psnr"]])
+    bars = curve_bars(ref, gold["member_psnr"])
+    got = np.array([curve[i] for i in its])
+    print("[trajectory] held-out PSNR (gpu / oracle / bar): " +
+          ", ".join(f"{i}: {a:.3f}/{b:.3f}/{c:.2f}" for i, a, b, c in zip(its, got, ref, bars)), flush=True)
     print(f"[trajectory] loss at 1/50/150: {losses[0]:.6f}/{losses[49]:.6f}/{losses[149]:.6f} vs "
           f"{gold['loss'][0]:.6f}/{gold['loss'][49]:.6f}/{gold['loss'][149]:.6f}", flush=True)
-    assert max(abs(d) for d in diffs.values()) <= 0.1, diffs
+    assert np.all(np.abs(got - ref) <= bars), dict(zip(its, np.round(got - ref, 3)))
     ctx.close()
