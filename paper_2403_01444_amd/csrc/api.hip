@@ -100,6 +100,19 @@ struct Slot {
     uint32_t* tile_walk = nullptr;   // list entries walked per tile by the forward blend
     int* order_fwd = nullptr;        // longest-first tile order of the forward blend
     int* order_bwd = nullptr;        // and of the backward blend
+    // chunk-major list of the depth-first binning (without gradient records):
+    // vals[0] holds the (chunk, tile) segments; `walked` the tile-major list,
+    // filled by the forward up to each tile's last staged entry (and in full
+    // by materialise_tile_major for the inspection calls)
+    uint32_t* chist = nullptr;       // [chunk][tile] pairs
+    uint64_t* cmb = nullptr;         // [chunk][tile] first slot in vals[0]
+    uint32_t* ttot = nullptr;        // pairs per tile
+    uint32_t* tstart = nullptr;      // first slot of each tile in the tile-major list
+    uint32_t* walked = nullptr;
+    uint64_t* tsum = nullptr;
+    bool chunked = false;
+    bool tile_major_full = false;    // walked holds the whole tile-major list
+    int64_t nchunks = 0;
     bool valid = false;
     GaussDev g{};
     CamDev cam{};
@@ -121,7 +134,10 @@ struct gs3_ctx {
     uint32_t* radix_hist = nullptr;
     uint64_t* scan_tmp = nullptr;
     uint32_t* bin_hist = nullptr;
-    uint64_t* bin_base = nullptr;
+    uint32_t* bin_base = nullptr;
+    uint32_t* bin_part = nullptr;    // segment sums of the tile-major scan of bin_hist
+    uint32_t* bin_ttot = nullptr;    // pairs per tile
+    uint64_t* bin_toff = nullptr;    // first pair of each tile
     uint32_t* sel_flag = nullptr;    // selection scratch (max_gaussians each)
     uint32_t* sel_pos = nullptr;
     uint64_t* sel_total = nullptr;
@@ -227,6 +243,10 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
              c->alloc(&s.order_fwd, c->max_tiles) && c->alloc(&s.order_bwd, c->max_tiles);
         if (ok && cfg->sort_mode == GS3_SORT_RADIX64)
             ok = c->alloc(&s.vals[1], PK) && c->alloc(&s.pkeys[0], PK) && c->alloc(&s.pkeys[1], PK);
+        if (ok && cfg->sort_mode == GS3_SORT_DEPTH_FIRST && cfg->grad_record_log2 <= 0)
+            ok = c->alloc(&s.chist, (int64_t)c->max_tiles * nchunks) && c->alloc(&s.cmb, (int64_t)c->max_tiles * nchunks) &&
+                 c->alloc(&s.ttot, c->max_tiles) && c->alloc(&s.tstart, c->max_tiles) && c->alloc(&s.walked, PK) &&
+                 c->alloc(&s.tsum, 1);
     }
     const int64_t sort_items = cfg->sort_mode == GS3_SORT_RADIX64 ? std::max(N, PK) : N;
     const int64_t hist_words = radix_hist_words(sort_items);
@@ -244,7 +264,9 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
         ok = ok && c->alloc(&c->grec, 9 * c->grec_cap);
     }
     if (ok && cfg->sort_mode == GS3_SORT_DEPTH_FIRST)
-        ok = c->alloc(&c->bin_hist, bin_words) && c->alloc(&c->bin_base, bin_words) && c->alloc(&c->bin_rect, N) &&
+        ok = c->alloc(&c->bin_hist, bin_words) && c->alloc(&c->bin_base, bin_words) &&
+             c->alloc(&c->bin_part, bin_scan_part_words(nchunks, c->max_tiles)) &&
+             c->alloc(&c->bin_ttot, c->max_tiles) && c->alloc(&c->bin_toff, c->max_tiles) && c->alloc(&c->bin_rect, N) &&
              c->alloc(&c->bin_goff, cfg->grad_record_log2 > 0 ? N : 1);
     if (ok && cfg->enable_ntc) {
         const gs3_ntc_config& nc = cfg->ntc;
@@ -681,14 +703,33 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
             // gradient gather needs it
             if (rec_mode) scan_u32_to_u64(L, sl.count, n, sl.goff, c->goff_total, c->scan_tmp);
             bin_gather(L, order, n, sl.rect, sl.count, sl.goff, cap, c->bin_rect, rec_mode ? c->bin_goff : nullptr);
-            bin_count(L, order, n, c->bin_rect, cd.tiles_x, cd.tiles_y, c->bin_hist);
-            scan_u32_to_u64(L, c->bin_hist, (int64_t)ntiles * nchunks, c->bin_base, sl.total, c->scan_tmp);
-            bin_scatter(L, order, n, c->bin_rect, c->bin_goff, cd.tiles_x, cd.tiles_y, c->bin_base, cap, sl.vals[0],
-                        rec_mode ? sl.gpos : nullptr);
-            ranges_from_hist(L, c->bin_base, sl.total, ntiles, (int)nchunks, cap, sl.ranges, c->flags);
+            if (rec_mode) {
+                // tile-major list (the record gather needs every pair's slot)
+                bin_count(L, order, n, c->bin_rect, cd.tiles_x, cd.tiles_y, c->bin_hist, nullptr);
+                bin_scan(L, c->bin_hist, nchunks, ntiles, (uint32_t)cap, c->bin_base, sl.total, c->bin_part,
+                         c->bin_ttot, c->bin_toff, c->scan_tmp);
+                // gpos (and the first slots bin_gather stored) exist only in
+                // record mode; without it the buffers hold one element
+                bin_scatter(L, order, n, c->bin_rect, rec_mode ? c->bin_goff : nullptr, cd.tiles_x, cd.tiles_y,
+                            c->bin_base, cap, sl.vals[0], rec_mode ? sl.gpos : nullptr);
+                ranges_from_hist(L, c->bin_base, sl.total, ntiles, cap, sl.ranges, c->flags);
+            } else {
+                // chunk-major list: every wave writes one run of consecutive
+                // slots; the forward walks each tile's segments
+                bin_count(L, order, n, c->bin_rect, cd.tiles_x, cd.tiles_y, sl.chist, sl.ttot);
+                scan_u32_to_u64(L, sl.chist, (int64_t)ntiles * nchunks, sl.cmb, sl.total, c->scan_tmp);
+                scan_u32_to_u32(L, sl.ttot, ntiles, sl.tstart, sl.tsum, c->scan_tmp);
+                ranges_from_starts(L, sl.tstart, sl.ttot, ntiles, cap, sl.ranges);
+                pairs_total_check(L, sl.total, cap, c->flags);
+                bin_scatter_chunked(L, order, n, c->bin_rect, cd.tiles_x, cd.tiles_y, sl.cmb, cap, sl.vals[0]);
+            }
+            sl.chunked = !rec_mode;
+            sl.nchunks = nchunks;
         } else {
             fill_u32(L, (uint32_t*)sl.ranges, 0u, 2 * (int64_t)ntiles);
             fill_u32(L, (uint32_t*)sl.total, 0u, 2);
+            sl.chunked = false;
+            sl.nchunks = 0;
         }
         sl.K_host = -1;
     } else {
@@ -712,7 +753,14 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
                             sl.gpos);
     }
     tile_order(L, sl.ranges, nullptr, ntiles, sl.order_fwd);
-    blend_forward(L, cd, sl.ranges, sl.vals[sl.cur], sl.rec, image, sl.T_final, sl.last, sl.tile_walk, sl.order_fwd);
+    sl.tile_major_full = false;
+    if (sl.chunked) {
+        const ChunkDev cl{sl.chist, sl.cmb, sl.nchunks, (uint32_t)cap, sl.walked};
+        blend_forward(L, cd, sl.ranges, sl.vals[0], sl.rec, image, sl.T_final, sl.last, sl.tile_walk, sl.order_fwd, &cl);
+    } else {
+        blend_forward(L, cd, sl.ranges, sl.vals[sl.cur], sl.rec, image, sl.T_final, sl.last, sl.tile_walk, sl.order_fwd,
+                      nullptr);
+    }
     gs3_status st = c->check_launch("render");
     if (st != GS3_OK) return st;
     sl.g = gd;
@@ -737,8 +785,8 @@ gs3_status gs3_render_backward(gs3_ctx* c, int32_t slot, const float* d_image, c
     ga.walk_off = c->walk_off; ga.grec = c->grec; ga.grec_cap = (uint64_t)c->grec_cap;
     ga.cap = (uint64_t)c->cfg.max_pairs;
     tile_order(L, sl.ranges, sl.tile_walk, ntiles, sl.order_bwd);
-    blend_backward(L, sl.cam, sl.ranges, sl.vals[sl.cur], sl.rec, d_image, sl.T_final, sl.last, ga, c->accum,
-                   out->d_opacity != nullptr || out->d_opacity_logits != nullptr, sl.order_bwd);
+    blend_backward(L, sl.cam, sl.ranges, sl.chunked ? sl.walked : sl.vals[sl.cur], sl.rec, d_image, sl.T_final,
+                   sl.last, ga, c->accum, out->d_opacity != nullptr || out->d_opacity_logits != nullptr, sl.order_bwd);
     GradsDev gd;
     gd.d_means = out->d_means; gd.d_quats = out->d_quats; gd.d_log_scales = out->d_log_scales;
     gd.d_opac = out->d_opacity_logits; gd.d_sh = out->d_sh; gd.d_dmu = sl.g.dmu ? out->d_dmu : nullptr;
@@ -873,14 +921,28 @@ gs3_status gs3_debug_pairs(gs3_ctx* c, int32_t slot, uint64_t* keys, uint32_t* v
     if (cap < K) return c->fail(GS3_EINVAL, "debug_pairs: buffer too small");
     if (K == 0) return GS3_OK;
     const int ntiles = sl.cam.tiles_x * sl.cam.tiles_y;
-    if (vals && hipMemcpyAsync(vals, sl.vals[sl.cur], (size_t)K * 4, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+    const uint32_t* tm = sl.vals[sl.cur];
+    if (sl.chunked) {
+        // the whole tile-major list from the chunk-major one (its prefix
+        // walked by the forward is unchanged by this)
+        if (!sl.tile_major_full) {
+            Launch L = c->L();
+            bin_scan(L, sl.chist, sl.nchunks, ntiles, (uint32_t)c->cfg.max_pairs, c->bin_base, c->walk_total,
+                     c->bin_part, c->bin_ttot, c->bin_toff, c->scan_tmp);
+            chunked_to_tile_major(L, sl.chist, sl.cmb, c->bin_base, sl.nchunks, ntiles, (uint64_t)c->cfg.max_pairs,
+                                  sl.vals[0], sl.walked);
+            sl.tile_major_full = true;
+        }
+        tm = sl.walked;
+    }
+    if (vals && hipMemcpyAsync(vals, tm, (size_t)K * 4, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
         return c->fail(GS3_EHIP, "debug_pairs: copy failed");
     if (keys) {
         if (c->cfg.sort_mode == GS3_SORT_RADIX64) {
             if (hipMemcpyAsync(keys, sl.pkeys[sl.cur], (size_t)K * 8, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
                 return c->fail(GS3_EHIP, "debug_pairs: copy failed");
         } else {
-            debug_keys(c->L(), sl.ranges, sl.vals[sl.cur], sl.key, ntiles, keys);
+            debug_keys(c->L(), sl.ranges, tm, sl.key, ntiles, keys);
         }
     }
     return c->check_launch("debug_pairs");

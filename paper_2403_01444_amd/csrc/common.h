@@ -475,6 +475,77 @@ __device__ __forceinline__ float wave_reduce_scatter8(const float v[8], int lane
     return c;                     // term index: lane >> 3
 }
 
+// The same for two independent sets of eight values (two tile entries):
+// the eight permlane32 and four permlane16 exchanges are issued back to
+// back after a single wait (the operands were all written before it), and
+// the two DPP chains interleave, so their read-after-write waits overlap.
+__device__ __forceinline__ void wave_reduce_scatter8x2(const float v[8], const float u[8], int lane, float& rv,
+                                                       float& ru) {
+    float va[8], ua[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        va[k] = v[k];
+        ua[k] = u[k];
+    }
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_permlane32_swap_b32 %0, %4\n\t"
+        "v_permlane32_swap_b32 %1, %5\n\t"
+        "v_permlane32_swap_b32 %2, %6\n\t"
+        "v_permlane32_swap_b32 %3, %7\n\t"
+        "v_permlane32_swap_b32 %8, %12\n\t"
+        "v_permlane32_swap_b32 %9, %13\n\t"
+        "v_permlane32_swap_b32 %10, %14\n\t"
+        "v_permlane32_swap_b32 %11, %15"
+        : "+v"(va[0]), "+v"(va[1]), "+v"(va[2]), "+v"(va[3]), "+v"(va[4]), "+v"(va[5]), "+v"(va[6]), "+v"(va[7]),
+          "+v"(ua[0]), "+v"(ua[1]), "+v"(ua[2]), "+v"(ua[3]), "+v"(ua[4]), "+v"(ua[5]), "+v"(ua[6]), "+v"(ua[7]));
+    float a[4], b[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        a[k] = va[k] + va[4 + k];
+        b[k] = ua[k] + ua[4 + k];
+    }
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_permlane16_swap_b32 %0, %2\n\t"
+        "v_permlane16_swap_b32 %1, %3\n\t"
+        "v_permlane16_swap_b32 %4, %6\n\t"
+        "v_permlane16_swap_b32 %5, %7"
+        : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(b[0]), "+v"(b[1]), "+v"(b[2]), "+v"(b[3]));
+    const float a0 = a[0] + a[2], a1 = a[1] + a[3], b0 = b[0] + b[2], b1 = b[1] + b[3];
+    const bool hi8 = lane & 8;
+    const int mv = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, hi8 ? a0 : a1), 0x128, 0xF, 0xF, false);
+    const int mu = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, hi8 ? b0 : b1), 0x128, 0xF, 0xF, false);
+    float c = (hi8 ? a1 : a0) + __builtin_bit_cast(float, mv);
+    float d = (hi8 ? b1 : b0) + __builtin_bit_cast(float, mu);
+    c = dpp_add<0xB1, 0xF>(c);
+    d = dpp_add<0xB1, 0xF>(d);
+    c = dpp_add<0x4E, 0xF>(c);
+    d = dpp_add<0x4E, 0xF>(d);
+    rv = dpp_add<0x141, 0xF>(c);
+    ru = dpp_add<0x141, 0xF>(d);
+}
+
+// Inclusive prefix sum over the 64 lanes with DPP moves: shifts by 1, 2, 4
+// and 8 lanes within each 16-lane row (lanes that would read before the row
+// start add nothing), then the last lane of row 0 into row 1 and of row 2
+// into row 3 (row_bcast:15), then the last lane of row 1 into rows 2 and 3
+// (row_bcast:31).  No LDS traffic, unlike a permute-based scan.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);   // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return x;
+}
+
+// The value of lane 63 (a wave-uniform scalar read).
+__device__ __forceinline__ uint32_t lane63_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
 // Sum over the 64 lanes with DPP moves (no LDS traffic); the result is
 // returned uniformly (read from lane 63).  Steps: pairs and quads
 // (quad_perm), 8 and 16 lanes (row_half_mirror, row_mirror), then rows

@@ -67,16 +67,51 @@ int64_t bin_chunks(int64_t n);
 // first pair slots goff, gathered into depth order
 void bin_gather(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
                 const uint64_t* goff, uint64_t cap, uint2* srect, uint32_t* sgoff);
+// Pairs per (chunk, tile), chunk-major: hist[chunk * ntiles + tile] with
+// ntiles = tiles_x * tiles_y, so each pass writes and reads a tile row of one
+// chunk as consecutive words; ttot (optional) receives the pairs per tile.
 void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, int tiles_x, int tiles_y,
-               uint32_t* hist);
+               uint32_t* hist, uint32_t* ttot);
+// ranges[t] = [start[t], start[t] + len[t]) clamped to cap
+void ranges_from_starts(const Launch& L, const uint32_t* start, const uint32_t* len, int ntiles, uint64_t cap,
+                        uint2* ranges);
+// First slot of every (tile, chunk) segment in the tile-major pair list:
+// base[chunk * ntiles + tile] = (pairs of earlier tiles) + (pairs of the
+// tile in earlier chunks), clamped to cap; the grand total goes to *total.
+// Scratch: part (bin_scan_part_words u32), ttot (ntiles u32), toff (ntiles
+// u64) and the scan's tmp.
+int64_t bin_scan_part_words(int64_t nchunks, int ntiles);
+void bin_scan(const Launch& L, const uint32_t* hist, int64_t nchunks, int ntiles, uint32_t cap, uint32_t* base,
+              uint64_t* total, uint32_t* part, uint32_t* ttot, uint64_t* toff, uint64_t* tmp);
 // also records, for each Gaussian's k-th rectangle tile, the slot of that
 // pair: gpos[goff[id] + k] (goff = exclusive scan of the tile counts)
 void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, const uint32_t* sgoff,
-                 int tiles_x, int tiles_y, const uint64_t* base, uint64_t cap, uint32_t* vals, uint32_t* gpos);
+                 int tiles_x, int tiles_y, const uint32_t* base, uint64_t cap, uint32_t* vals, uint32_t* gpos);
+// The chunk-major pair list of the depth-first binning, as the forward
+// blend reads it: segment lengths hist[chunk][tile], segment starts
+// cmb[chunk][tile] (the exclusive scan of hist in that order), and the
+// tile-major list `walked`, into which the forward writes each entry it
+// stages at its tile-major slot (the backward walks that list).
+struct ChunkDev {
+    const uint32_t* hist;
+    const uint64_t* cmb;
+    int64_t nchunks;
+    uint32_t cap;
+    uint32_t* walked;
+};
+// The same into the chunk-major list: cmb = exclusive scan of hist in its
+// [chunk][tile] order (the start of every (chunk, tile) segment).
+void bin_scatter_chunked(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, int tiles_x,
+                         int tiles_y, const uint64_t* cmb, uint64_t cap, uint32_t* vals);
+// Copy every (chunk, tile) segment of the chunk-major list to its slot in
+// the tile-major list (base_tm: the tile-major first slot of each segment,
+// from bin_scan); slots at or past cap are skipped.
+void chunked_to_tile_major(const Launch& L, const uint32_t* hist, const uint64_t* cmb, const uint32_t* base_tm,
+                           int64_t nchunks, int ntiles, uint64_t cap, const uint32_t* vals_cm, uint32_t* vals_tm);
 void gpos_from_pairs(const Launch& L, const uint64_t* keys, const uint32_t* vals, int64_t K, const uint2* rect,
                      const uint64_t* goff, int tiles_x, uint64_t cap, uint32_t* gpos);
-void ranges_from_hist(const Launch& L, const uint64_t* base, const uint64_t* total, int ntiles, int nchunks,
-                      uint64_t cap, uint2* ranges, int* overflow);
+void ranges_from_hist(const Launch& L, const uint32_t* base, const uint64_t* total, int ntiles, uint64_t cap,
+                      uint2* ranges, int* overflow);
 void pairs_total_check(const Launch& L, const uint64_t* total, uint64_t cap, int* overflow);
 
 // Per-pair gradient records of the backward blend: walked entries of tile t
@@ -99,8 +134,11 @@ struct GatherDev {
 // or by walked entries.  `order` holds ntiles ints.
 void tile_order(const Launch& L, const uint2* ranges, const uint32_t* walk, int ntiles, int* order);
 // `order` (optional) maps workgroups to tiles
+// chunks: the chunk-major list (vals is then that list), or NULL for a
+// tile-major list read through ranges.
 void blend_forward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals, const float4* rec,
-                   float* image, float* T_final, uint32_t* last, uint32_t* tile_walk, const int* order);
+                   float* image, float* T_final, uint32_t* last, uint32_t* tile_walk, const int* order,
+                   const ChunkDev* chunks);
 void blend_backward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals,
                     const float4* rec, const float* d_image, const float* T_final, const uint32_t* last,
                     const GatherDev& ga, float* accum, bool want_opacity, const int* order);

@@ -159,66 +159,148 @@ __global__ __launch_bounds__(256) void k_bin_gather(const uint32_t* __restrict__
 // tile rectangle covering each tile of the row.  Every covering Gaussian
 // adds +1 at its first column and -1 past its last to an LDS difference
 // array; a prefix sum over the row's columns gives the counts (the same
-// coverage test the scatter applies tile by tile).
+// coverage test the scatter applies tile by tile).  The counts are stored
+// chunk-major, so a wave writes its row as consecutive words.  A workgroup
+// takes kCountGroup consecutive chunks of one row block and, when ttot is
+// set, adds each tile's count over them to ttot (one atomic per tile and
+// group).
+constexpr int kCountGroup = 8;   // bin_chunks is a multiple of 8
+
 __global__ __launch_bounds__(kBinThreads) void k_bin_count(const uint2* __restrict__ srect, int64_t n, int tiles_x,
-                                                           int tiles_y, int64_t nchunks, uint32_t* __restrict__ hist) {
+                                                           int tiles_y, int64_t nchunks, uint32_t* __restrict__ hist,
+                                                           uint32_t* __restrict__ ttot) {
+    const int64_t ntiles = (int64_t)tiles_x * tiles_y;
     __shared__ uint2 s_rect[kBinChunk];
     __shared__ int s_diff[kBinRowsPerBlock][kMaxTilesX + 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int rowblock;
-    int64_t chunk;
-    bin_block(nchunks, rowblock, chunk);
+    const int64_t ngroups = nchunks / kCountGroup;
+    const int64_t group = (int64_t)blockIdx.x % ngroups;
+    const int rowblock = (int)((int64_t)blockIdx.x / ngroups);
     const int row = rowblock * kBinRowsPerBlock + w;
-    const int64_t e0 = chunk * kBinChunk;
-    const int m = (int)min((int64_t)kBinChunk, n - e0);
-    for (int e = threadIdx.x; e < m; e += kBinThreads) s_rect[e] = srect[e0 + e];
-    for (int k = lane; k <= kMaxTilesX; k += 64) s_diff[w][k] = 0;
-    __syncthreads();
-    if (row >= tiles_y) return;
-    for (int e = lane; e < m; e += 64) {
-        const uint2 r = s_rect[e];
-        if ((int)(r.x >> 16) <= row && row <= (int)(r.y >> 16)) {
-            atomicAdd(&s_diff[w][r.x & 0xFFFFu], 1);
-            atomicAdd(&s_diff[w][(r.y & 0xFFFFu) + 1u], -1);
+    uint32_t tot[4] = {0u, 0u, 0u, 0u};
+    for (int64_t chunk = group * kCountGroup; chunk < (group + 1) * kCountGroup; chunk++) {
+        const int64_t e0 = chunk * kBinChunk;
+        const int m = (int)min((int64_t)kBinChunk, n - e0);   // <= 0 for the padding chunks
+        __syncthreads();   // the previous chunk's rectangles are no longer read
+        for (int e = threadIdx.x; e < m; e += kBinThreads) s_rect[e] = srect[e0 + e];
+        for (int k = lane; k <= kMaxTilesX; k += 64) s_diff[w][k] = 0;
+        __syncthreads();
+        if (row >= tiles_y) continue;
+        for (int e = lane; e < m; e += 64) {
+            const uint2 r = s_rect[e];
+            if ((int)(r.x >> 16) <= row && row <= (int)(r.y >> 16)) {
+                atomicAdd(&s_diff[w][r.x & 0xFFFFu], 1);
+                atomicAdd(&s_diff[w][(r.y & 0xFFFFu) + 1u], -1);
+            }
+        }
+        // the wave's atomics are done before its reads below (LDS operations of
+        // one wave complete in order); lane l takes columns 4 l .. 4 l + 3
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int a[4];
+        int t = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            t += s_diff[w][4 * lane + k];
+            a[k] = t;
+        }
+        const int x = (int)wave_incl_scan_u32((uint32_t)t);   // inclusive scan of the lane totals
+        const int pre = x - t;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int tx = 4 * lane + k;
+            const uint32_t v = (uint32_t)(pre + a[k]);
+            tot[k] += v;
+            if (tx < tiles_x) hist[chunk * ntiles + (int64_t)row * tiles_x + tx] = v;
         }
     }
-    // the wave's atomics are done before its reads below (LDS operations of
-    // one wave complete in order); lane l takes columns 4 l .. 4 l + 3
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    int a[4];
-    int t = 0;
+    if (ttot && row < tiles_y) {
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-        t += s_diff[w][4 * lane + k];
-        a[k] = t;
+        for (int k = 0; k < 4; k++) {
+            const int tx = 4 * lane + k;
+            if (tx < tiles_x && tot[k]) atomicAdd(&ttot[(int64_t)row * tiles_x + tx], tot[k]);
+        }
     }
-    int x = t;   // inclusive scan of the lane totals
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
+}
+
+// Start slots of the tiles in the tile-major list: ranges[t] = [s, s + len)
+// from the exclusive scan of the tile totals, clamped to cap.
+__global__ __launch_bounds__(256) void k_ranges_from_starts(const uint32_t* __restrict__ start,
+                                                            const uint32_t* __restrict__ len, int ntiles,
+                                                            uint64_t cap, uint2* __restrict__ ranges) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= ntiles) return;
+    const uint64_t s = start[t], e = s + len[t];
+    ranges[t] = make_uint2((uint32_t)(s < cap ? s : cap), (uint32_t)(e < cap ? e : cap));
+}
+
+// Tile-major exclusive prefix of the chunk-major counts.  A thread owns one
+// tile and a segment of kBinScanSeg chunks, so every load and store of a
+// warp-wide step touches consecutive tiles of one chunk: (1) segment sums,
+// (2) per tile, the exclusive prefix over its segments and its total,
+// (3) an exclusive scan of the tile totals (scan_u32_to_u64), (4) each
+// segment's chunks walked again from the tile's and the segment's offset.
+constexpr int kBinScanSeg = 32;
+
+__global__ __launch_bounds__(256) void k_bin_scan_part(const uint32_t* __restrict__ hist, int64_t nchunks, int ntiles,
+                                                       int64_t nseg, uint32_t* __restrict__ part) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= ntiles) return;
+    for (int64_t sg = blockIdx.y; sg < nseg; sg += gridDim.y) {
+        const int64_t c0 = sg * kBinScanSeg;
+        const int64_t c1 = min(c0 + kBinScanSeg, nchunks);
+        uint32_t s = 0u;
+        for (int64_t c = c0; c < c1; c++) s += hist[c * ntiles + t];
+        part[sg * ntiles + t] = s;
     }
-    const int pre = x - t;
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-        const int tx = 4 * lane + k;
-        if (tx < tiles_x) hist[((int64_t)row * tiles_x + tx) * nchunks + chunk] = (uint32_t)(pre + a[k]);
+}
+
+__global__ __launch_bounds__(256) void k_bin_scan_tiles(uint32_t* __restrict__ part, int64_t nseg, int ntiles,
+                                                        uint32_t* __restrict__ ttot) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= ntiles) return;
+    uint32_t run = 0u;   // a tile holds at most one pair per Gaussian (< 2^31)
+    for (int64_t sg = 0; sg < nseg; sg++) {
+        const uint32_t v = part[sg * ntiles + t];
+        part[sg * ntiles + t] = run;
+        run += v;
+    }
+    ttot[t] = run;
+}
+
+__global__ __launch_bounds__(256) void k_bin_scan_base(const uint32_t* __restrict__ hist, int64_t nchunks, int ntiles,
+                                                       int64_t nseg, const uint32_t* __restrict__ part,
+                                                       const uint64_t* __restrict__ toff, uint32_t cap,
+                                                       uint32_t* __restrict__ base) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= ntiles) return;
+    for (int64_t sg = blockIdx.y; sg < nseg; sg += gridDim.y) {
+        const int64_t c0 = sg * kBinScanSeg;
+        const int64_t c1 = min(c0 + kBinScanSeg, nchunks);
+        uint64_t run = toff[t] + part[sg * ntiles + t];
+        for (int64_t c = c0; c < c1; c++) {
+            base[c * ntiles + t] = run < (uint64_t)cap ? (uint32_t)run : cap;
+            run += hist[c * ntiles + t];
+        }
     }
 }
 
 // Scatter pass, one wave per (tile row, chunk of depth-ordered Gaussians):
-// the wave lists the chunk's Gaussians covering its row in depth order with
-// the prefix of their column counts, then writes the row's pairs 64 at a
-// time, lane = pair.  A lane finds its Gaussian by binary search in the
-// prefix; lanes of one batch that share a tile column are ranked by lane
-// (eight ballots on the column bits), so every tile's entries keep the depth
-// order, and per-column cursors in LDS, starting at the slots the scan of the
-// counts gave, carry the ranks across batches.
+// the wave lists the chunk's Gaussians whose rectangle spans its row, in
+// depth order, then walks that list once with lane = tile column (lanes
+// l, l + 64, ... of the row): every column takes each listed Gaussian that
+// covers it at its cursor, which starts at the slot the scan of the counts
+// gave, so every tile's entries keep the depth order.  The first slot of
+// each (chunk, tile) segment comes from `base` in [chunk][tile] layout: the
+// tile-major list's slots (u32, already clamped to cap) or the chunk-major
+// list's (u64: the segments of one chunk in tile order, so a wave's row of
+// one chunk is a single run of consecutive slots).
+template <typename B>
 __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __restrict__ order, int64_t n,
                                                   const uint2* __restrict__ srect, const uint32_t* __restrict__ sgoff,
                                                   int tiles_x, int tiles_y, int64_t nchunks,
-                                                  const uint64_t* __restrict__ base, uint32_t cap,
+                                                  const B* __restrict__ base, uint32_t cap,
                                                   uint32_t* __restrict__ vals, uint32_t* __restrict__ gpos) {
     // A cursor starts at min(first slot, cap) and moves at most kBinChunk
     // past it, so with cap < 2^31 it never wraps; slots at or past cap are
@@ -226,9 +308,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __rest
     __shared__ uint2 s_rect[kBinChunk];
     __shared__ uint32_t s_id[kBinChunk];
     __shared__ uint32_t s_goff[kBinChunk];
-    __shared__ uint32_t s_cur[kBinRowsPerBlock][kMaxTilesX];   // per-column cursors of each wave's row
-    __shared__ uint16_t s_gl[kBinRowsPerBlock][kBinChunk];      // covering Gaussians (chunk positions)
-    __shared__ uint32_t s_wp[kBinRowsPerBlock][kBinChunk];      // exclusive prefix of their column counts
+    __shared__ uint2 s_cov[kBinRowsPerBlock][kBinChunk];   // covering Gaussians: (tx0 | tx1 << 16, chunk position)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int rowblock;
     int64_t chunk;
@@ -241,97 +321,73 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __rest
         s_rect[e] = srect[e0 + e];
         s_goff[e] = gpos ? sgoff[e0 + e] : 0u;
     }
-    if (row < tiles_y) {
-        for (int tx = lane; tx < tiles_x; tx += 64) {
-            const uint64_t b = base[((int64_t)row * tiles_x + tx) * nchunks + chunk];
-            s_cur[w][tx] = b < (uint64_t)cap ? (uint32_t)b : cap;
-        }
-    }
     __syncthreads();
     if (row >= tiles_y) return;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;   // lanes under this one
-    // 1. the covering Gaussians in depth order and the prefix of their widths
+    // 1. the chunk's Gaussians spanning this row, in depth order
     int G = 0;
-    uint32_t P = 0;
     for (int eb = 0; eb < m; eb += 64) {
         const int e = eb + lane;
-        uint32_t wd = 0u;
+        bool cov = false;
+        uint2 r = make_uint2(0u, 0u);
         if (e < m) {
-            const uint2 r = s_rect[e];
-            if ((int)(r.x >> 16) <= row && row <= (int)(r.y >> 16)) wd = (r.y & 0xFFFFu) - (r.x & 0xFFFFu) + 1u;
+            r = s_rect[e];
+            cov = (int)(r.x >> 16) <= row && row <= (int)(r.y >> 16);
         }
-        const uint64_t cov = __ballot(wd != 0u);
-        uint32_t x = wd;   // inclusive scan of the widths
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x, off, 64);
-            if (lane >= off) x += y;
-        }
-        if (wd) {
-            const int k = G + __popcll(cov & below);
-            s_gl[w][k] = (uint16_t)e;
-            s_wp[w][k] = P + x - wd;
-        }
-        G += __popcll(cov);
-        P += __shfl(x, 63, 64);
+        const uint64_t bal = __ballot(cov);
+        if (cov) s_cov[w][G + __popcll(bal & below)] = make_uint2((r.x & 0xFFFFu) | (r.y << 16), (uint32_t)e);
+        G += __popcll(bal);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // 2. the row's P pairs, 64 per round
-    for (uint32_t q0 = 0; q0 < P; q0 += 64) {
-        const uint32_t q = q0 + (uint32_t)lane;
-        const bool valid = q < P;
-        uint32_t tx = 0xFFFFFFFFu, id = 0u, kk = 0u;
-        if (valid) {
-            int lo = 0, hi = G - 1;   // last g with s_wp[g] <= q
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_wp[w][mid] <= q) lo = mid; else hi = mid - 1;
-            }
-            const int e = s_gl[w][lo];
-            const uint2 r = s_rect[e];
-            const uint32_t tx0 = r.x & 0xFFFFu, tx1 = r.y & 0xFFFFu;
-            const uint32_t d = q - s_wp[w][lo];
-            tx = tx0 + d;
-            id = s_id[e];
-            // slot of this pair in its Gaussian's own pair range
-            kk = s_goff[e] + (uint32_t)(row - (int)(r.x >> 16)) * (tx1 - tx0 + 1u) + d;
-        }
-        // lanes of this round with the same tile column
-        uint64_t peers = __ballot(valid);
+    // 2. lane = column: up to four column groups of 64 (kMaxTilesX = 256)
+    const B* brow = base + chunk * ((int64_t)tiles_x * tiles_y) + (int64_t)row * tiles_x;
+    uint32_t cur[4];
 #pragma unroll
-        for (int bit = 0; bit < 8; bit++) {
-            const bool set = (tx >> bit) & 1u;
-            const uint64_t bal = __ballot(set);
-            peers &= set ? bal : ~bal;
-        }
-        if (valid) {
-            const uint32_t pos = s_cur[w][tx] + (uint32_t)__popcll(peers & below);
-            if (pos < cap) {
-                vals[pos] = id;
-                if (gpos && kk < cap) gpos[kk] = pos;
+    for (int cg = 0; cg < 4; cg++) {
+        const int tx = 64 * cg + lane;
+        const uint64_t b = tx < tiles_x ? (uint64_t)brow[tx] : (uint64_t)cap;
+        cur[cg] = b < (uint64_t)cap ? (uint32_t)b : cap;
+    }
+    const int ncg = (tiles_x + 63) >> 6;
+    for (int k = 0; k < G; k++) {
+        const uint2 cv = s_cov[w][k];
+        const int tx0 = (int)(cv.x & 0xFFFFu), tx1 = (int)(cv.x >> 16);
+        const uint32_t id = s_id[cv.y];
+#pragma unroll
+        for (int cg = 0; cg < 4; cg++) {
+            if (cg >= ncg) break;
+            const int tx = 64 * cg + lane;
+            if (tx >= tx0 && tx <= tx1) {   // tx1 < tiles_x
+                const uint32_t pos = cur[cg];
+                if (pos < cap) {
+                    vals[pos] = id;
+                    if (gpos) {
+                        // slot of this pair in its Gaussian's own pair range
+                        const uint2 r = s_rect[cv.y];
+                        const uint32_t kk = s_goff[cv.y] + (uint32_t)(row - (int)(r.x >> 16)) *
+                                                               (uint32_t)(tx1 - tx0 + 1) + (uint32_t)(tx - tx0);
+                        if (kk < cap) gpos[kk] = pos;
+                    }
+                }
+                cur[cg] = pos + 1u;
             }
-            if ((peers >> lane) >> 1 == 0ull) s_cur[w][tx] = pos + 1u;   // the column's last lane this round
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
-__global__ __launch_bounds__(256) void k_ranges_from_hist(const uint64_t* __restrict__ base,
-                                                          const uint64_t* __restrict__ total, int ntiles,
-                                                          int64_t nchunks, uint64_t cap, uint2* __restrict__ ranges,
-                                                          int* __restrict__ overflow) {
+__global__ __launch_bounds__(256) void k_ranges_from_hist(const uint32_t* __restrict__ base,
+                                                          const uint64_t* __restrict__ total, int ntiles, uint64_t cap,
+                                                          uint2* __restrict__ ranges, int* __restrict__ overflow) {
     const int t = blockIdx.x * 256 + threadIdx.x;
     const uint64_t K = *total;
     if (t == 0 && K > cap) atomicOr(overflow, 1);
     if (t >= ntiles) return;
-    uint64_t s = base[(int64_t)t * nchunks];
-    uint64_t e = t + 1 < ntiles ? base[(int64_t)(t + 1) * nchunks] : K;
-    s = s < cap ? s : cap;
-    e = e < cap ? e : cap;
-    ranges[t] = make_uint2((uint32_t)s, (uint32_t)e);
+    // chunk 0's row of the bases: the first slot of every tile (clamped to cap)
+    const uint32_t s = base[t];
+    const uint32_t e = t + 1 < ntiles ? base[t + 1] : (uint32_t)(K < cap ? K : cap);
+    ranges[t] = make_uint2(s, e);
 }
 
 __global__ void k_total_check(const uint64_t* total, uint64_t cap, int* overflow) {
@@ -391,8 +447,17 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ r
 // vertically adjacent pixels of one column, so a staged record is read from
 // LDS once per R evaluations and the column terms of the exponent are shared.
 // The tile's Gaussian records are staged through LDS 256/R at a time.
+//
+// kChunked: the pairs are in the chunk-major list of the depth-first
+// binning (ChunkDev): the tile's entries are its segments of successive
+// depth chunks.  A cursor (chunk, offset) walks them: per batch, the first
+// wave reads the lengths and starts of the tile's segments in the next 64
+// chunks and scans the lengths, and each thread finds its entry's segment
+// by binary search.  Every staged entry's Gaussian index is also written to
+// the tile-major list at the tile's slot (ranges[tile].x + entry), which
+// the backward walks.  The result equals the walk of the tile-major list.
 // ---------------------------------------------------------------------------
-template <int R>
+template <int R, bool kChunked>
 __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int ntiles,
                                                                  const uint2* __restrict__ ranges,
                                                                  const uint32_t* __restrict__ vals,
@@ -400,9 +465,14 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                                                                  float* __restrict__ image, float* __restrict__ T_final,
                                                                  uint32_t* __restrict__ last_out,
                                                                  uint32_t* __restrict__ tile_walk,
-                                                                 const int* __restrict__ order) {
+                                                                 const int* __restrict__ order, ChunkDev cl) {
     constexpr int NT = kTile * kTile / R;
+    static_assert(!kChunked || NT >= 64, "the chunk window needs a full wave");
     __shared__ uint32_t s_walk;
+    __shared__ uint32_t s_pre[65];   // chunk window: exclusive prefix of the segment lengths
+    __shared__ uint32_t s_sb[64];    // and the slot of each segment's next entry
+    __shared__ int64_t s_cc;         // cursor: first chunk of the window
+    __shared__ uint32_t s_co;        // and the entries of it already staged
     const int tile = order ? order[blockIdx.x] : tile_of_block(blockIdx.x, ntiles);
     __shared__ float4 s_w0[NT];
     __shared__ float4 s_w1[NT];
@@ -431,21 +501,94 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
         last[k] = 0u;
         fpy[k] = (px < cam.W && py0 + k < cam.H) ? (float)(py0 + k) : kStopped;
     }
-    if (threadIdx.x == 0) s_walk = 0u;
-    for (uint32_t b = start; b < end; b += NT) {
+    if (threadIdx.x == 0) {
+        s_walk = 0u;
+        s_cc = 0;
+        s_co = 0u;
+    }
+    const uint32_t total = end - start;
+    for (uint32_t eb = 0; eb < total;) {   // eb: entries staged so far
         bool all = true;
 #pragma unroll
         for (int k = 0; k < R; k++) all = all && (fpy[k] != fpy[k]);
         if (__syncthreads_count(all) == NT) break;
-        const uint32_t e = b + threadIdx.x;
-        if (e < end) {
-            const uint32_t id = vals[e];
-            s_w0[threadIdx.x] = rec[3 * (int64_t)id + 0];
-            s_w1[threadIdx.x] = rec[3 * (int64_t)id + 1];
-            s_w2[threadIdx.x] = blend_stage_w2(rec[3 * (int64_t)id + 2], tx0p, ty0p);
+        uint32_t cnt_u;
+        if (kChunked) {
+            const int64_t ntl = (int64_t)ntiles;
+            if (threadIdx.x < 64) {
+                const int l = threadIdx.x;
+                const int64_t c = s_cc + l;
+                uint32_t len = 0u, sb = 0u;
+                if (c < cl.nchunks) {
+                    len = cl.hist[c * ntl + tile];
+                    const uint64_t b = cl.cmb[c * ntl + tile];
+                    sb = b < (uint64_t)cl.cap ? (uint32_t)b : cl.cap;
+                }
+                if (l == 0) {
+                    len -= s_co;
+                    sb += s_co;
+                }
+                const uint32_t x = wave_incl_scan_u32(len);   // inclusive scan of the lengths
+                s_pre[l + 1] = x;
+                if (l == 0) s_pre[0] = 0u;
+                s_sb[l] = sb;
+            }
+            __syncthreads();
+            const uint32_t avail = s_pre[64];
+            // (avail exceeds the rest of the tile's range only when the pair
+            // list overflowed and the ranges were clamped to cap)
+            cnt_u = min(min((uint32_t)NT, avail), total - eb);
+            const uint32_t e = threadIdx.x;
+            if (e < cnt_u) {
+                int lo = 0, hi = 63;   // the last segment starting at or before entry e
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_pre[mid] <= e) lo = mid; else hi = mid - 1;
+                }
+                const uint32_t idx = s_sb[lo] + (e - s_pre[lo]);
+                if (idx < cl.cap) {
+                    const uint32_t id = vals[idx];
+                    s_w0[threadIdx.x] = rec[3 * (int64_t)id + 0];
+                    s_w1[threadIdx.x] = rec[3 * (int64_t)id + 1];
+                    s_w2[threadIdx.x] = blend_stage_w2(rec[3 * (int64_t)id + 2], tx0p, ty0p);
+                    const uint32_t slot = start + eb + e;
+                    if (slot < cl.cap) cl.walked[slot] = id;
+                } else {
+                    // past the pair capacity (the render reports the overflow):
+                    // an entry no pixel takes
+                    s_w0[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    s_w1[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    s_w2[threadIdx.x] = make_float4(0.f, 0.f, 0.f, __uint_as_float(0u));
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                // advance past the cnt_u staged entries
+                if (cnt_u == avail) {
+                    s_cc += 64;
+                    s_co = 0u;
+                } else {
+                    int lo = 0, hi = 63;   // the segment holding the next entry
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_pre[mid] <= cnt_u) lo = mid; else hi = mid - 1;
+                    }
+                    s_co = (lo == 0 ? s_co : 0u) + (cnt_u - s_pre[lo]);
+                    s_cc += lo;
+                }
+            }
+        } else {
+            const uint32_t e = start + eb + threadIdx.x;
+            if (e < end) {
+                const uint32_t id = vals[e];
+                s_w0[threadIdx.x] = rec[3 * (int64_t)id + 0];
+                s_w1[threadIdx.x] = rec[3 * (int64_t)id + 1];
+                s_w2[threadIdx.x] = blend_stage_w2(rec[3 * (int64_t)id + 2], tx0p, ty0p);
+            }
+            __syncthreads();
+            cnt_u = min((uint32_t)NT, total - eb);
         }
-        __syncthreads();
-        const int cnt = (int)min((uint32_t)NT, end - b);
+        const int cnt = (int)cnt_u;
         if (!all) {
             // branch-free per-pixel body: every lane evaluates, selects keep
             // the state of pixels that do not take the contribution
@@ -480,7 +623,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                     c1[k] += wgt * w1.w;
                     c2[k] += wgt * w2.x;
                     T[k] = take ? Tn : T[k];
-                    last[k] = take ? b - start + (uint32_t)j + 1u : last[k];
+                    last[k] = take ? eb + (uint32_t)j + 1u : last[k];
                     fpy[k] = stop ? kStopped : fpy[k];
                 }
             };
@@ -496,6 +639,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
             }
             if (j + 1 == cnt) eval(j);
         }
+        eb += cnt_u;
         __syncthreads();
     }
     const int64_t P = (int64_t)cam.W * cam.H;
@@ -565,16 +709,16 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
     const uint32_t start = ranges[tile].x;
     const uint32_t woff = kRecords ? walk_off[tile] : 0u;
     const int64_t P = (int64_t)cam.W * cam.H;
-    float T[R], g0[R], g1[R], g2[R], b0[R], b1[R], b2[R];   // b: colour behind the current contributor
+    // gb: dL/dC . (colour behind the current contributor), the only use of
+    // that colour (dL/dalpha_i = T_i (dL/dC . c_i - gb)); it starts at the
+    // background and moves to alpha c + (1 - alpha) b past each contributor
+    float T[R], g0[R], g1[R], g2[R], gb[R];
     uint32_t last[R];
 #pragma unroll
     for (int k = 0; k < R; k++) {
         T[k] = 1.0f;
         last[k] = 0u;
         g0[k] = g1[k] = g2[k] = 0.f;
-        b0[k] = cam.bg[0];
-        b1[k] = cam.bg[1];
-        b2[k] = cam.bg[2];
         if (px < cam.W && py0 + k < cam.H) {
             const int64_t p = (int64_t)(py0 + k) * cam.W + px;
             T[k] = T_final[p];
@@ -583,9 +727,12 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
             g1[k] = d_image[P + p];
             g2[k] = d_image[2 * P + p];
         }
+        gb[k] = g0[k] * cam.bg[0] + g1[k] * cam.bg[1] + g2[k] * cam.bg[2];
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // reduce-scatter terms: u, v, A, B, C, r, g, b; lane group (lane >> 3) holds term (lane >> 3)
+    // reduce-scatter terms: the image-space mean terms summed as dp dx and
+    // dp dy (the conic is applied to the sums per entry), the conic terms,
+    // r, g, b; lane group (lane >> 3) holds term (lane >> 3)
     const int my_term = lane >> 3;
     const int my_slot = my_term < 5 ? my_term : my_term + 1;   // index in the nine-term layout
     for (int64_t jb = ((int64_t)(maxlast - 1) / NT) * NT; jb >= 0; jb -= NT) {
@@ -599,11 +746,14 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
         }
         __syncthreads();
         const int cnt = (int)min((int64_t)NT, (int64_t)maxlast - jb);
-        for (int j = cnt - 1; j >= 0; j--) {
+        // one entry: this thread's R pixels walk back past entry j (their
+        // transmittance and behind-colour state), and gr receives the eight
+        // terms summed over them; returns whether any pixel of the wave
+        // takes the entry
+        auto entry = [&](int j, float gr[8], float& gop) -> bool {
             const uint32_t ej = (uint32_t)jb + (uint32_t)j;
-            float gr[8];   // this thread's sums of the eight terms over its R pixels
-            float gop = 0.f;
-            bool act = false;
+            gop = 0.f;
+            uint64_t act = 0ull;
             const float4 w0 = s_w0[j], w1 = s_w1[j], w2 = s_w2[j];
             const uint32_t box = __float_as_uint(w2.w);
             const float cr = w1.z, cg = w1.w, cb = w2.x;
@@ -633,40 +783,78 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
                 const float G = __expf(power[k]);
                 const float raw = w1.y * G;
                 const float alpha = fminf(0.99f, raw);
-                act = act || ok[k];
+                act |= __ballot(ok[k]);
                 // T recovery T_i = T_{i+1} / (1 - alpha_i), with the hardware reciprocal (1 ulp)
                 const float Tk = ok[k] ? T[k] * __builtin_amdgcn_rcpf(1.0f - alpha) : T[k];
                 T[k] = Tk;
                 const float aok = ok[k] ? alpha : 0.0f;   // zero: the pixel's state is kept
                 const float wgt = aok * Tk;
-                const float e0 = cr - b0[k], e1 = cg - b1[k], e2 = cb - b2[k];
-                const float dal = Tk * (g0[k] * e0 + g1[k] * e1 + g2[k] * e2);
-                // colour behind the next contributor: alpha c + (1 - alpha) b
-                b0[k] += aok * e0;
-                b1[k] += aok * e1;
-                b2[k] += aok * e2;
+                const float e = (g0[k] * cr + g1[k] * cg + g2[k] * cb) - gb[k];
+                const float dal = Tk * e;
+                gb[k] += aok * e;
                 const bool unclamped = ok[k] && raw < 0.99f;
                 const float dp = unclamped ? dal * raw : 0.0f;
                 gop += unclamped ? dal * G : 0.0f;
-                // d power / d(u, v) = (A dx + B dy, B dx + C dy); the conic
-                // terms -dx^2 / 2, -dx dy, -dy^2 / 2 get their constant factors
-                // after the reduction (kConicScale)
+                // d power / d(u, v) = (A dx + B dy, B dx + C dy): the sums of
+                // dp dx and dp dy take A, B, C after the reduction; the conic
+                // terms -dx^2 / 2, -dx dy, -dy^2 / 2 get their constant
+                // factors there too (kConicScale)
                 const float tx = dp * dx, ty = dp * dy[k];
-                const float t8[8] = {w0.z * tx + w0.w * ty, w0.w * tx + w1.x * ty, tx * dx, tx * dy[k],
-                                     ty * dy[k], g0[k] * wgt, g1[k] * wgt, g2[k] * wgt};
+                const float t8[8] = {tx, ty, tx * dx, tx * dy[k], ty * dy[k], g0[k] * wgt, g1[k] * wgt, g2[k] * wgt};
 #pragma unroll
                 for (int c = 0; c < 8; c++) gr[c] = k == 0 ? t8[c] : gr[c] + t8[c];
             }
-            const bool any = __any(act);
+            return act != 0ull;
+        };
+        // two entries per reduction: their exchanges and DPP chains overlap
+        int j = cnt - 1;
+        for (; j >= 1; j -= 2) {
+            float ga[8], gc[8], opa, opc;
+            const bool anya = entry(j, ga, opa);
+            const bool anyc = entry(j - 1, gc, opc);
+            float ra = 0.f, rc = 0.f;
+            if (anya || anyc) wave_reduce_scatter8x2(ga, gc, lane, ra, rc);
+            if ((lane & 7) == 0) {
+                s_g[wv][my_slot][j] = ra;
+                s_g[wv][my_slot][j - 1] = rc;
+            }
+            if (kOpacity) {
+                const float oa = anya ? wave_sum_dpp(opa) : 0.f;
+                const float oc = anyc ? wave_sum_dpp(opc) : 0.f;
+                if (lane == 8) {
+                    s_g[wv][5][j] = oa;
+                    s_g[wv][5][j - 1] = oc;
+                }
+            }
+        }
+        if (j == 0) {
+            float ga[8], opa;
+            const bool any = entry(0, ga, opa);
             float red = 0.f, redop = 0.f;
             if (any) {
-                red = wave_reduce_scatter8(gr, lane);
-                if (kOpacity) redop = wave_sum_dpp(gop);
+                red = wave_reduce_scatter8(ga, lane);
+                if (kOpacity) redop = wave_sum_dpp(opa);
             }
-            if ((lane & 7) == 0) s_g[wv][my_slot][j] = red;
-            if (kOpacity && lane == 8) s_g[wv][5][j] = redop;
+            if ((lane & 7) == 0) s_g[wv][my_slot][0] = red;
+            if (kOpacity && lane == 8) s_g[wv][5][0] = redop;
         }
         __syncthreads();
+        // term k of entry e summed over the waves: the mean terms from the
+        // sums of dp dx and dp dy and the entry's conic (A, B, C)
+        auto entry_term = [&](int k, int e) -> float {
+            float v = s_g[0][k][e];
+#pragma unroll
+            for (int w = 1; w < NW; w++) v += s_g[w][k][e];
+            if (k <= 1) {
+                float o = s_g[0][1 - k][e];
+#pragma unroll
+                for (int w = 1; w < NW; w++) o += s_g[w][1 - k][e];
+                const float4 w0 = s_w0[e];
+                const float C = s_w1[e].x;
+                return k == 0 ? w0.z * v + w0.w * o : w0.w * o + C * v;
+            }
+            return v * kConicScale[k];
+        };
         if (kRecords) {
             if ((int)threadIdx.x < cnt) {
                 const uint32_t widx = woff + (uint32_t)jb + threadIdx.x;   // compact index of this walked entry
@@ -677,10 +865,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
                         if (fits) grec[(int64_t)k * grec_cap + widx] = 0.f;
                         continue;
                     }
-                    float v = s_g[0][k][threadIdx.x];
-#pragma unroll
-                    for (int w = 1; w < NW; w++) v += s_g[w][k][threadIdx.x];
-                    v *= kConicScale[k];
+                    const float v = entry_term(k, threadIdx.x);
                     if (fits)
                         grec[(int64_t)k * grec_cap + widx] = v;
                     else if (v != 0.f)
@@ -693,10 +878,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
             for (int q = threadIdx.x; q < 9 * cnt; q += NT) {
                 const int e = q / 9, k = q - 9 * e;
                 if (!kOpacity && k == 5) continue;
-                float v = s_g[0][k][e];
-#pragma unroll
-                for (int w = 1; w < NW; w++) v += s_g[w][k][e];
-                v *= kConicScale[k];
+                const float v = entry_term(k, e);
                 if (v != 0.f) atomicAdd(accum + 9 * (int64_t)s_id[e] + k, v);
             }
         }
@@ -965,23 +1147,87 @@ static dim3 bin_grid(int64_t nchunks, int tiles_y) {
 }
 
 void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, int tiles_x, int tiles_y,
-               uint32_t* hist) {
+               uint32_t* hist, uint32_t* ttot) {
     const int64_t nchunks = n > 0 ? bin_chunks(n) : 0;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_count", L.st);
-    hipLaunchKernelGGL(k_bin_count, bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, srect, n, tiles_x, tiles_y,
-                       nchunks, hist);
+    if (ttot) fill_u32(L, ttot, 0u, (int64_t)tiles_x * tiles_y);
+    const unsigned grid = (unsigned)((nchunks / kCountGroup) * ((tiles_y + kBinRowsPerBlock - 1) / kBinRowsPerBlock));
+    hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(kBinThreads), 0, L.st, srect, n, tiles_x, tiles_y, nchunks, hist,
+                       ttot);
+    if (L.prof) L.prof->end(L.st);
+}
+
+void ranges_from_starts(const Launch& L, const uint32_t* start, const uint32_t* len, int ntiles, uint64_t cap,
+                        uint2* ranges) {
+    if (L.prof) L.prof->begin("tile_ranges", L.st);
+    hipLaunchKernelGGL(k_ranges_from_starts, dim3(blocks_for(ntiles, 256)), dim3(256), 0, L.st, start, len, ntiles,
+                       cap, ranges);
+    if (L.prof) L.prof->end(L.st);
+}
+
+int64_t bin_scan_part_words(int64_t nchunks, int ntiles) {
+    return ((nchunks + kBinScanSeg - 1) / kBinScanSeg) * (int64_t)ntiles;
+}
+
+void bin_scan(const Launch& L, const uint32_t* hist, int64_t nchunks, int ntiles, uint32_t cap, uint32_t* base,
+              uint64_t* total, uint32_t* part, uint32_t* ttot, uint64_t* toff, uint64_t* tmp) {
+    if (nchunks <= 0 || ntiles <= 0) return;
+    if (L.prof) L.prof->begin("scan", L.st);
+    const int64_t nseg = (nchunks + kBinScanSeg - 1) / kBinScanSeg;
+    const dim3 grid((unsigned)((ntiles + 255) / 256), (unsigned)std::min<int64_t>(nseg, 65535));
+    hipLaunchKernelGGL(k_bin_scan_part, grid, dim3(256), 0, L.st, hist, nchunks, ntiles, nseg, part);
+    hipLaunchKernelGGL(k_bin_scan_tiles, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, L.st, part, nseg,
+                       ntiles, ttot);
+    if (L.prof) L.prof->end(L.st);
+    scan_u32_to_u64(L, ttot, ntiles, toff, total, tmp);
+    if (L.prof) L.prof->begin("scan", L.st);
+    hipLaunchKernelGGL(k_bin_scan_base, grid, dim3(256), 0, L.st, hist, nchunks, ntiles, nseg, part, toff, cap, base);
+    if (L.prof) L.prof->end(L.st);
+}
+
+template <typename B>
+static void bin_scatter_impl(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect,
+                             const uint32_t* sgoff, int tiles_x, int tiles_y, const B* base, uint64_t cap,
+                             uint32_t* vals, uint32_t* gpos) {
+    const int64_t nchunks = n > 0 ? bin_chunks(n) : 0;
+    if (nchunks == 0) return;
+    if (L.prof) L.prof->begin("bin_scatter", L.st);
+    hipLaunchKernelGGL(k_bin_rows<B>, bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, order, n, srect, sgoff,
+                       tiles_x, tiles_y, nchunks, base, (uint32_t)cap, vals, gpos);
     if (L.prof) L.prof->end(L.st);
 }
 
 void bin_scatter(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, const uint32_t* sgoff,
-                 int tiles_x, int tiles_y, const uint64_t* base, uint64_t cap, uint32_t* vals, uint32_t* gpos) {
-    const int64_t nchunks = n > 0 ? bin_chunks(n) : 0;
-    if (nchunks == 0) return;
-    if (L.prof) L.prof->begin("bin_scatter", L.st);
-    hipLaunchKernelGGL(k_bin_rows, bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, order, n, srect, sgoff,
-                       tiles_x, tiles_y, nchunks, base, (uint32_t)cap, vals, gpos);
-    if (L.prof) L.prof->end(L.st);
+                 int tiles_x, int tiles_y, const uint32_t* base, uint64_t cap, uint32_t* vals, uint32_t* gpos) {
+    bin_scatter_impl(L, order, n, srect, sgoff, tiles_x, tiles_y, base, cap, vals, gpos);
+}
+
+void bin_scatter_chunked(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, int tiles_x,
+                         int tiles_y, const uint64_t* cmb, uint64_t cap, uint32_t* vals) {
+    bin_scatter_impl(L, order, n, srect, (const uint32_t*)nullptr, tiles_x, tiles_y, cmb, cap, vals,
+                     (uint32_t*)nullptr);
+}
+
+__global__ __launch_bounds__(256) void k_chunked_to_tile_major(const uint32_t* __restrict__ hist,
+                                                               const uint64_t* __restrict__ cmb,
+                                                               const uint32_t* __restrict__ base_tm, int64_t m,
+                                                               uint64_t cap, const uint32_t* __restrict__ vals_cm,
+                                                               uint32_t* __restrict__ vals_tm) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (chunk, tile) in [chunk][tile] order
+    if (i >= m) return;
+    const uint32_t len = hist[i];
+    const uint64_t src = cmb[i], dst = base_tm[i];
+    for (uint32_t k = 0; k < len; k++)
+        if (src + k < cap && dst + k < cap) vals_tm[dst + k] = vals_cm[src + k];
+}
+
+void chunked_to_tile_major(const Launch& L, const uint32_t* hist, const uint64_t* cmb, const uint32_t* base_tm,
+                           int64_t nchunks, int ntiles, uint64_t cap, const uint32_t* vals_cm, uint32_t* vals_tm) {
+    const int64_t m = nchunks * ntiles;
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_chunked_to_tile_major, dim3(blocks_for(m, 256)), dim3(256), 0, L.st, hist, cmb, base_tm, m, cap,
+                       vals_cm, vals_tm);
 }
 
 void gpos_from_pairs(const Launch& L, const uint64_t* keys, const uint32_t* vals, int64_t K, const uint2* rect,
@@ -991,11 +1237,11 @@ void gpos_from_pairs(const Launch& L, const uint64_t* keys, const uint32_t* vals
                        tiles_x, cap, gpos);
 }
 
-void ranges_from_hist(const Launch& L, const uint64_t* base, const uint64_t* total, int ntiles, int nchunks,
-                      uint64_t cap, uint2* ranges, int* overflow) {
+void ranges_from_hist(const Launch& L, const uint32_t* base, const uint64_t* total, int ntiles, uint64_t cap,
+                      uint2* ranges, int* overflow) {
     if (L.prof) L.prof->begin("tile_ranges", L.st);
-    hipLaunchKernelGGL(k_ranges_from_hist, dim3(blocks_for(ntiles, 256)), dim3(256), 0, L.st, base, total, ntiles,
-                       (int64_t)nchunks, cap, ranges, overflow);
+    hipLaunchKernelGGL(k_ranges_from_hist, dim3(blocks_for(ntiles, 256)), dim3(256), 0, L.st, base, total, ntiles, cap,
+                       ranges, overflow);
     if (L.prof) L.prof->end(L.st);
 }
 
@@ -1016,12 +1262,18 @@ void tile_order(const Launch& L, const uint2* ranges, const uint32_t* walk, int 
 }
 
 void blend_forward(const Launch& L, const CamDev& cam, const uint2* ranges, const uint32_t* vals, const float4* rec,
-                   float* image, float* T_final, uint32_t* last, uint32_t* tile_walk, const int* order) {
+                   float* image, float* T_final, uint32_t* last, uint32_t* tile_walk, const int* order,
+                   const ChunkDev* chunks) {
     const int ntiles = cam.tiles_x * cam.tiles_y;
     if (L.prof) L.prof->begin("blend_fwd", L.st);
-    hipLaunchKernelGGL(k_blend_fwd<kBlendRows>, dim3(order ? (unsigned)ntiles : blend_grid(ntiles)),
-                       dim3(kTile * kTile / kBlendRows), 0, L.st, cam, ntiles, ranges, vals, rec, image, T_final, last,
-                       tile_walk, order);
+    const dim3 grid(order ? (unsigned)ntiles : blend_grid(ntiles));
+    const ChunkDev cl = chunks ? *chunks : ChunkDev{};
+    if (chunks)
+        hipLaunchKernelGGL((k_blend_fwd<kBlendRows, true>), grid, dim3(kTile * kTile / kBlendRows), 0, L.st, cam, ntiles,
+                           ranges, vals, rec, image, T_final, last, tile_walk, order, cl);
+    else
+        hipLaunchKernelGGL((k_blend_fwd<kBlendRows, false>), grid, dim3(kTile * kTile / kBlendRows), 0, L.st, cam,
+                           ntiles, ranges, vals, rec, image, T_final, last, tile_walk, order, cl);
     if (L.prof) L.prof->end(L.st);
 }
 

@@ -187,11 +187,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict_
     if (dtotal) {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
         const uint32_t v = dtotal[threadIdx.x];
-        uint32_t x = v;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x, off, 64);
-            if (lane >= off) x += y;
-        }
+        const uint32_t x = wave_incl_scan_u32(v);
         if (lane == 63) s_dw[w] = x;
         __syncthreads();
         dbase = x - v;
@@ -229,8 +225,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict_
 #pragma unroll
     for (int r = 0; r < I; r++) {
         const int64_t idx = base + r * 64 + lane;
-        if (idx < n) {
-            const uint32_t pos = s_base[w][dig[r]] + rank[r];
+        const uint32_t pos = s_base[w][dig[r]] + rank[r];
+        if (idx < n && pos < (uint64_t)n) {   // pos < n always holds for consistent counts
             kout[pos] = key[r];
             vout[pos] = val[r];
         }
@@ -248,13 +244,9 @@ __global__ __launch_bounds__(64) void k_radix_digit_scan(uint32_t* __restrict__ 
     for (int64_t i0 = 0; i0 < nb; i0 += 64) {
         const int64_t i = i0 + lane;
         const uint32_t v = i < nb ? h[i] : 0u;
-        uint32_t x = v;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x, off, 64);
-            if (lane >= off) x += y;
-        }
+        const uint32_t x = wave_incl_scan_u32(v);
         if (i < nb) h[i] = carry + x - v;
-        carry += __shfl(x, 63, 64);
+        carry += lane63_u32(x);
     }
     if (lane == 0) dtotal[blockIdx.x] = carry;
 }
