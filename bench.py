@@ -612,6 +612,38 @@ def main():
         all_roof[k] = (round(amount / sec / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4) if bound == "alu"
                        else round(amount / sec / 1e9 / HBM_PEAK_GBS, 4))
 
+    # the NTC table gradient two ways on the same loop: the CSR gather over
+    # the per-frame contribution lists (the step above) and per-point float
+    # atomics into the table (token 0: no contribution lists, and the
+    # backward gathers the encoding again)
+    table_grad = None
+    if "ntc_bwd" in kernels:
+        tok = st1.token
+        st1.token = 0
+        for _ in range(args.warmup):
+            st1.step()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_reset()
+        for _ in range(args.steps):
+            st1.step()
+        torch.cuda.synchronize()
+        ctx.profile(False)
+        st1.token = tok
+
+        def per_step(name):
+            ms, cnt = ctx.profile_query(name)
+            return ms / args.steps if cnt else 0.0
+
+        csr = {k: round(kernels[k]["ms_per_launch"] * kernels[k]["launches_per_step"], 4)
+               for k in ("ntc_fwd", "ntc_bwd", "ntc_scatter") if k in kernels}
+        atom = {k: round(per_step(k), 4) for k in ("ntc_fwd", "ntc_bwd")}
+        table_grad = {"csr_gather_ms_per_step": csr, "csr_gather_backward_ms": round(csr["ntc_bwd"] +
+                                                                                    csr.get("ntc_scatter", 0.0), 4),
+                      "atomic_ms_per_step": atom, "atomic_backward_ms": atom["ntc_bwd"],
+                      "used": "csr_gather"}
+        ctx.ntc_load(params_warm)
+
     qual = None
     if not args.no_quality:
         del st1
@@ -645,7 +677,7 @@ def main():
         "warmup_s": round(t_warm, 3), "warmup_iters": args.warmup_iters, "frame_setup_s": round(t_prepare + t_reorder, 4),
         "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in kernels.items()},
         "roofline": roof, "roofline_frac_by_kernel": all_roof, "rasterizer_hbm": raster_hbm, "cpu_baseline": base,
-        "equal_psnr": qual,
+        "ntc_table_gradient": table_grad, "equal_psnr": qual,
     }
     print(json.dumps(res))
 

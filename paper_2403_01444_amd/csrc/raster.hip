@@ -108,16 +108,13 @@ __global__ __launch_bounds__(256) void k_ranges_from_keys(const uint64_t* __rest
 // depth-first ordering.  The Gaussians are first sorted by (depth bits,
 // index) and their tile rectangles gathered into that order.  The sorted
 // sequence is cut into chunks of kBinChunk.  A workgroup stages one chunk's
-// rectangles in LDS; each of its four waves owns one tile row and walks the
-// chunk in order, taking 64 Gaussians per step and visiting (ballot, lowest
-// set bit first) those whose rectangle spans its row.  Lane l keeps the
-// cursors of columns l, l + 64, ... in registers, so a Gaussian's tiles are
-// updated in parallel and no two lanes share a cursor.  Pass 1 counts pairs
-// per (tile, chunk); an exclusive scan in tile-major order gives each
-// (tile, chunk) its first slot; pass 2 repeats the walk and writes Gaussian
-// indices at consecutive slots.  Inside a tile the result is ordered by
-// (chunk, position in chunk), i.e. by (depth bits, index): the order a stable
-// (tile, depth) sort gives.
+// rectangles in LDS; each of its waves owns one tile row.  Pass 1 counts
+// pairs per (chunk, tile); an exclusive scan of the counts gives each
+// (chunk, tile) segment its first slot; pass 2 lists the chunk's Gaussians
+// spanning the row in depth order and writes, column by column, the indices
+// of those covering the column at consecutive slots of the segment.  Inside
+// a tile the result is ordered by (chunk, position in chunk), i.e. by
+// (depth bits, index): the order a stable (tile, depth) sort gives.
 // ---------------------------------------------------------------------------
 #ifndef GS3_BIN_ROWS
 #define GS3_BIN_ROWS 8
@@ -288,27 +285,32 @@ __global__ __launch_bounds__(256) void k_bin_scan_base(const uint32_t* __restric
 
 // Scatter pass, one wave per (tile row, chunk of depth-ordered Gaussians):
 // the wave lists the chunk's Gaussians whose rectangle spans its row, in
-// depth order, then walks that list once with lane = tile column (lanes
-// l, l + 64, ... of the row): every column takes each listed Gaussian that
-// covers it at its cursor, which starts at the slot the scan of the counts
-// gave, so every tile's entries keep the depth order.  The first slot of
-// each (chunk, tile) segment comes from `base` in [chunk][tile] layout: the
-// tile-major list's slots (u32, already clamped to cap) or the chunk-major
-// list's (u64: the segments of one chunk in tile order, so a wave's row of
-// one chunk is a single run of consecutive slots).
+// depth order, and holds that list in registers, 64 Gaussians per group
+// (lane = position in the group).  It then walks the row's columns: at
+// column tx the Gaussians covering tx find their rank among the covering
+// ones by a ballot and a masked bit count, and write their indices at
+// consecutive slots from the (chunk, tile) segment's first slot.  One store
+// instruction therefore fills one segment (about a dozen consecutive
+// words) instead of touching a dozen tiles' lists, and every tile's entries
+// keep the depth order.  The first slot of each (chunk, tile) segment comes
+// from `base` in [chunk][tile] layout: the tile-major list's slots (u32,
+// already clamped to cap) or the chunk-major list's (u64).
+constexpr int kBinGroups = kBinChunk / 64;   // register groups of the covering list
+static_assert(kBinChunk % 64 == 0, "the covering list is held in groups of 64");
+
 template <typename B>
 __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __restrict__ order, int64_t n,
                                                   const uint2* __restrict__ srect, const uint32_t* __restrict__ sgoff,
                                                   int tiles_x, int tiles_y, int64_t nchunks,
                                                   const B* __restrict__ base, uint32_t cap,
                                                   uint32_t* __restrict__ vals, uint32_t* __restrict__ gpos) {
-    // A cursor starts at min(first slot, cap) and moves at most kBinChunk
-    // past it, so with cap < 2^31 it never wraps; slots at or past cap are
-    // not written.
+    // A segment's slots start at min(first slot, cap) and run at most
+    // kBinChunk past it, so with cap < 2^31 they never wrap; slots at or
+    // past cap are not written.
     __shared__ uint2 s_rect[kBinChunk];
     __shared__ uint32_t s_id[kBinChunk];
     __shared__ uint32_t s_goff[kBinChunk];
-    __shared__ uint2 s_cov[kBinRowsPerBlock][kBinChunk];   // covering Gaussians: (tx0 | tx1 << 16, chunk position)
+    __shared__ uint32_t s_cov[kBinRowsPerBlock][kBinChunk];   // chunk positions of the row's covering Gaussians
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int rowblock;
     int64_t chunk;
@@ -329,49 +331,86 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __rest
     for (int eb = 0; eb < m; eb += 64) {
         const int e = eb + lane;
         bool cov = false;
-        uint2 r = make_uint2(0u, 0u);
         if (e < m) {
-            r = s_rect[e];
+            const uint2 r = s_rect[e];
             cov = (int)(r.x >> 16) <= row && row <= (int)(r.y >> 16);
         }
         const uint64_t bal = __ballot(cov);
-        if (cov) s_cov[w][G + __popcll(bal & below)] = make_uint2((r.x & 0xFFFFu) | (r.y << 16), (uint32_t)e);
+        if (cov) s_cov[w][G + __popcll(bal & below)] = (uint32_t)e;
         G += __popcll(bal);
     }
+    if (G == 0) return;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // 2. lane = column: up to four column groups of 64 (kMaxTilesX = 256)
-    const B* brow = base + chunk * ((int64_t)tiles_x * tiles_y) + (int64_t)row * tiles_x;
-    uint32_t cur[4];
+    // 2. the list in registers: column span, index and (record mode) the
+    // slot of column 0 of this row in the Gaussian's own pair range
+    int lo[kBinGroups], hi[kBinGroups];
+    uint32_t gid[kBinGroups], gk[kBinGroups];
+    int cmin = 1 << 30, cmax = -1;
 #pragma unroll
-    for (int cg = 0; cg < 4; cg++) {
-        const int tx = 64 * cg + lane;
-        const uint64_t b = tx < tiles_x ? (uint64_t)brow[tx] : (uint64_t)cap;
-        cur[cg] = b < (uint64_t)cap ? (uint32_t)b : cap;
+    for (int gi = 0; gi < kBinGroups; gi++) {
+        lo[gi] = 1 << 30;
+        hi[gi] = -1;
+        gid[gi] = 0u;
+        gk[gi] = 0u;
+        const int k = 64 * gi + lane;
+        if (64 * gi < G && k < G) {
+            const uint32_t e = s_cov[w][k];
+            const uint2 r = s_rect[e];
+            lo[gi] = (int)(r.x & 0xFFFFu);
+            hi[gi] = (int)(r.y & 0xFFFFu);   // < tiles_x
+            gid[gi] = s_id[e];
+            if (gpos)
+                gk[gi] = s_goff[e] + (uint32_t)(row - (int)(r.x >> 16)) * (uint32_t)(hi[gi] - lo[gi] + 1) -
+                         (uint32_t)lo[gi];
+            cmin = min(cmin, lo[gi]);
+            cmax = max(cmax, hi[gi]);
+        }
     }
-    const int ncg = (tiles_x + 63) >> 6;
-    for (int k = 0; k < G; k++) {
-        const uint2 cv = s_cov[w][k];
-        const int tx0 = (int)(cv.x & 0xFFFFu), tx1 = (int)(cv.x >> 16);
-        const uint32_t id = s_id[cv.y];
 #pragma unroll
-        for (int cg = 0; cg < 4; cg++) {
-            if (cg >= ncg) break;
-            const int tx = 64 * cg + lane;
-            if (tx >= tx0 && tx <= tx1) {   // tx1 < tiles_x
-                const uint32_t pos = cur[cg];
-                if (pos < cap) {
-                    vals[pos] = id;
-                    if (gpos) {
-                        // slot of this pair in its Gaussian's own pair range
-                        const uint2 r = s_rect[cv.y];
-                        const uint32_t kk = s_goff[cv.y] + (uint32_t)(row - (int)(r.x >> 16)) *
-                                                               (uint32_t)(tx1 - tx0 + 1) + (uint32_t)(tx - tx0);
-                        if (kk < cap) gpos[kk] = pos;
+    for (int off = 32; off >= 1; off >>= 1) {
+        cmin = min(cmin, __shfl_xor(cmin, off));
+        cmax = max(cmax, __shfl_xor(cmax, off));
+    }
+    cmin = __builtin_amdgcn_readfirstlane(cmin);
+    cmax = __builtin_amdgcn_readfirstlane(cmax);
+    const int ngr = (G + 63) >> 6;
+    // 3. the columns the list covers; lane l of colb[cg] holds the first
+    // slot of column 64 cg + l
+    const B* brow = base + chunk * ((int64_t)tiles_x * tiles_y) + (int64_t)row * tiles_x;
+    uint32_t colb[kMaxTilesX / 64];
+#pragma unroll
+    for (int cg = 0; cg < kMaxTilesX / 64; cg++) {
+        const int tx = 64 * cg + lane;
+        const uint64_t b = (tx < tiles_x && cg * 64 <= cmax) ? (uint64_t)brow[tx] : (uint64_t)cap;
+        colb[cg] = b < (uint64_t)cap ? (uint32_t)b : cap;
+    }
+#pragma unroll
+    for (int cg = 0; cg < kMaxTilesX / 64; cg++) {
+        if (64 * cg > cmax) break;
+        const int t0 = max(cmin, 64 * cg), t1 = min(cmax, 64 * cg + 63);
+        for (int tx = t0; tx <= t1; tx++) {
+            uint32_t pos = (uint32_t)__builtin_amdgcn_readlane((int)colb[cg], tx - 64 * cg);
+#pragma unroll
+            for (int gi = 0; gi < kBinGroups; gi++) {
+                if (gi >= ngr) break;
+                const bool c = lo[gi] <= tx && tx <= hi[gi];
+                const uint64_t bal = __builtin_amdgcn_ballot_w64(c);
+                if (c) {
+                    // rank among the covering lanes below this one
+                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                    const uint32_t slot = pos + rank;
+                    if (slot < cap) {
+                        vals[slot] = gid[gi];
+                        if (gpos) {
+                            const uint32_t kk = gk[gi] + (uint32_t)tx;
+                            if (kk < cap) gpos[kk] = slot;
+                        }
                     }
                 }
-                cur[cg] = pos + 1u;
+                pos += (uint32_t)__popcll(bal);
             }
         }
     }
@@ -612,6 +651,10 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                     for (int k = 0; k < R; k++)
                         if (band[k]) ok[k] = blend_exact_test(power[k], w1.y);
                 }
+                bool any_ok = false;   // no pixel of the wave takes the entry: nothing changes
+#pragma unroll
+                for (int k = 0; k < R; k++) any_ok = any_ok || ok[k];
+                if (!__any(any_ok)) return;
 #pragma unroll
                 for (int k = 0; k < R; k++) {
                     const float alpha = fminf(0.99f, w1.y * __expf(power[k]));
@@ -674,6 +717,10 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
 // (tile, Gaussian).  kOpacity: also reduce the opacity term.
 // factors of the nine reduced terms: the conic terms are summed as dx^2,
 // dx dy and dy^2 (powers of two: the scaling is exact)
+#ifndef GS3_BWD_BATCH
+#define GS3_BWD_BATCH 128
+#endif
+constexpr int kBwdBatch = GS3_BWD_BATCH;   // backward blend: entries staged per batch (LDS: about 200 B each)
 __constant__ float kConicScale[9] = {1.f, 1.f, -0.5f, -1.f, -0.5f, 1.f, 1.f, 1.f, 1.f};
 
 template <int R, bool kRecords, bool kOpacity>
@@ -690,11 +737,12 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
                                                                  float* __restrict__ accum,
                                                                  const int* __restrict__ order) {
     constexpr int NT = kTile * kTile / R, NW = NT / 64;
-    __shared__ float4 s_w0[NT];
-    __shared__ float4 s_w1[NT];
-    __shared__ float4 s_w2[NT];   // blend_stage_w2 form
-    __shared__ uint32_t s_id[NT];
-    __shared__ float s_g[NW][9][NT + 1];   // per-wave sums, [wave][term][entry] (padded: term rows on distinct banks)
+    constexpr int KB = kBwdBatch < NT ? kBwdBatch : NT;   // entries staged per batch
+    __shared__ float4 s_w0[KB];
+    __shared__ float4 s_w1[KB];
+    __shared__ float4 s_w2[KB];   // blend_stage_w2 form
+    __shared__ uint32_t s_id[KB];
+    __shared__ float s_g[NW][9][KB + 1];   // per-wave sums, [wave][term][entry] (padded: term rows on distinct banks)
     const int tile = order ? order[blockIdx.x] : tile_of_block(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const uint32_t maxlast = tile_walk[tile];
@@ -734,10 +782,17 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
     // dp dy (the conic is applied to the sums per entry), the conic terms,
     // r, g, b; lane group (lane >> 3) holds term (lane >> 3)
     const int my_term = lane >> 3;
+    // the wave's last contributor: entries past it reach none of its pixels
+    uint32_t wlast = 0u;
+#pragma unroll
+    for (int k = 0; k < R; k++) wlast = max(wlast, last[k]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, off));
+    wlast = __builtin_amdgcn_readfirstlane(wlast);
     const int my_slot = my_term < 5 ? my_term : my_term + 1;   // index in the nine-term layout
-    for (int64_t jb = ((int64_t)(maxlast - 1) / NT) * NT; jb >= 0; jb -= NT) {
+    for (int64_t jb = ((int64_t)(maxlast - 1) / KB) * KB; jb >= 0; jb -= KB) {
         const uint32_t e = (uint32_t)jb + threadIdx.x;
-        if (e < maxlast) {
+        if ((int)threadIdx.x < KB && e < maxlast) {
             const uint32_t id = vals[start + e];
             s_id[threadIdx.x] = id;
             s_w0[threadIdx.x] = rec[3 * (int64_t)id + 0];
@@ -745,7 +800,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
             s_w2[threadIdx.x] = blend_stage_w2(rec[3 * (int64_t)id + 2], tx0p, ty0p);
         }
         __syncthreads();
-        const int cnt = (int)min((int64_t)NT, (int64_t)maxlast - jb);
+        const int cnt = (int)min((int64_t)KB, (int64_t)maxlast - jb);
         // one entry: this thread's R pixels walk back past entry j (their
         // transmittance and behind-colour state), and gr receives the eight
         // terms summed over them; returns whether any pixel of the wave
@@ -753,6 +808,11 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
         auto entry = [&](int j, float gr[8], float& gop) -> bool {
             const uint32_t ej = (uint32_t)jb + (uint32_t)j;
             gop = 0.f;
+            if (ej >= wlast) {
+#pragma unroll
+                for (int c = 0; c < 8; c++) gr[c] = 0.f;
+                return false;
+            }
             uint64_t act = 0ull;
             const float4 w0 = s_w0[j], w1 = s_w1[j], w2 = s_w2[j];
             const uint32_t box = __float_as_uint(w2.w);
@@ -775,6 +835,15 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
 #pragma unroll
                 for (int k = 0; k < R; k++)
                     if (band[k]) ok[k] = blend_exact_test(power[k], w1.y);
+            }
+            // no pixel of the wave takes the entry: its state and sums stay
+            bool any_ok = false;
+#pragma unroll
+            for (int k = 0; k < R; k++) any_ok = any_ok || ok[k];
+            if (!__any(any_ok)) {
+#pragma unroll
+                for (int c = 0; c < 8; c++) gr[c] = 0.f;
+                return false;
             }
             // branch-free per-pixel body: selects keep the state of pixels
             // that this Gaussian does not reach
