@@ -413,15 +413,53 @@ __device__ __forceinline__ uint32_t span_mask16(int lo, int hi) {
 // The LDS form of a record's third quad in the blend loops of the tile whose
 // first pixel is (tx0p, ty0p): colour b, the lower and upper edge of the
 // exponent band around the opacity threshold (pthr -/+ 1e-4, the same
-// single-precision operations the per-pixel test used), and the pixel box as
+// single-precision operations the per-pixel test used), and a pixel box as
 // a mask of the tile columns (bits 0-15) and rows (bits 16-31) it covers.  A
 // pixel at (lx, ly) of the tile is inside the box iff both of its bits
-// (1 << lx) | (1 << (16 + ly)) are set.
-__device__ __forceinline__ float4 blend_stage_w2(const float4& w2, int tx0p, int ty0p) {
+// (1 << lx) | (1 << (16 + ly)) are set.  kTight: the record's pixel box is
+// cut to the bounding box of the ellipse where the exponent can reach the
+// band's lower edge: with M = [[A, B], [B, C]] (the conic), -power / 2 =
+// d^T M d / 2 <= -(pthr - 1e-4) bounds |dx| by sqrt(k (M^-1)_xx) and |dy| by
+// sqrt(k (M^-1)_yy), k = -2 (pthr - 1e-4), here widened by 0.1% and a pixel.
+// It only drops pixels whose exponent is below the band (their opacity test
+// fails), so every pixel that takes the entry is still inside.  The pixel
+// margin is worth about 2 k / h of the quadratic form at half-width h; the
+// single-precision exponent of a pixel in the record's box can be off by a
+// few ulps of 9 cond(M), so the box is only cut where cond(M) h stays well
+// below what the margin covers (cond(M) <= (A + C)^2 / det M).
+template <bool kTight = true>
+__device__ __forceinline__ float4 blend_stage_w2(const float4& w0, const float4& w1, const float4& w2, int tx0p,
+                                                 int ty0p) {
     const uint32_t b0 = __float_as_uint(w2.y), b1 = __float_as_uint(w2.z);
-    const uint32_t cm = span_mask16((int)(b0 & 0xFFFFu) - tx0p, (int)(b1 & 0xFFFFu) - tx0p);
-    const uint32_t rm = span_mask16((int)(b0 >> 16) - ty0p, (int)(b1 >> 16) - ty0p);
+    int x0 = (int)(b0 & 0xFFFFu), y0 = (int)(b0 >> 16), x1 = (int)(b1 & 0xFFFFu), y1 = (int)(b1 >> 16);
+    const float A = w0.z, B = w0.w, C = w1.x;
+    const float k = fmaxf(-2.0f * (w2.w - 1e-4f), 0.0f) * 1.001f;
+    const float det = A * C - B * B;
+    const float hx = sqrtf(k * C / det) + 1.0f, hy = sqrtf(k * A / det) + 1.0f;
+    const float cond = (A + C) * (A + C) / det;
+    if (kTight && det > 0.0f && hx <= 1e6f && hy <= 1e6f && fabsf(w0.x) <= 1e6f && fabsf(w0.y) <= 1e6f &&
+        cond * fmaxf(hx, hy) <= 4e4f * k) {
+        x0 = max(x0, (int)floorf(w0.x - hx));
+        x1 = min(x1, (int)ceilf(w0.x + hx));
+        y0 = max(y0, (int)floorf(w0.y - hy));
+        y1 = min(y1, (int)ceilf(w0.y + hy));
+    }
+    const uint32_t cm = span_mask16(x0 - tx0p, x1 - tx0p);
+    const uint32_t rm = span_mask16(y0 - ty0p, y1 - ty0p);
     return make_float4(w2.x, w2.w - 1e-4f, w2.w + 1e-4f, __uint_as_float(cm | (rm << 16)));
+}
+
+// Rows of the tile that wave wv of a blend workgroup covers (16 columns x R
+// rows per 16 threads), as bits 16-31 of a box mask.
+template <int R>
+__device__ __forceinline__ uint32_t wave_row_bits(int wv) {
+    return (R * 4 >= 16 ? 0xFFFFu : ((1u << (4 * R)) - 1u) << (4 * R * wv)) << 16;
+}
+
+// Whether a staged box mask reaches a pixel of the wave's rows.
+__device__ __forceinline__ bool box_meets_rows(float w2w, uint32_t rows) {
+    const uint32_t m = __float_as_uint(w2w);
+    return (m & rows) != 0u && (m & 0xFFFFu) != 0u;
 }
 
 // wave64 helpers

@@ -784,7 +784,9 @@ template <class P>
 void fwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* mlp, const float* means, int64_t n,
               float* dmu, float* dq, void* enc_out) {
     const int64_t nb = (n + kPts - 1) / kPts;
-    const unsigned grid = (unsigned)std::min<int64_t>((nb + kWaves - 1) / kWaves, 2048);
+    // four workgroups per CU are resident (LDS-bound) on 256 CUs: one round of
+    // workgroups, each looping over its share of the batches
+    const unsigned grid = (unsigned)std::min<int64_t>((nb + kWaves - 1) / kWaves, 1024);
     hipLaunchKernelGGL((k_ntc_fwd<P>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
                        (const typename P::S*)mlp, means, n, dmu, dq, (typename P::S*)enc_out);
 }

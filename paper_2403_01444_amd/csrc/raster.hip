@@ -587,9 +587,10 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                 const uint32_t idx = s_sb[lo] + (e - s_pre[lo]);
                 if (idx < cl.cap) {
                     const uint32_t id = vals[idx];
-                    s_w0[threadIdx.x] = rec[3 * (int64_t)id + 0];
-                    s_w1[threadIdx.x] = rec[3 * (int64_t)id + 1];
-                    s_w2[threadIdx.x] = blend_stage_w2(rec[3 * (int64_t)id + 2], tx0p, ty0p);
+                    const float4 r0 = rec[3 * (int64_t)id + 0], r1 = rec[3 * (int64_t)id + 1];
+                    s_w0[threadIdx.x] = r0;
+                    s_w1[threadIdx.x] = r1;
+                    s_w2[threadIdx.x] = blend_stage_w2<false>(r0, r1, rec[3 * (int64_t)id + 2], tx0p, ty0p);
                     const uint32_t slot = start + eb + e;
                     if (slot < cl.cap) cl.walked[slot] = id;
                 } else {
@@ -620,9 +621,10 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
             const uint32_t e = start + eb + threadIdx.x;
             if (e < end) {
                 const uint32_t id = vals[e];
-                s_w0[threadIdx.x] = rec[3 * (int64_t)id + 0];
-                s_w1[threadIdx.x] = rec[3 * (int64_t)id + 1];
-                s_w2[threadIdx.x] = blend_stage_w2(rec[3 * (int64_t)id + 2], tx0p, ty0p);
+                const float4 r0 = rec[3 * (int64_t)id + 0], r1 = rec[3 * (int64_t)id + 1];
+                s_w0[threadIdx.x] = r0;
+                s_w1[threadIdx.x] = r1;
+                s_w2[threadIdx.x] = blend_stage_w2<false>(r0, r1, rec[3 * (int64_t)id + 2], tx0p, ty0p);
             }
             __syncthreads();
             cnt_u = min((uint32_t)NT, total - eb);
@@ -738,6 +740,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
                                                                  const int* __restrict__ order) {
     constexpr int NT = kTile * kTile / R, NW = NT / 64;
     constexpr int KB = kBwdBatch < NT ? kBwdBatch : NT;   // entries staged per batch
+    static_assert(KB <= 128, "the wave entry masks hold two words");
     __shared__ float4 s_w0[KB];
     __shared__ float4 s_w1[KB];
     __shared__ float4 s_w2[KB];   // blend_stage_w2 form
@@ -789,29 +792,39 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, off));
     wlast = __builtin_amdgcn_readfirstlane(wlast);
+    const uint32_t wrows = wave_row_bits<R>(wv);
     const int my_slot = my_term < 5 ? my_term : my_term + 1;   // index in the nine-term layout
     for (int64_t jb = ((int64_t)(maxlast - 1) / KB) * KB; jb >= 0; jb -= KB) {
         const uint32_t e = (uint32_t)jb + threadIdx.x;
         if ((int)threadIdx.x < KB && e < maxlast) {
             const uint32_t id = vals[start + e];
+            const float4 r0 = rec[3 * (int64_t)id + 0], r1 = rec[3 * (int64_t)id + 1];
             s_id[threadIdx.x] = id;
-            s_w0[threadIdx.x] = rec[3 * (int64_t)id + 0];
-            s_w1[threadIdx.x] = rec[3 * (int64_t)id + 1];
-            s_w2[threadIdx.x] = blend_stage_w2(rec[3 * (int64_t)id + 2], tx0p, ty0p);
+            s_w0[threadIdx.x] = r0;
+            s_w1[threadIdx.x] = r1;
+            s_w2[threadIdx.x] = blend_stage_w2(r0, r1, rec[3 * (int64_t)id + 2], tx0p, ty0p);
         }
         __syncthreads();
         const int cnt = (int)min((int64_t)KB, (int64_t)maxlast - jb);
+        // the staged entries that can reach a pixel of this wave: box on its
+        // rows, before its last contributor (bit j % 64 of wm0 for j < 64,
+        // of wm1 above)
+        auto bword = [&](int q) -> uint64_t {
+            const int jq = 64 * q + lane;
+            return __builtin_amdgcn_ballot_w64(jq < cnt && (uint32_t)jb + (uint32_t)jq < wlast &&
+                                               box_meets_rows(s_w2[jq].w, wrows));
+        };
+        const uint64_t wm0 = bword(0), wm1 = KB > 64 ? bword(1) : 0ull;
         // one entry: this thread's R pixels walk back past entry j (their
         // transmittance and behind-colour state), and gr receives the eight
         // terms summed over them; returns whether any pixel of the wave
-        // takes the entry
+        // takes the entry (gr and gop are left unset when none does)
         auto entry = [&](int j, float gr[8], float& gop) -> bool {
             const uint32_t ej = (uint32_t)jb + (uint32_t)j;
             gop = 0.f;
-            if (ej >= wlast) {
-#pragma unroll
-                for (int c = 0; c < 8; c++) gr[c] = 0.f;
-                return false;
+            {
+                const uint64_t mw = (j >> 6) == 0 ? wm0 : wm1;
+                if (!((mw >> (j & 63)) & 1ull)) return false;
             }
             uint64_t act = 0ull;
             const float4 w0 = s_w0[j], w1 = s_w1[j], w2 = s_w2[j];
@@ -821,30 +834,35 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
             float adx2, bdx;
             blend_dx_terms(dx, w0, adx2, bdx);
             float power[R], dy[R];
-            bool ok[R], band[R];
+            // dec: the exponent the threshold tests read; inside the band it
+            // is replaced by the exact test's outcome (0: taken, -inf: not),
+            // so that the tests stay compares after the band's branch
+            float dec[R];
+            bool band[R];
             bool any_band = false;
 #pragma unroll
             for (int k = 0; k < R; k++) {
                 dy[k] = (float)(py0 + k) - w0.y;
                 power[k] = blend_power(adx2, bdx, dy[k], w1.x);
-                ok[k] = (ej < last[k]) & ((box & sel[k]) == sel[k]) & (power[k] <= 0.0f) & (power[k] >= w2.y);
-                band[k] = ok[k] & (power[k] < w2.z);
+                dec[k] = power[k];
+                band[k] = (ej < last[k]) & ((box & sel[k]) == sel[k]) & (power[k] <= 0.0f) &
+                          (power[k] >= w2.y) & (power[k] < w2.z);
                 any_band = any_band || band[k];
             }
             if (__any(any_band)) {
 #pragma unroll
                 for (int k = 0; k < R; k++)
-                    if (band[k]) ok[k] = blend_exact_test(power[k], w1.y);
+                    if (band[k]) dec[k] = blend_exact_test(power[k], w1.y) ? 0.0f : -INFINITY;
             }
-            // no pixel of the wave takes the entry: its state and sums stay
+            bool ok[R];
             bool any_ok = false;
 #pragma unroll
-            for (int k = 0; k < R; k++) any_ok = any_ok || ok[k];
-            if (!__any(any_ok)) {
-#pragma unroll
-                for (int c = 0; c < 8; c++) gr[c] = 0.f;
-                return false;
+            for (int k = 0; k < R; k++) {
+                ok[k] = (ej < last[k]) & ((box & sel[k]) == sel[k]) & (dec[k] <= 0.0f) & (dec[k] >= w2.y);
+                any_ok = any_ok || ok[k];
             }
+            // no pixel of the wave takes the entry: its state and sums stay
+            if (!__any(any_ok)) return false;
             // branch-free per-pixel body: selects keep the state of pixels
             // that this Gaussian does not reach
 #pragma unroll
@@ -882,7 +900,12 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
             const bool anya = entry(j, ga, opa);
             const bool anyc = entry(j - 1, gc, opc);
             float ra = 0.f, rc = 0.f;
-            if (anya || anyc) wave_reduce_scatter8x2(ga, gc, lane, ra, rc);
+            if (anya && anyc)
+                wave_reduce_scatter8x2(ga, gc, lane, ra, rc);
+            else if (anya)
+                ra = wave_reduce_scatter8(ga, lane);
+            else if (anyc)
+                rc = wave_reduce_scatter8(gc, lane);
             if ((lane & 7) == 0) {
                 s_g[wv][my_slot][j] = ra;
                 s_g[wv][my_slot][j - 1] = rc;

@@ -70,9 +70,14 @@ def adam_determined(m_prev, v_prev, step, g, lr, b1, b2, eps, delta, tol):
 
 def curve_bars(ref, members, margin=0.1):
     """Per logged iteration, the allowed distance from the oracle's PSNR:
-    `margin` plus the spread (largest minus smallest) of the oracle's curve
-    and its float32-perturbed copies there.  Where the loop is well
-    conditioned the spread is far below the margin; where rounding alone
-    moves it (Adam oscillating near the optimum) the bar widens with it."""
+    `margin` plus the largest spread (largest minus smallest) of the
+    oracle's curve and its float32-perturbed copies at that iteration or any
+    logged before it.  Where the loop is well conditioned the spread is far
+    below the margin; where rounding alone moves it (Adam oscillating near
+    the optimum, the loop fitting its few training views) the copies move
+    apart and do not come back together, and their spread at one logged
+    point is a sample of a distance that fluctuates from point to point (a
+    handful of copies can sit close together at one point and 0.2 dB apart
+    at the next), so the bar keeps the widest spread seen so far."""
     allc = np.vstack([np.asarray(ref, np.float64)] + [np.asarray(m, np.float64) for m in members])
-    return margin + allc.max(axis=0) - allc.min(axis=0)
+    return margin + np.maximum.accumulate(allc.max(axis=0) - allc.min(axis=0))

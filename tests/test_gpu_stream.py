@@ -61,7 +61,11 @@ def test_two_frames_track_the_oracle_stream():
     * Spawned counts equal up to the Gaussians whose oracle view-space
       average lies within 1e-3 of tau_grad (single precision may decide
       those either way); the additional set after quantity control within
-      that many plus 2%.
+      that many plus 2%.  Both also widened by the perturbed copies'
+      largest distance from the oracle's count: from the second frame on,
+      each stream starts from its own carried Gaussians, and rounding alone
+      moves the oracle's added count there by tens (1020-1101 against 1047
+      over eight copies of this configuration).
     * The carried (baked) Gaussians: means within 1e-5, quaternions within
       1e-4, SH within 1e-4 of the largest coefficient, each plus the
       perturbed copies' largest distance from the oracle.
@@ -120,8 +124,11 @@ def test_two_frames_track_the_oracle_stream():
         st2 = tr.last_stage2
         print(f"[stream] frame {f}: spawned {res.spawned} (oracle {fo['spawned']}), additional {st2.m} "
               f"(oracle {fo['added'].n}), {near} averages within 1e-3 of the threshold", flush=True)
-        assert abs(res.spawned - fo["spawned"]) <= near
-        assert abs(st2.m - fo["added"].n) <= near + 0.02 * fo["added"].n
+        sp_spread = max(abs(m["spawned"] - fo["spawned"]) for m in fm)
+        add_spread = max(abs(m["added"].n - fo["added"].n) for m in fm)
+        print(f"[stream] frame {f}: copies' spread spawned {sp_spread}, added {add_spread}", flush=True)
+        assert abs(res.spawned - fo["spawned"]) <= near + sp_spread
+        assert abs(st2.m - fo["added"].n) <= near + 0.02 * fo["added"].n + add_spread
         # the carried Gaussians
         b = tr.g
         shmax = np.abs(fo["baked"].sh).max()
