@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--render-reps", type=int, default=50)
+    ap.add_argument("--frame-reps", type=int, default=6,
+                    help="frames of 150 iterations timed for s/frame (the first is a warm-up; 0 = skip)")
     ap.add_argument("--batch-views", type=int, default=4,
                     help="views per step of the multi-view batch variant (1 = skip it)")
     ap.add_argument("--other-precisions", default="f32,bf16",
@@ -498,7 +500,7 @@ def main():
     # median of 5 frames after one warm-up frame
     frame_s = []
     g_in = gs3.GaussiansGPU.from_host(g)
-    for rep in range(6):
+    for rep in range(args.frame_reps):
         ctx.ntc_load(params_warm)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -512,7 +514,7 @@ def main():
         del st_f, g_f
     ctx.check_flags()
     ctx.ntc_load(params_warm)
-    s_per_frame = float(np.median(frame_s))
+    s_per_frame = float(np.median(frame_s)) if frame_s else None
 
     # render FPS on the held-out view: NTC query + transform + raster (and raster alone)
     hc = held[0]
@@ -663,7 +665,7 @@ def main():
         "config": {"workload": args.workload, "gaussians": g.n, "sh_degree": g.sh_degree,
                    "width": cams[0].width, "height": cams[0].height, "views": len(cams),
                    "ntc_precision": args.precision, "sort_mode": args.sort_mode},
-        "s_per_frame_150_iters": round(s_per_frame, 4),
+        "s_per_frame_150_iters": None if s_per_frame is None else round(s_per_frame, 4),
         "s_per_frame_runs": [round(x, 4) for x in frame_s],
         "s_per_frame_note": "per-frame setup (Morton order + NTC contribution lists) + 150 iterations, "
                             "median of 5 frames after 1 warm-up frame",
