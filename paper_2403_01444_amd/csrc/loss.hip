@@ -6,10 +6,13 @@
 // rows (a thread takes four adjacent outputs of a halo row, so it reads 14
 // inputs and forms their products once), then the columns (a thread takes
 // four outputs of one column from 14 row-filtered values).  Forward: five
-// filtered maps -> SSIM and its partial derivatives with respect to the
+// filtered maps (the two means, then the three second moments, through the
+// same LDS) -> SSIM and its partial derivatives with respect to the
 // filtered mean, E[x^2] and E[xy] at each pixel.  Backward: the adjoint of a
 // zero-padded correlation with a symmetric window is the same correlation,
-// so the three partial maps are filtered again and combined with x and y.
+// so the three partial maps are filtered again (one at a time) and combined
+// with x and y.  Keeping few row-filtered maps in LDS at once lets five
+// workgroups share a CU.
 #include <mutex>
 
 #include "../../include/gs3.h"
@@ -66,54 +69,54 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ x, const f
 }
 
 // Row filter: for the tasks t = threadIdx.x, threadIdx.x + 256, ... of the
-// 42 x 8 (halo row r, column quad q) tasks, outputs at columns 4 q .. 4 q + 3.
-// kProducts: the five SSIM moments of src[0] = x and src[1] = y; otherwise
-// the NM maps src[m] -> dst[m].
-template <int NM, bool kProducts>
+// 42 x 8 (halo row r, column quad q) tasks, outputs at columns 4 q .. 4 q + 3
+// of the NM maps src[m] -> dst[m].
+template <int NM>
 __device__ __forceinline__ void row_filter(const Win& win, const float (*src)[kHH][kHW + 1],
                                            float (*dst)[kHH][kTW + 1]) {
     for (int t = threadIdx.x; t < kHH * (kTW / kQ); t += 256) {
         const int r = t / (kTW / kQ), c0 = (t % (kTW / kQ)) * kQ;
-        if constexpr (kProducts) {
-            // the five SSIM moments of x (src) and y (src2)
-            float u[kIn], v[kIn];
 #pragma unroll
-            for (int i = 0; i < kIn; i++) {
-                u[i] = src[0][r][c0 + i];
-                v[i] = src[1][r][c0 + i];
-            }
+        for (int m = 0; m < NM; m++) {
+            float u[kIn];
+#pragma unroll
+            for (int i = 0; i < kIn; i++) u[i] = src[m][r][c0 + i];
 #pragma unroll
             for (int o = 0; o < kQ; o++) {
-                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+                float a = 0.f;
 #pragma unroll
-                for (int j = 0; j < 11; j++) {
-                    const float uj = u[o + j], vj = v[o + j], wj = win.g[j];
-                    a0 += wj * uj;
-                    a1 += wj * vj;
-                    a2 += wj * uj * uj;
-                    a3 += wj * vj * vj;
-                    a4 += wj * uj * vj;
-                }
-                dst[0][r][c0 + o] = a0;
-                dst[1][r][c0 + o] = a1;
-                dst[2][r][c0 + o] = a2;
-                dst[3][r][c0 + o] = a3;
-                dst[4][r][c0 + o] = a4;
+                for (int j = 0; j < 11; j++) a += win.g[j] * u[o + j];
+                dst[m][r][c0 + o] = a;
             }
-        } else {
+        }
+    }
+}
+
+// Row filter of the three second moments x^2, y^2, x y of src[0] = x and
+// src[1] = y (same task layout as row_filter).
+__device__ __forceinline__ void row_filter_second(const Win& win, const float (*src)[kHH][kHW + 1],
+                                                  float (*dst)[kHH][kTW + 1]) {
+    for (int t = threadIdx.x; t < kHH * (kTW / kQ); t += 256) {
+        const int r = t / (kTW / kQ), c0 = (t % (kTW / kQ)) * kQ;
+        float u[kIn], v[kIn];
 #pragma unroll
-            for (int m = 0; m < NM; m++) {
-                float u[kIn];
+        for (int i = 0; i < kIn; i++) {
+            u[i] = src[0][r][c0 + i];
+            v[i] = src[1][r][c0 + i];
+        }
 #pragma unroll
-                for (int i = 0; i < kIn; i++) u[i] = src[m][r][c0 + i];
+        for (int o = 0; o < kQ; o++) {
+            float a2 = 0.f, a3 = 0.f, a4 = 0.f;
 #pragma unroll
-                for (int o = 0; o < kQ; o++) {
-                    float a = 0.f;
-#pragma unroll
-                    for (int j = 0; j < 11; j++) a += win.g[j] * u[o + j];
-                    dst[m][r][c0 + o] = a;
-                }
+            for (int j = 0; j < 11; j++) {
+                const float uj = u[o + j], vj = v[o + j], wj = win.g[j];
+                a2 += wj * uj * uj;
+                a3 += wj * vj * vj;
+                a4 += wj * uj * vj;
             }
+            dst[0][r][c0 + o] = a2;
+            dst[1][r][c0 + o] = a3;
+            dst[2][r][c0 + o] = a4;
         }
     }
 }
@@ -135,7 +138,7 @@ __device__ __forceinline__ void col_filter(const Win& win, const float (*src)[kT
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, const float* __restrict__ y, int H,
                                                   int W, Win win, float* __restrict__ maps, double* __restrict__ bsum) {
     __shared__ float s_img[2][kHH][kHW + 1];   // x, y halo tiles
-    __shared__ float sh[5][kHH][kTW + 1];
+    __shared__ float sh[3][kHH][kTW + 1];      // row-filtered maps, three at a time
     __shared__ float s_w[2][4];
     const int ch = blockIdx.z;
     const int bx = blockIdx.x, by = blockIdx.y;
@@ -150,15 +153,21 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, c
         s_img[1][r][c] = in ? yc[(int64_t)gy * W + gx] : 0.f;
     }
     __syncthreads();
-    row_filter<5, true>(win, s_img, sh);
-    __syncthreads();
+    // the means first, then the second moments through the same LDS maps
+    // (their products formed in the second row pass): three maps of LDS
+    // instead of five leave room for five workgroups per CU
     const int c = threadIdx.x % kTW, g = threadIdx.x / kTW;
     float mx[kQ], my[kQ], exx[kQ], eyy[kQ], exy[kQ];
+    row_filter<2>(win, s_img, sh);
+    __syncthreads();
     col_filter(win, sh[0], g, c, mx);
     col_filter(win, sh[1], g, c, my);
-    col_filter(win, sh[2], g, c, exx);
-    col_filter(win, sh[3], g, c, eyy);
-    col_filter(win, sh[4], g, c, exy);
+    __syncthreads();
+    row_filter_second(win, s_img, sh);
+    __syncthreads();
+    col_filter(win, sh[0], g, c, exx);
+    col_filter(win, sh[1], g, c, eyy);
+    col_filter(win, sh[2], g, c, exy);
     const int gx = bx * kTW + c;
     const int64_t N = 3 * P;
     float s_sum = 0.f, l1 = 0.f;
@@ -206,7 +215,7 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, c
                                                   int W, Win win, float lam, const float* __restrict__ maps,
                                                   float* __restrict__ d) {
     __shared__ float sm[3][kHH][kHW + 1];
-    __shared__ float sh[3][kHH][kTW + 1];
+    __shared__ float sh[1][kHH][kTW + 1];   // one row-filtered map at a time
     const int ch = blockIdx.z;
     const int bx = blockIdx.x, by = blockIdx.y;
     const int64_t P = (int64_t)H * W, N = 3 * P;
@@ -219,14 +228,16 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, c
         sm[1][r][c] = in ? maps[N + p] : 0.f;
         sm[2][r][c] = in ? maps[2 * N + p] : 0.f;
     }
-    __syncthreads();
-    row_filter<3, false>(win, sm, sh);
-    __syncthreads();
     const int c = threadIdx.x % kTW, g = threadIdx.x / kTW;
     float fm[kQ], fe[kQ], ff[kQ];
-    col_filter(win, sh[0], g, c, fm);
-    col_filter(win, sh[1], g, c, fe);
-    col_filter(win, sh[2], g, c, ff);
+    float* const fout[3] = {fm, fe, ff};
+#pragma unroll
+    for (int m = 0; m < 3; m++) {
+        __syncthreads();
+        row_filter<1>(win, sm + m, sh);
+        __syncthreads();
+        col_filter(win, sh[0], g, c, fout[m]);
+    }
     const int gx = bx * kTW + c;
     const float invN = 1.0f / (float)N;
 #pragma unroll
