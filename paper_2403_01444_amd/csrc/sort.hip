@@ -2,7 +2,9 @@
 //
 // Scan: three kernels (per-block reduce, single-block scan of the block
 // sums, per-block rescan with the block prefix).  Each block owns 2048
-// consecutive items (256 threads x 8).
+// consecutive items (256 threads x 8).  Up to eight blocks' worth of items
+// (the per-tile totals of a view, for instance) take one kernel: a single
+// block walks them 2048 at a time with a running carry.
 //
 // Radix sort: 8-bit digits, one histogram kernel and one scatter kernel per
 // pass.  A block owns 256 x I consecutive items (I = 8, or 4 for inputs
@@ -128,6 +130,43 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const Tin* __restrict__ 
     }
 }
 
+// Inputs of at most kSmallScan items: one block walks them kTileItems at a
+// time with a running carry (one launch instead of three).
+constexpr int64_t kSmallScan = 8 * kTileItems;
+
+template <typename Tout>
+__global__ __launch_bounds__(kThreads) void k_scan_single(const uint32_t* __restrict__ in, int64_t n,
+                                                          Tout* __restrict__ out, uint64_t* __restrict__ total) {
+    __shared__ uint64_t s_w[kThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t carry = 0;
+    for (int64_t b0 = 0; b0 < n; b0 += kTileItems) {
+        const int64_t base = b0 + (int64_t)threadIdx.x * kItems;
+        uint32_t v[kItems];
+        load8(in, base, n, v);
+        uint64_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; k++) s += (uint64_t)v[k];
+        const uint64_t x = wave_incl_scan(s, lane);
+        if (lane == 63) s_w[w] = x;
+        __syncthreads();
+        uint64_t pre = carry, tot = 0;
+        for (int k = 0; k < kThreads / 64; k++) {
+            if (k < w) pre += s_w[k];
+            tot += s_w[k];
+        }
+        uint64_t run = pre + x - s;
+#pragma unroll
+        for (int k = 0; k < kItems; k++) {
+            if (base + k < n) out[base + k] = (Tout)run;
+            run += v[k];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
 template <typename Tout>
 void scan_impl(const Launch& L, const uint32_t* in, int64_t n, Tout* out, uint64_t* total, uint64_t* tmp) {
     int64_t nb = (n + kTileItems - 1) / kTileItems;
@@ -136,6 +175,11 @@ void scan_impl(const Launch& L, const uint32_t* in, int64_t n, Tout* out, uint64
         return;
     }
     if (L.prof) L.prof->begin("scan", L.st);
+    if (n <= kSmallScan) {
+        hipLaunchKernelGGL((k_scan_single<Tout>), dim3(1), dim3(kThreads), 0, L.st, in, n, out, total);
+        if (L.prof) L.prof->end(L.st);
+        return;
+    }
     hipLaunchKernelGGL((k_scan_reduce<uint32_t>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, in, n, tmp);
     hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kThreads), 0, L.st, tmp, nb, total);
     hipLaunchKernelGGL((k_scan_down<uint32_t, Tout>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, in, n, tmp, out);
