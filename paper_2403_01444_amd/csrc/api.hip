@@ -297,13 +297,14 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
         }
         c->n_table_floats = off * 2;
         c->n_params = c->n_table_floats + ntc_mlp_params();
-        // one NTC-backward workgroup per CU (its registers allow one per CU);
-        // each loops over its share of the point batches in a single round
+        // up to two NTC-backward workgroups per CU (their LDS allows two in
+        // half precision, one in float32); each loops over its share of the
+        // point batches in a single round
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
-        c->max_parts = cus;
+        c->max_parts = 2 * cus;
         ok = c->alloc(&c->p, c->n_params) && c->alloc(&c->g, c->n_params) && c->alloc(&c->m, c->n_params) &&
              c->alloc(&c->v, c->n_params) && c->alloc((float**)&c->work, c->n_params) &&
              c->alloc(&c->g_part, (int64_t)c->max_parts * ntc_mlp_params()) && c->alloc(&c->warm_bsum, (N + 255) / 256);

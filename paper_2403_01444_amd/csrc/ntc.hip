@@ -7,11 +7,13 @@
 // the 16 x 16 (point, level) pairs of a batch.  Activations go through LDS in
 // [point][feature] layout; every layer is a 16 x 16 MFMA tile product
 // (v_mfma_f32_16x16x16 f16 / bf16, or 16x16x4 f32), weights staged once per
-// workgroup in LDS.  The backward pass recomputes the forward, propagates
-// the output gradient through the three layers, accumulates the weight
-// gradients with MFMA (contraction over the batch's 16 points) in FP32
-// registers, and scatter-adds the encoding gradient into the FP32 table
-// gradient with global atomics.
+// workgroup in LDS.  The backward pass recomputes the forward and
+// propagates the output gradient through the three layers, each wave on its
+// own batch; then the four waves accumulate the weight gradients of the
+// four batches with MFMA (contraction over each batch's 16 points) in FP32
+// registers, each wave a quarter of the weight tiles; the encoding gradient
+// goes to the per-entry gather of the table gradient, or is scatter-added
+// into it with global atomics.
 //
 // Half-precision backward: each activation-gradient stage is rescaled by a
 // power of two so that its largest magnitude in the batch sits near 2^13
@@ -322,6 +324,16 @@ __device__ __forceinline__ int clamp_exp(int k) { return k < -126 ? -126 : (k > 
 // kCSR: write the encoding gradient (n x 32 floats) to `denc` for the
 // per-entry gather of the prepared contribution lists; otherwise scatter-add
 // it into the table gradient with atomics.
+//
+// Each iteration takes four batches, one per wave.  Phase A (each wave on its
+// own batch): the encoding, the forward layers, the output gradient and the
+// activation gradients of the three layers, all kept in the wave's LDS
+// arrays (activations and gradients side by side), and the encoding
+// gradient.  Phase B (after a workgroup barrier): the weight gradients of
+// all four batches, split between the waves by output rows (wave w: the 16
+// rows 16 w.. of dW1 and dW2 and the 16 columns 16 w.. of dW3), so a wave
+// holds 7 accumulator tiles instead of 28 and the register file leaves room
+// for more than one wave per SIMD.
 template <class P, bool kCSR>
 __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S* __restrict__ table,
                                                  const typename P::S* __restrict__ mlp, const float* __restrict__ means,
@@ -331,16 +343,18 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
                                                  const typename P::S* __restrict__ enc_in) {
     using S = typename P::S;
     constexpr int kWElems = 64 * LD32 + 64 * LD64 + 32 * LD64 + 64 * LD64 + 64 * LD16;
-    constexpr int kWBytes = (int)sizeof(S) * kWElems > kMlpParams * 4 ? (int)sizeof(S) * kWElems : kMlpParams * 4;
-    __shared__ __align__(16) unsigned char sWraw[kWBytes];
-    S* sW1 = reinterpret_cast<S*>(sWraw);
+    __shared__ __align__(16) S sWraw[kWElems];
+    S* sW1 = sWraw;
     S* sW2 = sW1 + 64 * LD32;
     S* sW1t = sW2 + 64 * LD64;
     S* sW2t = sW1t + 32 * LD64;
     S* sW3t = sW2t + 64 * LD64;
+    // per wave: encoding, activations, their gradients, output gradient
     __shared__ S sX[kWaves][kPts * LD32], sH1[kWaves][kPts * LD64], sH2[kWaves][kPts * LD64];
+    __shared__ S sD1[kWaves][kPts * LD64], sD2[kWaves][kPts * LD64];
     __shared__ S sO[kWaves][kPts * LD16];
-    __shared__ float sE[kWaves][kPts * 33];
+    __shared__ float sE[kCSR ? 1 : kWaves][kPts * 33];
+    __shared__ int sK[kWaves][3];   // each batch's scale exponents k0, k1, k2
     load_weights<P>(mlp, sW1, sW2, nullptr, sW1t, sW2t, sW3t);
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -348,14 +362,16 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
     S* X = sX[w];
     S* H1 = sH1[w];
     S* H2 = sH2[w];
+    S* D1 = sD1[w];
+    S* D2 = sD2[w];
     S* O = sO[w];
-    float* E = sE[w];
-    f4v gW1[4][2], gW2[4][4], gW3[4];
-    for (int a = 0; a < 4; a++) {
-        for (int b = 0; b < 2; b++) gW1[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
-        for (int b = 0; b < 4; b++) gW2[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
-        gW3[a] = f4v{0.f, 0.f, 0.f, 0.f};
-    }
+    float* E = sE[kCSR ? 0 : w];
+    // this wave's weight-gradient tiles: dW1 rows 16 w.. (2 column tiles),
+    // dW2 rows 16 w.. (4 column tiles), dW3 columns 16 w..
+    f4v gW1[2], gW2[4], gW3;
+    for (int a = 0; a < 2; a++) gW1[a] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int a = 0; a < 4; a++) gW2[a] = f4v{0.f, 0.f, 0.f, 0.f};
+    gW3 = f4v{0.f, 0.f, 0.f, 0.f};
     // the level slices this lane writes in the level-major encoding gradient:
     // levels 2 g and 8 + 2 g (and the level after each)
     float2* dlev[2] = {nullptr, nullptr};
@@ -365,15 +381,15 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
     }
     const int64_t nb = (n + kPts - 1) / kPts;
     for (int64_t b0 = (int64_t)blockIdx.x * kWaves; b0 < nb; b0 += (int64_t)gridDim.x * kWaves) {
+        // ---------------- phase A: this wave's batch ----------------
         const int64_t pt = (b0 + w) * kPts + p;
-        const bool valid = pt < n;
+        const bool valid = pt < n;   // false for every lane of a wave past the last batch
         float x[3] = {0.f, 0.f, 0.f};
         bool in = false;
         if (valid) {
             const float mu[3] = {means[3 * pt], means[3 * pt + 1], means[3 * pt + 2]};
             in = ntc_normalise(nd, mu, x);
         }
-        wave_sync();
         // 1. encoding: the forward's, when it kept it, else recomputed
         if (enc_in && valid) {
             enc_from_cache<P>(X, p, g, enc_in, pt);
@@ -415,21 +431,7 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
             for (int r = 0; r < 4; r++) H2[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(fmaxf(a[r], 0.f));
         }
         wave_sync();
-        // 3. dW3[o][m] += sum_p dO[p][o] H2[p][m]
-        {
-            const float inv = ldexpf(1.0f, -k0);
-#pragma unroll
-            for (int nt = 0; nt < 4; nt++) {
-                f4v t = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int ks = 0; ks < kPts / P::KSTEP; ks++) {
-                    const int k0 = ks * P::KSTEP + P::KPL * g;
-                    t = P::mfma(frag_k_strided<P>(O, LD16, col, k0), frag_k_strided<P>(H2, LD64, nt * 16 + col, k0), t);
-                }
-                gW3[nt] += t * inv;
-            }
-        }
-        // 4. dH2 = (W3^T dO) * [H2 > 0], written over H2 (same positions)
+        // 3. dH2 = (W3^T dO) * [H2 > 0]
         f4v d2[4];
         float m2 = 0.f;
 #pragma unroll
@@ -443,36 +445,18 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
         }
         int k1 = k0;
         if (P::kScaled) k1 = clamp_exp(k0 + pow2_exp(wave_max(m2)));
-        wave_sync();   // all reads of H2 (step 3) done
         {
             const float f = ldexpf(1.0f, k1 - k0);
             for (int mt = 0; mt < 4; mt++)
-                for (int r = 0; r < 4; r++) H2[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(d2[mt][r] * f);
+                for (int r = 0; r < 4; r++) D2[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(d2[mt][r] * f);
         }
         wave_sync();
-        // 5. dW2[m][k] += sum_p dH2[p][m] H1[p][k]
-        {
-            const float inv = ldexpf(1.0f, -k1);
-#pragma unroll
-            for (int mt = 0; mt < 4; mt++)
-#pragma unroll
-                for (int nt = 0; nt < 4; nt++) {
-                    f4v t = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int ks = 0; ks < kPts / P::KSTEP; ks++) {
-                        const int k0 = ks * P::KSTEP + P::KPL * g;
-                        t = P::mfma(frag_k_strided<P>(H2, LD64, mt * 16 + col, k0),
-                                    frag_k_strided<P>(H1, LD64, nt * 16 + col, k0), t);
-                    }
-                    gW2[mt][nt] += t * inv;
-                }
-        }
-        // 6. dH1 = (W2^T dH2) * [H1 > 0], written over H1
+        // 4. dH1 = (W2^T dH2) * [H1 > 0]
         f4v d1[4];
         float m1 = 0.f;
 #pragma unroll
         for (int mt = 0; mt < 4; mt++) {
-            d1[mt] = layer_tile<P, 64>(sW2t, LD64, mt * 16, H2, LD64, lane);
+            d1[mt] = layer_tile<P, 64>(sW2t, LD64, mt * 16, D2, LD64, lane);
             for (int r = 0; r < 4; r++) {
                 const bool on = P::tof(H1[p * LD64 + mt * 16 + 4 * g + r]) > 0.f;
                 d1[mt][r] = on ? d1[mt][r] : 0.f;
@@ -481,32 +465,23 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
         }
         int k2 = k1;
         if (P::kScaled) k2 = clamp_exp(k1 + pow2_exp(wave_max(m1)));
-        wave_sync();   // all reads of H1 (step 5) done
         {
             const float f = ldexpf(1.0f, k2 - k1);
             for (int mt = 0; mt < 4; mt++)
-                for (int r = 0; r < 4; r++) H1[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(d1[mt][r] * f);
+                for (int r = 0; r < 4; r++) D1[p * LD64 + mt * 16 + 4 * g + r] = P::cvt(d1[mt][r] * f);
+        }
+        if (lane == 0) {
+            sK[w][0] = k0;
+            sK[w][1] = k1;
+            sK[w][2] = k2;
         }
         wave_sync();
-        // 7. dW1[m][k] += sum_p dH1[p][m] X[p][k];  dX = W1^T dH1
+        // 5. dX = W1^T dH1: the encoding gradient
         {
             const float inv = ldexpf(1.0f, -k2);
 #pragma unroll
-            for (int mt = 0; mt < 4; mt++)
-#pragma unroll
-                for (int nt = 0; nt < 2; nt++) {
-                    f4v t = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int ks = 0; ks < kPts / P::KSTEP; ks++) {
-                        const int k0 = ks * P::KSTEP + P::KPL * g;
-                        t = P::mfma(frag_k_strided<P>(H1, LD64, mt * 16 + col, k0),
-                                    frag_k_strided<P>(X, LD32, nt * 16 + col, k0), t);
-                    }
-                    gW1[mt][nt] += t * inv;
-                }
-#pragma unroll
             for (int mt = 0; mt < 2; mt++) {
-                const f4v e = layer_tile<P, 64>(sW1t, LD64, mt * 16, H1, LD64, lane);
+                const f4v e = layer_tile<P, 64>(sW1t, LD64, mt * 16, D1, LD64, lane);
                 if (kCSR) {
                     // level-major [level][point][2]: one level's slice (8 n bytes)
                     // stays cache-resident while the gather walks that level
@@ -520,43 +495,79 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
                 }
             }
         }
-        wave_sync();
-        // 8. scatter-add the encoding gradient into the table gradient
-        if (!kCSR && in) {
+        if (!kCSR) {
+            wave_sync();
+            // 6. scatter-add the encoding gradient into the table gradient
+            if (in) {
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int lv = 4 * g + j;
-                uint32_t ent[8];
-                float wt[8];
-                ntc_corners(nd, lv, x, ent, wt);
-                const float e0 = E[p * 33 + 2 * lv], e1 = E[p * 33 + 2 * lv + 1];
+                for (int j = 0; j < 4; j++) {
+                    const int lv = 4 * g + j;
+                    uint32_t ent[8];
+                    float wt[8];
+                    ntc_corners(nd, lv, x, ent, wt);
+                    const float e0 = E[p * 33 + 2 * lv], e1 = E[p * 33 + 2 * lv + 1];
 #pragma unroll
-                for (int c = 0; c < 8; c++) {
-                    atomicAdd(g_table + 2 * (int64_t)ent[c], wt[c] * e0);
-                    atomicAdd(g_table + 2 * (int64_t)ent[c] + 1, wt[c] * e1);
+                    for (int c = 0; c < 8; c++) {
+                        atomicAdd(g_table + 2 * (int64_t)ent[c], wt[c] * e0);
+                        atomicAdd(g_table + 2 * (int64_t)ent[c] + 1, wt[c] * e1);
+                    }
                 }
             }
         }
+        __syncthreads();
+        // ---------------- phase B: weight gradients of the four batches ----------------
+#pragma unroll
+        for (int b = 0; b < kWaves; b++) {
+            const float inv0 = ldexpf(1.0f, -sK[b][0]);
+            const float inv1 = ldexpf(1.0f, -sK[b][1]);
+            const float inv2 = ldexpf(1.0f, -sK[b][2]);
+            // dW3[o][m] += sum_p dO[p][o] H2[p][m], columns m = 16 w..
+            {
+                f4v t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < kPts / P::KSTEP; ks++) {
+                    const int kk = ks * P::KSTEP + P::KPL * g;
+                    t = P::mfma(frag_k_strided<P>(sO[b], LD16, col, kk),
+                                frag_k_strided<P>(sH2[b], LD64, w * 16 + col, kk), t);
+                }
+                gW3 += t * inv0;
+            }
+            // dW2[m][k] += sum_p dH2[p][m] H1[p][k], rows m = 16 w..
+#pragma unroll
+            for (int nt = 0; nt < 4; nt++) {
+                f4v t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < kPts / P::KSTEP; ks++) {
+                    const int kk = ks * P::KSTEP + P::KPL * g;
+                    t = P::mfma(frag_k_strided<P>(sD2[b], LD64, w * 16 + col, kk),
+                                frag_k_strided<P>(sH1[b], LD64, nt * 16 + col, kk), t);
+                }
+                gW2[nt] += t * inv1;
+            }
+            // dW1[m][k] += sum_p dH1[p][m] X[p][k], rows m = 16 w..
+#pragma unroll
+            for (int nt = 0; nt < 2; nt++) {
+                f4v t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < kPts / P::KSTEP; ks++) {
+                    const int kk = ks * P::KSTEP + P::KPL * g;
+                    t = P::mfma(frag_k_strided<P>(sD1[b], LD64, w * 16 + col, kk),
+                                frag_k_strided<P>(sX[b], LD32, nt * 16 + col, kk), t);
+                }
+                gW1[nt] += t * inv2;
+            }
+        }
+        __syncthreads();   // phase B's reads done before the next batches are written
     }
-    // weight-gradient partials of this workgroup: the four waves add their
-    // tiles into LDS (reusing the weight area), then one coalesced row out.
-    __syncthreads();
-    float* red = reinterpret_cast<float*>(sWraw);
-    for (int k = threadIdx.x; k < kMlpParams; k += blockDim.x) red[k] = 0.f;
-    __syncthreads();
-    for (int mt = 0; mt < 4; mt++)
-        for (int nt = 0; nt < 2; nt++)
-            for (int r = 0; r < 4; r++) atomicAdd(red + (mt * 16 + 4 * g + r) * 32 + nt * 16 + col, gW1[mt][nt][r]);
-    for (int mt = 0; mt < 4; mt++)
-        for (int nt = 0; nt < 4; nt++)
-            for (int r = 0; r < 4; r++)
-                atomicAdd(red + 64 * 32 + (mt * 16 + 4 * g + r) * 64 + nt * 16 + col, gW2[mt][nt][r]);
-    for (int nt = 0; nt < 4; nt++)
-        for (int r = 0; r < 4; r++)
-            if (4 * g + r < 7) atomicAdd(red + 64 * 32 + 64 * 64 + (4 * g + r) * 64 + nt * 16 + col, gW3[nt][r]);
-    __syncthreads();
+    // weight-gradient partials of this workgroup: every wave writes its own
+    // tiles (they are disjoint and cover the MLP's parameters once)
     float* out = g_part + (int64_t)blockIdx.x * kMlpParams;
-    for (int k = threadIdx.x; k < kMlpParams; k += blockDim.x) out[k] = red[k];
+    for (int nt = 0; nt < 2; nt++)
+        for (int r = 0; r < 4; r++) out[(w * 16 + 4 * g + r) * 32 + nt * 16 + col] = gW1[nt][r];
+    for (int nt = 0; nt < 4; nt++)
+        for (int r = 0; r < 4; r++) out[64 * 32 + (w * 16 + 4 * g + r) * 64 + nt * 16 + col] = gW2[nt][r];
+    for (int r = 0; r < 4; r++)
+        if (4 * g + r < 7) out[64 * 32 + 64 * 64 + (4 * g + r) * 64 + w * 16 + col] = gW3[r];
 }
 
 // ---------------------------------------------------------------------------
@@ -796,7 +807,10 @@ void bwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* 
               const float* d_dmu, const float* d_dq, float* g_table, float* g_mlp, float* g_part, int max_parts,
               const NtcCsr* csr, const void* enc_in) {
     const int64_t nb = (n + kPts - 1) / kPts;
-    const unsigned grid = (unsigned)std::min<int64_t>((nb + kWaves - 1) / kWaves, max_parts);
+    // max_parts is two per CU: the half-precision kernels fit two workgroups
+    // on a CU, the float32 one (twice the LDS) one
+    const int parts = sizeof(typename P::S) == 4 ? max_parts / 2 : max_parts;
+    const unsigned grid = (unsigned)std::min<int64_t>((nb + kWaves - 1) / kWaves, parts);
     if (csr) {
         hipLaunchKernelGGL((k_ntc_bwd<P, true>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
                            (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, csr->denc,
