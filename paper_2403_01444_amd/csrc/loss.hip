@@ -56,6 +56,46 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* out) {
     }
 }
 
+// The loss from the per-block (L1, SSIM) sums: one block of 256 threads, a
+// fixed summation order.
+__device__ __forceinline__ void finalize_sums(const double* __restrict__ bsum, int64_t nblk, int64_t N, float lam,
+                                              float* __restrict__ loss, int* __restrict__ nonfinite) {
+    __shared__ double s[2][4];
+    // four independent partial sums per thread (fixed order), then combined
+    double a4[4] = {0.0, 0.0, 0.0, 0.0}, b4[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t k = threadIdx.x;
+    for (; k + 768 < nblk; k += 1024) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const double2 v = reinterpret_cast<const double2*>(bsum)[k + 256 * u];
+            a4[u] += v.x;
+            b4[u] += v.y;
+        }
+    }
+    for (; k < nblk; k += 256) {
+        a4[0] += bsum[2 * k];
+        b4[0] += bsum[2 * k + 1];
+    }
+    double a = (a4[0] + a4[1]) + (a4[2] + a4[3]), b = (b4[0] + b4[1]) + (b4[2] + b4[3]);
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s[0][w] = a;
+        s[1][w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double l1 = (s[0][0] + s[0][1] + s[0][2] + s[0][3]) / (double)N;
+        const double ss = (s[1][0] + s[1][1] + s[1][2] + s[1][3]) / (double)N;
+        const double L = lam == 0.f ? l1 : (1.0 - lam) * l1 + lam * (1.0 - ss);
+        loss[0] = (float)L;
+        if (!isfinite(L)) atomicOr(nonfinite, 1);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ x, const float* __restrict__ y, int64_t N,
                                             float scale, float* __restrict__ d, double* __restrict__ bsum) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -213,7 +253,8 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, c
 
 __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, const float* __restrict__ y, int H,
                                                   int W, Win win, float lam, const float* __restrict__ maps,
-                                                  float* __restrict__ d) {
+                                                  float* __restrict__ d, const double* __restrict__ bsum,
+                                                  int64_t nblk, float* __restrict__ loss, int* __restrict__ nonfinite) {
     __shared__ float sm[3][kHH][kHW + 1];
     __shared__ float sh[1][kHH][kTW + 1];   // one row-filtered map at a time
     const int ch = blockIdx.z;
@@ -249,44 +290,15 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, c
             d[p] = (1.f - lam) * sgnf(xv - yv) * invN - lam * invN * (fm[o] + 2.f * xv * fe[o] + yv * ff[o]);
         }
     }
+    // the loss value: the forward wrote every block's sums before this
+    // launch, so one block adds them up here instead of a launch of its own
+    if (bx == 0 && by == 0 && ch == 0) finalize_sums(bsum, nblk, N, lam, loss, nonfinite);
 }
+
 
 __global__ __launch_bounds__(256) void k_loss_finalize(const double* __restrict__ bsum, int64_t nblk, int64_t N,
                                                        float lam, float* __restrict__ loss, int* __restrict__ nonfinite) {
-    __shared__ double s[2][4];
-    // four independent partial sums per thread (fixed order), then combined
-    double a4[4] = {0.0, 0.0, 0.0, 0.0}, b4[4] = {0.0, 0.0, 0.0, 0.0};
-    int64_t k = threadIdx.x;
-    for (; k + 768 < nblk; k += 1024) {
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const double2 v = reinterpret_cast<const double2*>(bsum)[k + 256 * u];
-            a4[u] += v.x;
-            b4[u] += v.y;
-        }
-    }
-    for (; k < nblk; k += 256) {
-        a4[0] += bsum[2 * k];
-        b4[0] += bsum[2 * k + 1];
-    }
-    double a = (a4[0] + a4[1]) + (a4[2] + a4[3]), b = (b4[0] + b4[1]) + (b4[2] + b4[3]);
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off, 64);
-        b += __shfl_xor(b, off, 64);
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        s[0][w] = a;
-        s[1][w] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double l1 = (s[0][0] + s[0][1] + s[0][2] + s[0][3]) / (double)N;
-        const double ss = (s[1][0] + s[1][1] + s[1][2] + s[1][3]) / (double)N;
-        const double L = lam == 0.f ? l1 : (1.0 - lam) * l1 + lam * (1.0 - ss);
-        loss[0] = (float)L;
-        if (!isfinite(L)) atomicOr(nonfinite, 1);
-    }
+    finalize_sums(bsum, nblk, N, lam, loss, nonfinite);
 }
 
 Win make_window() {
@@ -323,10 +335,9 @@ void loss_forward_backward(const Launch& L, const float* x, const float* y, int 
         const Win win = make_window();
         dim3 grid((W + kTW - 1) / kTW, (H + kTH - 1) / kTH, 3);
         hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, L.st, x, y, H, W, win, w.partial_maps, w.block_sums);
-        hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, L.st, x, y, H, W, win, lambda, w.partial_maps, d_image);
         const int64_t nblk = (int64_t)grid.x * grid.y * grid.z;
-        hipLaunchKernelGGL(k_loss_finalize, dim3(1), dim3(256), 0, L.st, w.block_sums, nblk, N, lambda, loss_dev,
-                           nonfinite);
+        hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, L.st, x, y, H, W, win, lambda, w.partial_maps, d_image,
+                           (const double*)w.block_sums, nblk, loss_dev, nonfinite);
     }
     if (L.prof) L.prof->end(L.st);
 }
