@@ -285,7 +285,9 @@ def raster_bytes(n, K, P, S):
 
 
 def algorithmic_work(name, st):
-    """(bound, amount per launch, unit) of the work the method itself needs."""
+    """(bound, amount per step, unit) of the work the method itself needs
+    (a kernel launched twice per step, like the two phases of the binning
+    scatter and the forward blend, shares it between its launches)."""
     n, P, S = st["n"], st["pixels"], st["sh_floats"]
     if name in ("blend_fwd", "blend_bwd"):
         return "alu", 256 * st["walked"] * OPS_PER_EVALUATED_PAIR, "flop"
@@ -582,7 +584,7 @@ def main():
         w = algorithmic_work(dom, st)
         if w is not None:
             bound, amount, unit = w
-            sec = dom_ms * 1e-3
+            sec = dom_ms * kernels[dom]["launches_per_step"] * 1e-3
             if bound == "alu":
                 ach, peak, u = amount / sec / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
             else:
@@ -610,7 +612,7 @@ def main():
         if w is None:
             continue
         bound, amount, unit = w
-        sec = v["ms_per_launch"] * 1e-3
+        sec = v["ms_per_launch"] * v["launches_per_step"] * 1e-3
         all_roof[k] = (round(amount / sec / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4) if bound == "alu"
                        else round(amount / sec / 1e9 / HBM_PEAK_GBS, 4))
 
