@@ -631,14 +631,44 @@ __global__ __launch_bounds__(256) void k_csr_weights(NtcDev nd, const float* __r
 // read 16 at a time (coalesced, one 8-byte load each), each lane gathers its
 // point's encoding gradient, and the group sums with DPP (pairs, quads,
 // half-row and row mirror): fixed order.
+//
+// Every level takes the same number of contributions (8 per point) and reads
+// only its own slice of the encoding gradient (n x 8 bytes).  Workgroups are
+// handed to the 8 XCDs in turn, so workgroup b runs on XCD b mod 8; the grid
+// gives XCD x the entries of levels x and 15 - x (a coarse level with few,
+// long rows and a fine one with many short rows), one level after the other.
+// Each XCD then fetches two slices of the encoding gradient into its own L2
+// instead of all sixteen.  The placement is a performance choice only: the
+// result does not depend on where a workgroup runs.
 constexpr int kGatherLanes = 16;
-__global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ rows, const uint2* __restrict__ pw,
-                                                    const float* __restrict__ denc, int64_t n, int64_t entries,
-                                                    float* __restrict__ g_table) {
-    const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kGatherLanes;
+constexpr int kGatherEntries = 256 / kGatherLanes;   // entries per workgroup
+constexpr int kXcds = 8;
+
+struct GatherLevels {
+    int64_t begin[16];   // first entry of each level
+    int64_t end[16];     // one past its last entry
+};
+
+static int64_t gather_blocks(const GatherLevels& gl, int lv) {
+    return (gl.end[lv] - gl.begin[lv] + kGatherEntries - 1) / kGatherEntries;
+}
+
+__global__ __launch_bounds__(256) void k_csr_gather(GatherLevels gl, const uint2* __restrict__ rows,
+                                                    const uint2* __restrict__ pw, const float* __restrict__ denc,
+                                                    int64_t n, float* __restrict__ g_table) {
+    const int x = (int)(blockIdx.x % kXcds);
+    int64_t j = blockIdx.x / kXcds;   // this workgroup's place among its XCD's
+    int lv = x;
+    const int64_t na = (gl.end[lv] - gl.begin[lv] + kGatherEntries - 1) / kGatherEntries;
+    if (j >= na) {
+        j -= na;
+        lv = 15 - x;
+    }
+    const int64_t e = gl.begin[lv] + j * kGatherEntries + threadIdx.x / kGatherLanes;
+    const bool valid = e < gl.end[lv];
     const int sub = threadIdx.x % kGatherLanes;
     uint2 r = make_uint2(0u, 0u);
-    if (e < entries) r = rows[e];
+    if (valid) r = rows[e];
     float a0 = 0.f, a1 = 0.f;
     auto enc = [&](uint32_t c) {
         return *reinterpret_cast<const float2*>(denc + 2 * ((int64_t)((c >> 3) & 15) * n + (c >> 7)));
@@ -676,7 +706,7 @@ __global__ __launch_bounds__(256) void k_csr_gather(const uint2* __restrict__ ro
     a1 = dpp_add<0x4E, 0xF>(a1);
     a1 = dpp_add<0x141, 0xF>(a1);
     a1 = dpp_add<0x140, 0xF>(a1);
-    if (sub == 0 && e < entries && r.y > r.x) {
+    if (sub == 0 && valid && r.y > r.x) {
         g_table[2 * e] += a0;
         g_table[2 * e + 1] += a1;
     }
@@ -817,8 +847,16 @@ void bwd_impl(const Launch& L, const NtcDev& nd, const void* table, const void* 
                            (const typename P::S*)enc_in);
         if (L.prof) L.prof->end(L.st);
         if (L.prof) L.prof->begin("ntc_scatter", L.st);
-        hipLaunchKernelGGL(k_csr_gather, dim3(nblk(csr->entries * kGatherLanes, 256)), dim3(256), 0, L.st, csr->rows, csr->pw,
-                           csr->denc, n, csr->entries, g_table);
+        GatherLevels gl;
+        for (int lv = 0; lv < 16; lv++) {
+            gl.begin[lv] = nd.off[lv];
+            gl.end[lv] = lv < 15 ? nd.off[lv + 1] : csr->entries;
+        }
+        int64_t per_xcd = 0;
+        for (int x = 0; x < kXcds; x++)
+            per_xcd = std::max(per_xcd, gather_blocks(gl, x) + gather_blocks(gl, 15 - x));
+        hipLaunchKernelGGL(k_csr_gather, dim3((unsigned)(per_xcd * kXcds)), dim3(256), 0, L.st, gl, csr->rows,
+                           csr->pw, csr->denc, n, g_table);
     } else {
         hipLaunchKernelGGL((k_ntc_bwd<P, false>), dim3(grid), dim3(256), 0, L.st, nd, (const typename P::S*)table,
                            (const typename P::S*)mlp, means, n, d_dmu, d_dq, g_table, g_part, (float*)nullptr,
