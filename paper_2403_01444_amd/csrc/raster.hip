@@ -298,7 +298,7 @@ __global__ __launch_bounds__(256) void k_bin_scan_base(const uint32_t* __restric
 constexpr int kBinGroups = kBinChunk / 64;   // register groups of the covering list
 static_assert(kBinChunk % 64 == 0, "the covering list is held in groups of 64");
 
-template <typename B>
+template <typename B, bool kRec>
 __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __restrict__ order, int64_t n,
                                                   const uint2* __restrict__ srect, const uint32_t* __restrict__ sgoff,
                                                   int tiles_x, int tiles_y, int64_t nchunks,
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __rest
     for (int e = threadIdx.x; e < m; e += kBinThreads) {
         s_id[e] = order[e0 + e];
         s_rect[e] = srect[e0 + e];
-        s_goff[e] = gpos ? sgoff[e0 + e] : 0u;
+        s_goff[e] = kRec ? sgoff[e0 + e] : 0u;
     }
     __syncthreads();
     if (row >= tiles_y) return;
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __rest
             lo[gi] = (int)(r.x & 0xFFFFu);
             hi[gi] = (int)(r.y & 0xFFFFu);   // < tiles_x
             gid[gi] = s_id[e];
-            if (gpos)
+            if (kRec)
                 gk[gi] = s_goff[e] + (uint32_t)(row - (int)(r.x >> 16)) * (uint32_t)(hi[gi] - lo[gi] + 1) -
                          (uint32_t)lo[gi];
             cmin = min(cmin, lo[gi]);
@@ -395,19 +395,17 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const uint32_t* __rest
 #pragma unroll
             for (int gi = 0; gi < kBinGroups; gi++) {
                 if (gi >= ngr) break;
-                const bool c = lo[gi] <= tx && tx <= hi[gi];
-                const uint64_t bal = __builtin_amdgcn_ballot_w64(c);
-                if (c) {
-                    // rank among the covering lanes below this one
-                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                    const uint32_t slot = pos + rank;
-                    if (slot < cap) {
-                        vals[slot] = gid[gi];
-                        if (gpos) {
-                            const uint32_t kk = gk[gi] + (uint32_t)tx;
-                            if (kk < cap) gpos[kk] = slot;
-                        }
+                const uint64_t bal =
+                    __builtin_amdgcn_ballot_w64(lo[gi] <= tx) & __builtin_amdgcn_ballot_w64(tx <= hi[gi]);
+                // rank among the covering lanes below this one
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                const uint32_t slot = pos + rank;
+                if (__builtin_amdgcn_inverse_ballot_w64(bal) && slot < cap) {
+                    vals[slot] = gid[gi];
+                    if (kRec) {
+                        const uint32_t kk = gk[gi] + (uint32_t)tx;
+                        if (kk < cap) gpos[kk] = slot;
                     }
                 }
                 pos += (uint32_t)__popcll(bal);
@@ -1285,8 +1283,12 @@ static void bin_scatter_impl(const Launch& L, const uint32_t* order, int64_t n, 
     const int64_t nchunks = n > 0 ? bin_chunks(n) : 0;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_scatter", L.st);
-    hipLaunchKernelGGL(k_bin_rows<B>, bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, order, n, srect, sgoff,
-                       tiles_x, tiles_y, nchunks, base, (uint32_t)cap, vals, gpos);
+    if (gpos)
+        hipLaunchKernelGGL((k_bin_rows<B, true>), bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, order, n,
+                           srect, sgoff, tiles_x, tiles_y, nchunks, base, (uint32_t)cap, vals, gpos);
+    else
+        hipLaunchKernelGGL((k_bin_rows<B, false>), bin_grid(nchunks, tiles_y), dim3(kBinThreads), 0, L.st, order, n,
+                           srect, sgoff, tiles_x, tiles_y, nchunks, base, (uint32_t)cap, vals, gpos);
     if (L.prof) L.prof->end(L.st);
 }
 
