@@ -636,31 +636,38 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                 const uint32_t box = __float_as_uint(w2.w);
                 float adx2, bdx;
                 blend_dx_terms(fpx - w0.x, w0, adx2, bdx);
+                // lane masks (wave-uniform): okm[k] the lanes whose pixel k
+                // takes the entry, bm[k] those whose exponent lies in the
+                // band where the exact test decides
                 float power[R];
-                bool ok[R], band[R];
-                bool any_band = false;
+                uint64_t okm[R], bm[R];
+                uint64_t any_band = 0ull;
 #pragma unroll
                 for (int k = 0; k < R; k++) {
                     power[k] = blend_power(adx2, bdx, fpy[k] - w0.y, w1.x);
-                    ok[k] = ((box & sel[k]) == sel[k]) & (power[k] <= 0.0f) & (power[k] >= w2.y);
-                    band[k] = ok[k] & (power[k] < w2.z);
-                    any_band = any_band || band[k];
+                    const uint64_t pm = __builtin_amdgcn_ballot_w64((box & sel[k]) == sel[k]) &
+                                        __builtin_amdgcn_ballot_w64(power[k] <= 0.0f) &
+                                        __builtin_amdgcn_ballot_w64(power[k] >= w2.y);
+                    bm[k] = pm & __builtin_amdgcn_ballot_w64(power[k] < w2.z);
+                    okm[k] = pm & ~bm[k];
+                    any_band |= bm[k];
                 }
-                if (__any(any_band)) {
+                if (any_band) {
 #pragma unroll
                     for (int k = 0; k < R; k++)
-                        if (band[k]) ok[k] = blend_exact_test(power[k], w1.y);
+                        okm[k] |= bm[k] & __builtin_amdgcn_ballot_w64(blend_exact_test(power[k], w1.y));
                 }
-                bool any_ok = false;   // no pixel of the wave takes the entry: nothing changes
+                uint64_t any_ok = 0ull;   // no pixel of the wave takes the entry: nothing changes
 #pragma unroll
-                for (int k = 0; k < R; k++) any_ok = any_ok || ok[k];
-                if (!__any(any_ok)) return;
+                for (int k = 0; k < R; k++) any_ok |= okm[k];
+                if (!any_ok) return;
 #pragma unroll
                 for (int k = 0; k < R; k++) {
+                    const bool ok = __builtin_amdgcn_inverse_ballot_w64(okm[k]);
                     const float alpha = fminf(0.99f, w1.y * __expf(power[k]));
                     const float Tn = T[k] * (1.0f - alpha);
-                    const bool stop = ok[k] & (Tn < 1e-4f);
-                    const bool take = ok[k] & !stop;
+                    const bool stop = ok & (Tn < 1e-4f);
+                    const bool take = ok & !stop;
                     const float wgt = take ? alpha * T[k] : 0.0f;
                     c0[k] += wgt * w1.z;
                     c1[k] += wgt * w1.w;
@@ -678,7 +685,7 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_fwd(CamDev cam, int
                 bool active = false;
 #pragma unroll
                 for (int k = 0; k < R; k++) active = active | (fpy[k] == fpy[k]);
-                if (!__any(active)) break;
+                if (!__builtin_amdgcn_ballot_w64(active)) break;
             }
             if (j + 1 == cnt) eval(j);
         }
@@ -832,43 +839,41 @@ __global__ __launch_bounds__(kTile * kTile / R) void k_blend_bwd(CamDev cam, int
             float adx2, bdx;
             blend_dx_terms(dx, w0, adx2, bdx);
             float power[R], dy[R];
-            // dec: the exponent the threshold tests read; inside the band it
-            // is replaced by the exact test's outcome (0: taken, -inf: not),
-            // so that the tests stay compares after the band's branch
-            float dec[R];
-            bool band[R];
-            bool any_band = false;
+            // lane masks (wave-uniform): okm[k] the lanes whose pixel k takes
+            // the entry, bm[k] those whose exponent lies in the band where
+            // the exact test decides
+            uint64_t okm[R], bm[R];
+            uint64_t any_band = 0ull;
 #pragma unroll
             for (int k = 0; k < R; k++) {
                 dy[k] = (float)(py0 + k) - w0.y;
                 power[k] = blend_power(adx2, bdx, dy[k], w1.x);
-                dec[k] = power[k];
-                band[k] = (ej < last[k]) & ((box & sel[k]) == sel[k]) & (power[k] <= 0.0f) &
-                          (power[k] >= w2.y) & (power[k] < w2.z);
-                any_band = any_band || band[k];
+                const uint64_t pm =
+                    __builtin_amdgcn_ballot_w64(ej < last[k]) & __builtin_amdgcn_ballot_w64((box & sel[k]) == sel[k]) &
+                    __builtin_amdgcn_ballot_w64(power[k] <= 0.0f) & __builtin_amdgcn_ballot_w64(power[k] >= w2.y);
+                bm[k] = pm & __builtin_amdgcn_ballot_w64(power[k] < w2.z);
+                okm[k] = pm & ~bm[k];
+                any_band |= bm[k];
             }
-            if (__any(any_band)) {
+            if (any_band) {
 #pragma unroll
                 for (int k = 0; k < R; k++)
-                    if (band[k]) dec[k] = blend_exact_test(power[k], w1.y) ? 0.0f : -INFINITY;
+                    okm[k] |= bm[k] & __builtin_amdgcn_ballot_w64(blend_exact_test(power[k], w1.y));
             }
-            bool ok[R];
-            bool any_ok = false;
 #pragma unroll
-            for (int k = 0; k < R; k++) {
-                ok[k] = (ej < last[k]) & ((box & sel[k]) == sel[k]) & (dec[k] <= 0.0f) & (dec[k] >= w2.y);
-                any_ok = any_ok || ok[k];
-            }
+            for (int k = 0; k < R; k++) act |= okm[k];
             // no pixel of the wave takes the entry: its state and sums stay
-            if (!__any(any_ok)) return false;
+            if (!act) return false;
             // branch-free per-pixel body: selects keep the state of pixels
             // that this Gaussian does not reach
+            bool ok[R];
+#pragma unroll
+            for (int k = 0; k < R; k++) ok[k] = __builtin_amdgcn_inverse_ballot_w64(okm[k]);
 #pragma unroll
             for (int k = 0; k < R; k++) {
                 const float G = __expf(power[k]);
                 const float raw = w1.y * G;
                 const float alpha = fminf(0.99f, raw);
-                act |= __ballot(ok[k]);
                 // T recovery T_i = T_{i+1} / (1 - alpha_i), with the hardware reciprocal (1 ulp)
                 const float Tk = ok[k] ? T[k] * __builtin_amdgcn_rcpf(1.0f - alpha) : T[k];
                 T[k] = Tk;
