@@ -317,7 +317,7 @@ def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
     summary (FETCH_SIZE and WRITE_SIZE, scaled by what the counters read for
     a copy of known size), or None when there is no summary for this
-    workload or the kernel sources changed since it was taken."""
+    workload or kernel, or the kernel sources changed since it was taken."""
     import hashlib
     path = os.path.join(HERE, "profiles", f"stage1_step_{workload}_hbm_traffic.txt")
     if not os.path.exists(path):
@@ -327,15 +327,16 @@ def measured_traffic(kernel, workload):
         if ": " in line and not line.startswith(" "):
             k, v = line.strip().split(": ", 1)
             kv[k] = v
-    if kv.get("kernel") != kernel:
+    row = kv.get(f"traffic {kernel}")
+    if row is None:
         return None
     h = hashlib.sha256()
     for f in ("paper_2403_01444_amd/csrc/raster.hip", "paper_2403_01444_amd/csrc/common.h"):
         h.update(open(os.path.join(HERE, f), "rb").read())
     if h.hexdigest() != kv.get("source_sha256"):
         return None
-    return int((float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_factor"]) +
-                float(kv["write_kib_per_dispatch"]) * float(kv["write_factor"])) * 1024)
+    fetch_kib, write_kib = (float(x) for x in row.split())
+    return int((fetch_kib * float(kv["fetch_factor"]) + write_kib * float(kv["write_factor"])) * 1024)
 
 
 def cpu_baseline(g, cam, target_np, params, cfg):
