@@ -107,9 +107,7 @@ struct Slot {
     uint32_t* chist = nullptr;       // [chunk][tile] pairs
     uint64_t* cmb = nullptr;         // [chunk][tile] first slot in vals[0]
     uint32_t* ttot = nullptr;        // pairs per tile
-    uint32_t* tstart = nullptr;      // first slot of each tile in the tile-major list
     uint32_t* walked = nullptr;
-    uint64_t* tsum = nullptr;
     bool chunked = false;
     bool tile_major_full = false;    // walked holds the whole tile-major list
     int64_t nchunks = 0;
@@ -245,8 +243,7 @@ gs3_status gs3_create(const gs3_config* cfg, gs3_ctx** out) {
             ok = c->alloc(&s.vals[1], PK) && c->alloc(&s.pkeys[0], PK) && c->alloc(&s.pkeys[1], PK);
         if (ok && cfg->sort_mode == GS3_SORT_DEPTH_FIRST && cfg->grad_record_log2 <= 0)
             ok = c->alloc(&s.chist, (int64_t)c->max_tiles * nchunks) && c->alloc(&s.cmb, (int64_t)c->max_tiles * nchunks) &&
-                 c->alloc(&s.ttot, c->max_tiles) && c->alloc(&s.tstart, c->max_tiles) && c->alloc(&s.walked, PK) &&
-                 c->alloc(&s.tsum, 1);
+                 c->alloc(&s.ttot, c->max_tiles) && c->alloc(&s.walked, PK);
     }
     const int64_t sort_items = cfg->sort_mode == GS3_SORT_RADIX64 ? std::max(N, PK) : N;
     const int64_t hist_words = radix_hist_words(sort_items);
@@ -693,17 +690,15 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
     if (c->cfg.sort_mode == GS3_SORT_DEPTH_FIRST) {
         sl.cur = 0;
         if (n > 0) {
-            if (hipMemcpyAsync(c->dkeys[0], sl.key, (size_t)n * 4, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
-                return c->fail(GS3_EHIP, "render: copying the depth keys failed");
-            iota_u32(L, c->dvals[0], n);
-            const int r = radix_sort_u32(L, c->dkeys, c->dvals, n, 32, c->radix_hist, c->scan_tmp);
+            const int r = radix_order_u32(L, sl.key, c->dkeys, c->dvals, n, 32, c->radix_hist, c->scan_tmp);
             const uint32_t* order = c->dvals[r];
             const int64_t nchunks = bin_chunks(n);
             const bool rec_mode = c->grec_cap > 0;
             // first pair slot of each Gaussian: only the record mode's
             // gradient gather needs it
             if (rec_mode) scan_u32_to_u64(L, sl.count, n, sl.goff, c->goff_total, c->scan_tmp);
-            bin_gather(L, order, n, sl.rect, sl.count, sl.goff, cap, c->bin_rect, rec_mode ? c->bin_goff : nullptr);
+            bin_gather(L, order, n, sl.rect, sl.count, sl.goff, cap, c->bin_rect, rec_mode ? c->bin_goff : nullptr,
+                       rec_mode ? nullptr : sl.ttot, rec_mode ? 0 : (int64_t)ntiles);
             if (rec_mode) {
                 // tile-major list (the record gather needs every pair's slot)
                 bin_count(L, order, n, c->bin_rect, cd.tiles_x, cd.tiles_y, c->bin_hist, nullptr);
@@ -719,9 +714,7 @@ gs3_status gs3_render(gs3_ctx* c, int32_t slot, const gs3_gaussians* g, const fl
                 // slots; the forward walks each tile's segments
                 bin_count(L, order, n, c->bin_rect, cd.tiles_x, cd.tiles_y, sl.chist, sl.ttot);
                 scan_u32_to_u64(L, sl.chist, (int64_t)ntiles * nchunks, sl.cmb, sl.total, c->scan_tmp);
-                scan_u32_to_u32(L, sl.ttot, ntiles, sl.tstart, sl.tsum, c->scan_tmp);
-                ranges_from_starts(L, sl.tstart, sl.ttot, ntiles, cap, sl.ranges);
-                pairs_total_check(L, sl.total, cap, c->flags);
+                tile_ranges_from_counts(L, sl.ttot, ntiles, cap, sl.total, sl.ranges, c->flags);
                 bin_scatter_chunked(L, order, n, c->bin_rect, cd.tiles_x, cd.tiles_y, sl.cmb, cap, sl.vals[0]);
             }
             sl.chunked = !rec_mode;

@@ -35,6 +35,10 @@ int radix_sort_u32(const Launch& L, uint32_t* keys[2], uint32_t* vals[2], int64_
                    uint64_t* tmp);
 int radix_sort_u64(const Launch& L, uint64_t* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist,
                    uint64_t* tmp);
+// The same sort of keys_in (left unchanged) with the positions 0..n-1 as
+// values: the order that sorts keys_in, without copying the keys first.
+int radix_order_u32(const Launch& L, const uint32_t* keys_in, uint32_t* keys[2], uint32_t* vals[2], int64_t n,
+                    int bits, uint32_t* hist, uint64_t* tmp);
 
 void morton_codes(const Launch& L, const float* means, int64_t n, const float lo[3], const float inv[3],
                   uint32_t* code, uint32_t* idx);
@@ -64,17 +68,20 @@ constexpr int kMaxTilesX = 256;   // widest image: 4096 pixels
 // a multiple of 8 (the passes give each XCD an eighth; padding chunks are empty)
 int64_t bin_chunks(int64_t n);
 // tile rectangles (empty for culled Gaussians) and, when sgoff is set, the
-// first pair slots goff, gathered into depth order
+// first pair slots goff, gathered into depth order; also zeroes zero[0,
+// nzero) (the per-tile totals bin_count adds to; null with nzero 0)
 void bin_gather(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
-                const uint64_t* goff, uint64_t cap, uint2* srect, uint32_t* sgoff);
+                const uint64_t* goff, uint64_t cap, uint2* srect, uint32_t* sgoff, uint32_t* zero, int64_t nzero);
 // Pairs per (chunk, tile), chunk-major: hist[chunk * ntiles + tile] with
 // ntiles = tiles_x * tiles_y, so each pass writes and reads a tile row of one
-// chunk as consecutive words; ttot (optional) receives the pairs per tile.
+// chunk as consecutive words; ttot (optional, zeroed by the caller) receives
+// the pairs per tile.
 void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* srect, int tiles_x, int tiles_y,
                uint32_t* hist, uint32_t* ttot);
-// ranges[t] = [start[t], start[t] + len[t]) clamped to cap
-void ranges_from_starts(const Launch& L, const uint32_t* start, const uint32_t* len, int ntiles, uint64_t cap,
-                        uint2* ranges);
+// ranges[t] = [start, start + len[t]) clamped to cap, start the exclusive
+// prefix of len; sets *overflow when *total (the list's length) exceeds cap
+void tile_ranges_from_counts(const Launch& L, const uint32_t* len, int64_t ntiles, uint64_t cap, const uint64_t* total,
+                             uint2* ranges, int* overflow);
 // First slot of every (tile, chunk) segment in the tile-major pair list:
 // base[chunk * ntiles + tile] = (pairs of earlier tiles) + (pairs of the
 // tile in earlier chunks), clamped to cap; the grand total goes to *total.
@@ -112,7 +119,6 @@ void gpos_from_pairs(const Launch& L, const uint64_t* keys, const uint32_t* vals
                      const uint64_t* goff, int tiles_x, uint64_t cap, uint32_t* gpos);
 void ranges_from_hist(const Launch& L, const uint32_t* base, const uint64_t* total, int ntiles, uint64_t cap,
                       uint2* ranges, int* overflow);
-void pairs_total_check(const Launch& L, const uint64_t* total, uint64_t cap, int* overflow);
 
 // Per-pair gradient records of the backward blend: walked entries of tile t
 // (list positions [start_t, start_t + tile_walk[t])) get compact indices

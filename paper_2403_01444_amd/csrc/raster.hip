@@ -140,8 +140,10 @@ __device__ __forceinline__ void bin_block(int64_t nchunks, int& rowblock, int64_
 __global__ __launch_bounds__(256) void k_bin_gather(const uint32_t* __restrict__ order, int64_t n,
                                                     const uint2* __restrict__ rect, const uint32_t* __restrict__ count,
                                                     const uint64_t* __restrict__ goff, uint32_t cap,
-                                                    uint2* __restrict__ srect, uint32_t* __restrict__ sgoff) {
+                                                    uint2* __restrict__ srect, uint32_t* __restrict__ sgoff,
+                                                    uint32_t* __restrict__ zero, int64_t nzero) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < nzero) zero[e] = 0u;
     if (e >= n) return;
     const uint32_t id = order[e];
     srect[e] = count[id] ? rect[id] : make_uint2(0xFFFF0000u, 0u);   // empty: no row spans
@@ -223,15 +225,6 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const uint2* __restri
 
 // Start slots of the tiles in the tile-major list: ranges[t] = [s, s + len)
 // from the exclusive scan of the tile totals, clamped to cap.
-__global__ __launch_bounds__(256) void k_ranges_from_starts(const uint32_t* __restrict__ start,
-                                                            const uint32_t* __restrict__ len, int ntiles,
-                                                            uint64_t cap, uint2* __restrict__ ranges) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= ntiles) return;
-    const uint64_t s = start[t], e = s + len[t];
-    ranges[t] = make_uint2((uint32_t)(s < cap ? s : cap), (uint32_t)(e < cap ? e : cap));
-}
-
 // Tile-major exclusive prefix of the chunk-major counts.  A thread owns one
 // tile and a segment of kBinScanSeg chunks, so every load and store of a
 // warp-wide step touches consecutive tiles of one chunk: (1) segment sums,
@@ -425,10 +418,6 @@ __global__ __launch_bounds__(256) void k_ranges_from_hist(const uint32_t* __rest
     const uint32_t s = base[t];
     const uint32_t e = t + 1 < ntiles ? base[t + 1] : (uint32_t)(K < cap ? K : cap);
     ranges[t] = make_uint2(s, e);
-}
-
-__global__ void k_total_check(const uint64_t* total, uint64_t cap, int* overflow) {
-    if (threadIdx.x == 0 && *total > cap) atomicOr(overflow, 1);
 }
 
 // XCD-aware tile order: consecutive workgroups are dealt round-robin to the
@@ -1227,11 +1216,11 @@ void ranges_from_keys(const Launch& L, const uint64_t* keys, int64_t K, int ntil
 }
 
 void bin_gather(const Launch& L, const uint32_t* order, int64_t n, const uint2* rect, const uint32_t* count,
-                const uint64_t* goff, uint64_t cap, uint2* srect, uint32_t* sgoff) {
+                const uint64_t* goff, uint64_t cap, uint2* srect, uint32_t* sgoff, uint32_t* zero, int64_t nzero) {
     if (n <= 0) return;
     if (L.prof) L.prof->begin("bin_gather", L.st);
-    hipLaunchKernelGGL(k_bin_gather, dim3(blocks_for(n, 256)), dim3(256), 0, L.st, order, n, rect, count, goff,
-                       (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull), srect, sgoff);
+    hipLaunchKernelGGL(k_bin_gather, dim3(blocks_for(std::max(n, nzero), 256)), dim3(256), 0, L.st, order, n, rect,
+                       count, goff, (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull), srect, sgoff, zero, nzero);
     if (L.prof) L.prof->end(L.st);
 }
 
@@ -1246,20 +1235,12 @@ void bin_count(const Launch& L, const uint32_t* order, int64_t n, const uint2* s
     const int64_t nchunks = n > 0 ? bin_chunks(n) : 0;
     if (nchunks == 0) return;
     if (L.prof) L.prof->begin("bin_count", L.st);
-    if (ttot) fill_u32(L, ttot, 0u, (int64_t)tiles_x * tiles_y);
     const unsigned grid = (unsigned)((nchunks / kCountGroup) * ((tiles_y + kBinRowsPerBlock - 1) / kBinRowsPerBlock));
     hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(kBinThreads), 0, L.st, srect, n, tiles_x, tiles_y, nchunks, hist,
                        ttot);
     if (L.prof) L.prof->end(L.st);
 }
 
-void ranges_from_starts(const Launch& L, const uint32_t* start, const uint32_t* len, int ntiles, uint64_t cap,
-                        uint2* ranges) {
-    if (L.prof) L.prof->begin("tile_ranges", L.st);
-    hipLaunchKernelGGL(k_ranges_from_starts, dim3(blocks_for(ntiles, 256)), dim3(256), 0, L.st, start, len, ntiles,
-                       cap, ranges);
-    if (L.prof) L.prof->end(L.st);
-}
 
 int64_t bin_scan_part_words(int64_t nchunks, int ntiles) {
     return ((nchunks + kBinScanSeg - 1) / kBinScanSeg) * (int64_t)ntiles;
@@ -1344,9 +1325,6 @@ void ranges_from_hist(const Launch& L, const uint32_t* base, const uint64_t* tot
     if (L.prof) L.prof->end(L.st);
 }
 
-void pairs_total_check(const Launch& L, const uint64_t* total, uint64_t cap, int* overflow) {
-    hipLaunchKernelGGL(k_total_check, dim3(1), dim3(64), 0, L.st, total, cap, overflow);
-}
 
 static unsigned blend_grid(int ntiles) { return (unsigned)(((ntiles + 7) / 8) * 8); }
 

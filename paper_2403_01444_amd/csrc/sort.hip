@@ -167,6 +167,44 @@ __global__ __launch_bounds__(kThreads) void k_scan_single(const uint32_t* __rest
     if (threadIdx.x == 0) *total = carry;
 }
 
+// Tile ranges of the chunk-major pair list from the pairs per tile: one
+// block walks the counts with a running carry (as k_scan_single) and writes
+// ranges[t] = [start, start + len[t]) clamped to cap; the first thread also
+// flags an overflow when the list's total exceeds cap.
+__global__ __launch_bounds__(kThreads) void k_scan_ranges(const uint32_t* __restrict__ len, int64_t n, uint64_t cap,
+                                                          const uint64_t* __restrict__ total,
+                                                          uint2* __restrict__ ranges, int* __restrict__ overflow) {
+    __shared__ uint64_t s_w[kThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0 && *total > cap) atomicOr(overflow, 1);
+    uint64_t carry = 0;
+    for (int64_t b0 = 0; b0 < n; b0 += kTileItems) {
+        const int64_t base = b0 + (int64_t)threadIdx.x * kItems;
+        uint32_t v[kItems];
+        load8(len, base, n, v);
+        uint64_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; k++) s += (uint64_t)v[k];
+        const uint64_t x = wave_incl_scan(s, lane);
+        if (lane == 63) s_w[w] = x;
+        __syncthreads();
+        uint64_t pre = carry, tot = 0;
+        for (int k = 0; k < kThreads / 64; k++) {
+            if (k < w) pre += s_w[k];
+            tot += s_w[k];
+        }
+        uint64_t run = pre + x - s;
+#pragma unroll
+        for (int k = 0; k < kItems; k++) {
+            const uint64_t e = run + v[k];
+            if (base + k < n) ranges[base + k] = make_uint2((uint32_t)(run < cap ? run : cap), (uint32_t)(e < cap ? e : cap));
+            run = e;
+        }
+        carry += tot;
+        __syncthreads();
+    }
+}
+
 template <typename Tout>
 void scan_impl(const Launch& L, const uint32_t* in, int64_t n, Tout* out, uint64_t* total, uint64_t* tmp) {
     int64_t nb = (n + kTileItems - 1) / kTileItems;
@@ -247,7 +285,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict_
         const int64_t idx = base + r * 64 + lane;
         const bool valid = idx < n;
         key[r] = valid ? kin[idx] : (K)0;
-        val[r] = valid ? vin[idx] : 0u;
+        val[r] = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;   // no values: the input positions
         const uint32_t d = (uint32_t)(key[r] >> shift) & 0xFFu;
         dig[r] = d;
         const uint64_t peers = match_digit(d) & __ballot(valid);
@@ -298,15 +336,20 @@ __global__ __launch_bounds__(64) void k_radix_digit_scan(uint32_t* __restrict__ 
 // blocks per pass up to which the per-digit scan is used
 constexpr int64_t kDigitScanBlocks = 4096;
 
+// first: the keys the first pass reads (left unchanged; its output goes to
+// keys[1] as usual), or null to start from keys[0].  iota: the first pass
+// takes the input positions as values instead of reading vals[0].
 template <typename K, int I>
-int radix_passes(const Launch& L, K* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist, uint64_t* tmp) {
+int radix_passes(const Launch& L, const K* first, bool iota, K* keys[2], uint32_t* vals[2], int64_t n, int bits,
+                 uint32_t* hist, uint64_t* tmp) {
     int cur = 0;
     const int64_t nb = (n + kThreads * I - 1) / (kThreads * I);
     const int64_t hn = nb * 256;
     for (int shift = 0; shift < bits; shift += 8) {
         if (L.prof) L.prof->begin("radix_pass", L.st);
-        hipLaunchKernelGGL((k_radix_hist<K, I>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, keys[cur], n, shift,
-                           hist, nb);
+        const K* kin = shift == 0 && first ? first : keys[cur];
+        const uint32_t* vin = shift == 0 && iota ? nullptr : vals[cur];
+        hipLaunchKernelGGL((k_radix_hist<K, I>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, kin, n, shift, hist, nb);
         Launch inner{L.st, nullptr};
         uint32_t* dtotal = nullptr;
         if (nb <= kDigitScanBlocks) {
@@ -315,8 +358,8 @@ int radix_passes(const Launch& L, K* keys[2], uint32_t* vals[2], int64_t n, int 
         } else {
             scan_impl<uint32_t>(inner, hist, hn, hist, (uint64_t*)(tmp), tmp + 1);
         }
-        hipLaunchKernelGGL((k_radix_scatter<K, I>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, keys[cur],
-                           vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, nb, dtotal);
+        hipLaunchKernelGGL((k_radix_scatter<K, I>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, kin, vin,
+                           keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, nb, dtotal);
         if (L.prof) L.prof->end(L.st);
         cur ^= 1;
     }
@@ -327,10 +370,16 @@ int radix_passes(const Launch& L, K* keys[2], uint32_t* vals[2], int64_t n, int 
 constexpr int64_t kSmallSort = (int64_t)1 << 21;
 
 template <typename K>
-int radix_impl(const Launch& L, K* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist, uint64_t* tmp) {
-    if (n <= 1) return 0;
-    if (n < kSmallSort) return radix_passes<K, 4>(L, keys, vals, n, bits, hist, tmp);
-    return radix_passes<K, 8>(L, keys, vals, n, bits, hist, tmp);
+int radix_impl(const Launch& L, const K* first, bool iota, K* keys[2], uint32_t* vals[2], int64_t n, int bits,
+               uint32_t* hist, uint64_t* tmp) {
+    if (n <= 1 || bits <= 0) {
+        // nothing to order: the result is the input, in buffer 0
+        if (n > 0 && first) (void)hipMemcpyAsync(keys[0], first, (size_t)n * sizeof(K), hipMemcpyDeviceToDevice, L.st);
+        if (iota) iota_u32(L, vals[0], n);
+        return 0;
+    }
+    if (n < kSmallSort) return radix_passes<K, 4>(L, first, iota, keys, vals, n, bits, hist, tmp);
+    return radix_passes<K, 8>(L, first, iota, keys, vals, n, bits, hist, tmp);
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
@@ -407,6 +456,13 @@ void scan_u32_to_u64(const Launch& L, const uint32_t* in, int64_t n, uint64_t* o
     scan_impl<uint64_t>(L, in, n, out, total, tmp);
 }
 
+void tile_ranges_from_counts(const Launch& L, const uint32_t* len, int64_t ntiles, uint64_t cap, const uint64_t* total,
+                             uint2* ranges, int* overflow) {
+    if (L.prof) L.prof->begin("tile_ranges", L.st);
+    hipLaunchKernelGGL(k_scan_ranges, dim3(1), dim3(kThreads), 0, L.st, len, ntiles, cap, total, ranges, overflow);
+    if (L.prof) L.prof->end(L.st);
+}
+
 void scan_u32_to_u32(const Launch& L, const uint32_t* in, int64_t n, uint32_t* out, uint64_t* total, uint64_t* tmp) {
     scan_impl<uint32_t>(L, in, n, out, total, tmp);
 }
@@ -417,12 +473,17 @@ int64_t radix_hist_words(int64_t n) { return ((n + kThreads * 4 - 1) / (kThreads
 
 int radix_sort_u32(const Launch& L, uint32_t* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist,
                    uint64_t* tmp) {
-    return radix_impl<uint32_t>(L, keys, vals, n, bits, hist, tmp);
+    return radix_impl<uint32_t>(L, nullptr, false, keys, vals, n, bits, hist, tmp);
+}
+
+int radix_order_u32(const Launch& L, const uint32_t* keys_in, uint32_t* keys[2], uint32_t* vals[2], int64_t n,
+                    int bits, uint32_t* hist, uint64_t* tmp) {
+    return radix_impl<uint32_t>(L, keys_in, true, keys, vals, n, bits, hist, tmp);
 }
 
 int radix_sort_u64(const Launch& L, uint64_t* keys[2], uint32_t* vals[2], int64_t n, int bits, uint32_t* hist,
                    uint64_t* tmp) {
-    return radix_impl<uint64_t>(L, keys, vals, n, bits, hist, tmp);
+    return radix_impl<uint64_t>(L, nullptr, false, keys, vals, n, bits, hist, tmp);
 }
 
 void fill_u32(const Launch& L, uint32_t* p, uint32_t v, int64_t n) {
