@@ -380,19 +380,44 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
         dlev[1] = reinterpret_cast<float2*>(denc) + (int64_t)(8 + 2 * g) * n;
     }
     const int64_t nb = (n + kPts - 1) / kPts;
+    // the inputs of this wave's batch are loaded one round ahead, so that
+    // their latency overlaps the previous round's work
+    float nmu[3] = {0.f, 0.f, 0.f}, ndv[4] = {0.f, 0.f, 0.f, 0.f};
+    S nenc[8];
+    auto prefetch = [&](int64_t bb) {
+        const int64_t q = (bb + w) * kPts + p;
+        if (bb < nb && q < n) {
+            nmu[0] = means[3 * q];
+            nmu[1] = means[3 * q + 1];
+            nmu[2] = means[3 * q + 2];
+            if (enc_in) {
+#pragma unroll
+                for (int j = 0; j < 8; j++) nenc[j] = enc_in[q * 32 + 8 * g + j];
+            }
+            if (g == 0) {
+                ndv[0] = d_dmu[3 * q];
+                ndv[1] = d_dmu[3 * q + 1];
+                ndv[2] = d_dmu[3 * q + 2];
+                ndv[3] = d_dq[4 * q];
+            } else if (g == 1) {
+                ndv[0] = d_dq[4 * q + 1];
+                ndv[1] = d_dq[4 * q + 2];
+                ndv[2] = d_dq[4 * q + 3];
+            }
+        }
+    };
+    prefetch((int64_t)blockIdx.x * kWaves);
     for (int64_t b0 = (int64_t)blockIdx.x * kWaves; b0 < nb; b0 += (int64_t)gridDim.x * kWaves) {
         // ---------------- phase A: this wave's batch ----------------
         const int64_t pt = (b0 + w) * kPts + p;
         const bool valid = pt < n;   // false for every lane of a wave past the last batch
         float x[3] = {0.f, 0.f, 0.f};
         bool in = false;
-        if (valid) {
-            const float mu[3] = {means[3 * pt], means[3 * pt + 1], means[3 * pt + 2]};
-            in = ntc_normalise(nd, mu, x);
-        }
+        if (valid) in = ntc_normalise(nd, nmu, x);
         // 1. encoding: the forward's, when it kept it, else recomputed
         if (enc_in && valid) {
-            enc_from_cache<P>(X, p, g, enc_in, pt);
+#pragma unroll
+            for (int j = 0; j < 8; j++) X[p * LD32 + 8 * g + j] = nenc[j];
         } else if (in) {
             encode_lane<P>(nd, table, x, g, X, p);
         } else {
@@ -400,16 +425,11 @@ __global__ __launch_bounds__(256) void k_ntc_bwd(NtcDev nd, const typename P::S*
         }
         // output gradient (lanes of group 0 own the 7 outputs of their point)
         float dv[4] = {0.f, 0.f, 0.f, 0.f};
-        if (in && g == 0) {
-            dv[0] = d_dmu[3 * pt];
-            dv[1] = d_dmu[3 * pt + 1];
-            dv[2] = d_dmu[3 * pt + 2];
-            dv[3] = d_dq[4 * pt];
-        } else if (in && g == 1) {
-            dv[0] = d_dq[4 * pt + 1];
-            dv[1] = d_dq[4 * pt + 2];
-            dv[2] = d_dq[4 * pt + 3];
+        if (in && g <= 1) {
+#pragma unroll
+            for (int r = 0; r < 4; r++) dv[r] = ndv[r];
         }
+        prefetch(b0 + (int64_t)gridDim.x * kWaves);
         // the activation gradients of this batch are held scaled by 2^k0,
         // 2^k1, 2^k2 (exact powers of two; the weight gradients unscale them)
         int k0 = 0;
