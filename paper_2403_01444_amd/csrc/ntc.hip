@@ -258,15 +258,24 @@ __global__ __launch_bounds__(256) void k_ntc_fwd(NtcDev nd, const typename P::S*
     S* H1 = sH1[w];
     S* H2 = sH2[w];
     const int64_t nb = (n + kPts - 1) / kPts;
+    // each batch's means are loaded one round ahead
+    float nmu[3] = {0.f, 0.f, 0.f};
+    auto prefetch = [&](int64_t bb) {
+        const int64_t q = (bb + w) * kPts + p;
+        if (bb < nb && q < n) {
+            nmu[0] = means[3 * q];
+            nmu[1] = means[3 * q + 1];
+            nmu[2] = means[3 * q + 2];
+        }
+    };
+    prefetch((int64_t)blockIdx.x * kWaves);
     for (int64_t b0 = (int64_t)blockIdx.x * kWaves; b0 < nb; b0 += (int64_t)gridDim.x * kWaves) {
         const int64_t pt = (b0 + w) * kPts + p;
         const bool valid = pt < n;
         float x[3] = {0.f, 0.f, 0.f};
         bool in = false;
-        if (valid) {
-            const float mu[3] = {means[3 * pt], means[3 * pt + 1], means[3 * pt + 2]};
-            in = ntc_normalise(nd, mu, x);
-        }
+        if (valid) in = ntc_normalise(nd, nmu, x);
+        prefetch(b0 + (int64_t)gridDim.x * kWaves);
         wave_sync();   // previous batch's reads of X done
         if (in) {
             encode_lane<P>(nd, table, x, g, X, p);
