@@ -29,6 +29,8 @@ constexpr int kHW = kTW + 2 * kR;    // halo tile width (42)
 constexpr int kHH = kTH + 2 * kR;    // halo tile height (42)
 constexpr int kQ = 4;                // outputs per thread in each filter pass
 constexpr int kIn = kQ + 2 * kR;     // inputs per thread in each filter pass (14)
+constexpr int kQR = 8;               // outputs per task of the row filters: 42 x 4 tasks, one round of 256 threads
+constexpr int kInR = kQR + 2 * kR;   // their inputs (18)
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
 
@@ -109,20 +111,21 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ x, const f
 }
 
 // Row filter: for the tasks t = threadIdx.x, threadIdx.x + 256, ... of the
-// 42 x 8 (halo row r, column quad q) tasks, outputs at columns 4 q .. 4 q + 3
-// of the NM maps src[m] -> dst[m].
+// 42 x 4 (halo row r, column octet q) tasks, outputs at columns 8 q .. 8 q + 7
+// of the NM maps src[m] -> dst[m] (one round of tasks: 168 of the 256
+// threads, each reading 18 inputs per map).
 template <int NM>
 __device__ __forceinline__ void row_filter(const Win& win, const float (*src)[kHH][kHW + 1],
                                            float (*dst)[kHH][kTW + 1]) {
-    for (int t = threadIdx.x; t < kHH * (kTW / kQ); t += 256) {
-        const int r = t / (kTW / kQ), c0 = (t % (kTW / kQ)) * kQ;
+    for (int t = threadIdx.x; t < kHH * (kTW / kQR); t += 256) {
+        const int r = t / (kTW / kQR), c0 = (t % (kTW / kQR)) * kQR;
 #pragma unroll
         for (int m = 0; m < NM; m++) {
-            float u[kIn];
+            float u[kInR];
 #pragma unroll
-            for (int i = 0; i < kIn; i++) u[i] = src[m][r][c0 + i];
+            for (int i = 0; i < kInR; i++) u[i] = src[m][r][c0 + i];
 #pragma unroll
-            for (int o = 0; o < kQ; o++) {
+            for (int o = 0; o < kQR; o++) {
                 float a = 0.f;
 #pragma unroll
                 for (int j = 0; j < 11; j++) a += win.g[j] * u[o + j];
@@ -136,16 +139,16 @@ __device__ __forceinline__ void row_filter(const Win& win, const float (*src)[kH
 // src[1] = y (same task layout as row_filter).
 __device__ __forceinline__ void row_filter_second(const Win& win, const float (*src)[kHH][kHW + 1],
                                                   float (*dst)[kHH][kTW + 1]) {
-    for (int t = threadIdx.x; t < kHH * (kTW / kQ); t += 256) {
-        const int r = t / (kTW / kQ), c0 = (t % (kTW / kQ)) * kQ;
-        float u[kIn], v[kIn];
+    for (int t = threadIdx.x; t < kHH * (kTW / kQR); t += 256) {
+        const int r = t / (kTW / kQR), c0 = (t % (kTW / kQR)) * kQR;
+        float u[kInR], v[kInR];
 #pragma unroll
-        for (int i = 0; i < kIn; i++) {
+        for (int i = 0; i < kInR; i++) {
             u[i] = src[0][r][c0 + i];
             v[i] = src[1][r][c0 + i];
         }
 #pragma unroll
-        for (int o = 0; o < kQ; o++) {
+        for (int o = 0; o < kQR; o++) {
             float a2 = 0.f, a3 = 0.f, a4 = 0.f;
 #pragma unroll
             for (int j = 0; j < 11; j++) {
