@@ -13,10 +13,11 @@ the seeded view order of reading C10.
   either way on a rounding-sized difference; those are reported, not
   compared.
 * The held-out PSNR every 10 iterations of a 150-iteration run: within
-  0.1 dB of the oracle's curve plus the largest spread, at or before that
-  iteration, of the oracle's curve and eight copies of its loop perturbed
-  by float32-sized relative noise (1e-6 on the image and gradient of every
-  iteration; tests/parity.py: curve_bars), all in
+  0.1 dB of the oracle's curve plus 1.5 times the largest spread, at or
+  before that iteration, of the oracle's curve and eight copies of its loop
+  perturbed by float32-sized relative noise (1e-6 on the image and gradient
+  of every iteration; the factor covers the GPU run as one more member of
+  that family; tests/parity.py: curve_bars), all in
   tests/golden/stage1_ring-50k-256px.json, written by the script beside it
   from the oracle alone.  The first 50 iterations are conditioned (spread
   a few hundredths of a dB); later the loop overfits its four views and

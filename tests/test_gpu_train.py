@@ -24,8 +24,8 @@ def test_direct_adam_small_scene_tracks_oracle_loop():
       the step within 1e-3 x lr wherever the oracle's Adam step is
       determined to 0.5e-3 x lr by its gradient to that precision.
     * The PSNR of the view every 10 iterations of a 50-iteration run within
-      0.1 dB of the oracle's curve plus the largest spread so far of the
-      oracle's curve and sixteen copies of its loop perturbed by
+      0.1 dB of the oracle's curve plus 1.5 times the largest spread so far
+      of the oracle's curve and sixteen copies of its loop perturbed by
       float32-sized relative noise
       (1e-6 on the image and gradients of every iteration): the curve is
       conditioned to a few thousandths of a dB for 20 iterations; by 50, as
