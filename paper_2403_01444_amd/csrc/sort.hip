@@ -1,10 +1,12 @@
 // Prefix sums and a stable LSD radix sort for gfx950 (wave64).
 //
-// Scan: three kernels (per-block reduce, single-block scan of the block
-// sums, per-block rescan with the block prefix).  Each block owns 2048
-// consecutive items (256 threads x 8).  Up to eight blocks' worth of items
-// (the per-tile totals of a view, for instance) take one kernel: a single
-// block walks them 2048 at a time with a running carry.
+// Scan: per-block reduce, then a per-block rescan with the block prefix;
+// each block of the rescan adds up the sums of the blocks before it (up to
+// 2048 blocks; above that a single-block scan of the block sums runs in
+// between).  Each block owns 2048 consecutive items (256 threads x 8).  Up
+// to eight blocks' worth of items (the per-tile totals of a view, for
+// instance) take one kernel: a single block walks them 2048 at a time with
+// a running carry.
 //
 // Radix sort: 8-bit digits, one histogram kernel and one scatter kernel per
 // pass.  A block owns 256 x I consecutive items (I = 8, or 4 for inputs
@@ -90,21 +92,46 @@ __global__ __launch_bounds__(kThreads) void k_scan_bsums(uint64_t* __restrict__ 
     if (threadIdx.x == 0) *total = carry;
 }
 
-template <typename Tin, typename Tout>
+// bpre: the exclusive prefix of the block sums (k_scan_bsums), or, with
+// kSelf, the raw block sums (k_scan_reduce): the block then adds up those of
+// the blocks before it itself (nb of them at most kSelfPrefixBlocks) and the
+// last block writes the total, one launch fewer than k_scan_bsums.
+constexpr int64_t kSelfPrefixBlocks = 2048;
+
+template <typename Tin, typename Tout, bool kSelf>
 __global__ __launch_bounds__(kThreads) void k_scan_down(const Tin* __restrict__ in, int64_t n,
-                                                        const uint64_t* __restrict__ bpre, Tout* __restrict__ out) {
+                                                        const uint64_t* __restrict__ bpre, Tout* __restrict__ out,
+                                                        uint64_t* __restrict__ total) {
     __shared__ uint64_t s_w[kThreads / 64];
+    __shared__ uint64_t s_p[kThreads / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
     uint32_t v[kItems];
     load8(in, base, n, v);
+    uint64_t bp = 0;
+    if (kSelf) {
+        for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kThreads) bp += bpre[b];
+        for (int off = 32; off > 0; off >>= 1) bp += __shfl_xor(bp, off, 64);
+        if (lane == 0) s_p[w] = bp;
+    }
     uint64_t s = 0;
 #pragma unroll
     for (int k = 0; k < kItems; k++) s += (uint64_t)v[k];
     uint64_t x = wave_incl_scan(s, lane);
     if (lane == 63) s_w[w] = x;
     __syncthreads();
-    uint64_t pre = bpre[blockIdx.x];
+    uint64_t pre;
+    if (kSelf) {
+        pre = 0;
+        for (int k = 0; k < kThreads / 64; k++) pre += s_p[k];
+        if (threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) {
+            uint64_t t = pre;
+            for (int k = 0; k < kThreads / 64; k++) t += s_w[k];
+            *total = t;
+        }
+    } else {
+        pre = bpre[blockIdx.x];
+    }
     for (int k = 0; k < w; k++) pre += s_w[k];
     uint64_t run = pre + x - s;
     Tout o[kItems];
@@ -219,8 +246,14 @@ void scan_impl(const Launch& L, const uint32_t* in, int64_t n, Tout* out, uint64
         return;
     }
     hipLaunchKernelGGL((k_scan_reduce<uint32_t>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, in, n, tmp);
-    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kThreads), 0, L.st, tmp, nb, total);
-    hipLaunchKernelGGL((k_scan_down<uint32_t, Tout>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, in, n, tmp, out);
+    if (nb <= kSelfPrefixBlocks) {
+        hipLaunchKernelGGL((k_scan_down<uint32_t, Tout, true>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, in, n,
+                           tmp, out, total);
+    } else {
+        hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kThreads), 0, L.st, tmp, nb, total);
+        hipLaunchKernelGGL((k_scan_down<uint32_t, Tout, false>), dim3((unsigned)nb), dim3(kThreads), 0, L.st, in, n,
+                           tmp, out, total);
+    }
     if (L.prof) L.prof->end(L.st);
 }
 
